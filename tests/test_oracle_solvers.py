@@ -1,0 +1,93 @@
+"""Pins of the oracle's Krylov solvers and reference solves (no GPU)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import assembly, krylov, pfc, precond, reference, solve
+
+
+def _prob(dim, N, jitter=0.1, psibar=-0.3, amp=0.05, seed=3):
+    mesh = wl.make_mesh(dim, N, jitter=jitter, seed=seed)
+    M, K = assembly.mass_stiffness(mesh)
+    psi = wl.psi0(mesh.n, psibar, amp, seed=seed)
+    return mesh, M, K, psi
+
+
+def test_pcg_against_direct_and_tolerance():
+    mesh, M, K, _ = _prob(2, 8)
+    C = (M + 0.7 * K).tocsr()
+    rng = np.random.default_rng(0)
+    b = rng.normal(size=mesh.n)
+    x, it = krylov.pcg(lambda v: C @ v, b, 1.0 / C.diagonal(), tol=1e-3)
+    assert np.linalg.norm(b - C @ x) <= 1e-3 * np.linalg.norm(b)
+    assert it > 0
+    x2, it2 = krylov.pcg(lambda v: C @ v, b, 1.0 / C.diagonal(), tol=1e-13, maxit=1000)
+    xd = reference.dense_solve(C, b)
+    assert np.linalg.norm(x2 - xd) <= 1e-11 * np.linalg.norm(xd)
+    # fixed count replays the same iterate
+    x3, it3 = krylov.pcg(lambda v: C @ v, b, 1.0 / C.diagonal(), fixed=it)
+    assert it3 == it and np.array_equal(x3, x)
+    # zero rhs
+    x0, i0 = krylov.pcg(lambda v: C @ v, np.zeros(mesh.n), 1.0 / C.diagonal())
+    assert i0 == 0 and not x0.any()
+
+
+@pytest.mark.parametrize("dim,N,tau,m11", [(2, 6, 0.1, 1.0), (2, 6, 1.0, 1.0 / pfc.ROS3PW_GAMMA),
+                                           (3, 4, 0.5, 1.0 / pfc.ROS3PW_GAMMA)])
+def test_fgmres_pch_against_dense_lu(dim, N, tau, m11):
+    mesh, M, K, psi = _prob(dim, N)
+    r = -0.35
+    Nm = assembly.N_matrix(mesh, psi)
+    rng = np.random.default_rng(2)
+    b = rng.normal(size=3 * mesh.n)
+    A = pfc.AR_sparse(M, K, Nm, r, tau, m11)
+    yd = reference.dense_solve(A, b)
+    y, info = solve.solve_stage(M, K, Nm, r, tau, m11, b, tol=1e-8)
+    assert info["converged"]
+    assert np.linalg.norm(b - A @ y) <= 1e-8 * np.linalg.norm(b)
+    y2, info2 = solve.solve_stage(M, K, Nm, r, tau, m11, b, tol=1e-13)
+    assert np.linalg.norm(y2 - yd) <= 1e-10 * np.linalg.norm(yd)
+    # replaying the recorded schedule reproduces the solve exactly
+    y3, info3 = solve.solve_stage(M, K, Nm, r, tau, m11, b, tol=1e-8, replay=info["schedule"])
+    assert np.array_equal(y3, y) and info3["steps"] == info["steps"]
+
+
+def test_unpreconditioned_gmres_agrees_with_dense_lu():
+    mesh, M, K, psi = _prob(2, 4)
+    r, tau = -0.35, 0.3
+    A = pfc.AR_sparse(M, K, assembly.N_matrix(mesh, psi), r, tau, 1.0)
+    b = np.random.default_rng(5).normal(size=3 * mesh.n)
+    y, info = krylov.fgmres(lambda v: A @ v, lambda v: v, b, tol=1e-11, restart=3 * mesh.n)
+    yd = reference.dense_solve(A, b)
+    assert np.linalg.norm(y - yd) <= 1e-8 * np.linalg.norm(yd)
+    # and the preconditioned one needs far fewer steps (Section 6, Fig. precon_no-precon)
+    _, info_p = solve.solve_stage(M, K, assembly.N_matrix(mesh, psi), r, tau, 1.0, b, tol=1e-11)
+    assert info_p["steps"] < info["steps"]
+
+
+@pytest.mark.parametrize("dim,N", [(2, 6), (3, 3)])
+def test_fft_exact_against_dense(dim, N):
+    mesh = wl.make_mesh(dim, N, jitter=0.0)
+    M, K = assembly.mass_stiffness(mesh)
+    c = -0.27
+    r, tau, m11 = -0.3, 0.8, 1.0 / pfc.ROS3PW_GAMMA
+    Nm = assembly.N_matrix(mesh, np.full(mesh.n, c))
+    b = np.random.default_rng(7).normal(size=3 * mesh.n)
+    yd = reference.dense_solve(pfc.AR_sparse(M, K, Nm, r, tau, m11), b)
+    yf = reference.fft_exact(mesh, M, K, r, tau, m11, c, b)
+    assert np.linalg.norm(yf - yd) <= 1e-12 * np.linalg.norm(yd)
+
+
+def test_fgmres_against_fft_exact_mid_size():
+    mesh = wl.make_mesh(2, 32, jitter=0.0)
+    M, K = assembly.mass_stiffness(mesh)
+    c, r, tau, m11 = -0.3, -0.35, 1.0, 1.0 / pfc.ROS3PW_GAMMA
+    Nm = assembly.N_matrix(mesh, np.full(mesh.n, c))
+    b = np.random.default_rng(9).normal(size=3 * mesh.n)
+    yf = reference.fft_exact(mesh, M, K, r, tau, m11, c, b)
+    y, info = solve.solve_stage(M, K, Nm, r, tau, m11, b, tol=1e-12)
+    assert np.linalg.norm(y - yf) <= 1e-10 * np.linalg.norm(yf)
+    # iteration counts of the same order as the paper's tables (context, not a pin of the paper's numbers)
+    assert 5 <= info["steps"] <= 80
