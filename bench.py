@@ -1,0 +1,145 @@
+"""Benchmark of the PFC block-preconditioned FGMRES stage solve on one MI355X.
+
+Default workload (the headline configuration): 2D periodic 512x512 P1 mesh
+(262,144 nodes, 786,432 unknowns), node positions jittered by U[-0.2h, 0.2h],
+r = -0.35, psibar = -0.3, psi_0 = psibar + U[-0.01, 0.01], Ros3Pw steps with
+tau = 1.0, N(psi) reassembled every step, FGMRES(30) to 1e-8 relative
+residual, float64.  One "step" is one Rosenbrock step: N reassembly and three
+stage solves.  Inputs are synthetic and seeded; everything is resident in HBM
+before the timed region starts.
+
+Prints one JSON line.  `value` is stage solves per second.  `roofline` uses the
+algorithmic bytes of the solver kernel (paper_1501_06852_amd.roofline) per
+launch over the average launch period measured with HIP events on the solver
+stream.  `cpu_baseline` times the float64 oracle on one Rosenbrock step of the
+same workload on the host (single thread).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (dim, N, jitter, r, psibar, tau, precision, default steps)
+    "pfc2d_512_fp64": (2, 512, 0.2, -0.35, -0.3, 1.0, 0, 20),
+    "pfc3d_64_mixed": (3, 64, 0.0, -0.3, -0.25, 0.5, 1, 10),
+    "pfc2d_64_fp64": (2, 64, 0.0, -0.35, -0.3, 0.1, 0, 1),
+}
+
+
+def run_cpu_baseline(dim, N, jitter, r, psibar, tau, seed):
+    """The oracle as it stands, one Rosenbrock step (three stage solves), one thread."""
+    from threadpoolctl import threadpool_limits
+
+    import workloads as wl
+    from oracle import assembly, pfc as opfc, solve as osolve
+
+    mesh = wl.make_mesh(dim, N, jitter=jitter, seed=seed)
+    M, K = assembly.mass_stiffness(mesh)
+    psi = wl.psi0(mesh.n, psibar, 0.01, seed=seed)
+    with threadpool_limits(1):
+        x0 = opfc.consistent_init(mesh, M, K, r, psi)
+        t0 = time.perf_counter()
+        x1, infos = osolve.rosenbrock_run(mesh, M, K, x0, r, tau, 1, tol=1e-8)
+        dt = time.perf_counter() - t0
+    return dict(value=3.0 / dt, unit="stage solves/s", cores=1, kind="oracle",
+                sample=f"1 Rosenbrock step (3 stage solves, {sum(i['steps'] for i in infos)} Arnoldi steps) of the same "
+                       f"workload, oracle float64 FGMRES(30)+P_CH+Jacobi-PCG, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="pfc2d_512_fp64", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import workloads as wl
+    from paper_1501_06852_amd import pfc, roofline
+
+    dim, N, jitter, r, psibar, tau, prec, dsteps = WORKLOADS[args.workload]
+    steps = args.steps if args.steps is not None else dsteps
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    mesh = wl.make_mesh(dim, N, jitter=jitter, seed=args.seed)
+    n = mesh.n
+    h = pfc.pfc_mesh_create_p1(dim, n, mesh.elem_nodes, mesh.elem_coords)
+    nnz = pfc.pfc_mesh_query(h)["nnz"]
+    z = nnz // n
+    opts = pfc.pfc_opts_default(precision=prec, max_run_steps=max(steps, args.warmup, 1))
+    inst = pfc.pfc_instance_create(h, opts)
+    psi = wl.psi0(n, psibar, 0.01, seed=args.seed)
+    state = torch.zeros(3 * n, dtype=torch.float64, device=dev)
+    state[n:2 * n] = torch.tensor(psi, dtype=torch.float64, device=dev)
+    # warm-up: consistent initial values and `warmup` steps (not timed)
+    pfc.pfc_rosenbrock_run(inst, n, state, r, psibar, tau, max(args.warmup, 0), pfc.PFC_INIT_CONSISTENT)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    st, infos = pfc.pfc_rosenbrock_run(inst, n, state, r, psibar, tau, steps, pfc.PFC_INIT_GIVEN)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    launches, graphs = pfc.pfc_instance_launch_stats(inst)
+    solves = 3 * steps
+    w = 4 if prec == 1 else 8
+    alg = sum(roofline.solve_bytes(n, z, w, i) for i in infos) + steps * roofline.step_bytes(n, z, mesh.n_elem, dim)
+    period_s = gpu_ms * 1e-3 / max(1, launches)
+    achieved = alg / max(1, launches) / period_s / 1e9
+    res = [i["true_rel_res"] for i in infos]
+    out = {
+        "metric": "PFC block solves/s @1e-8 rel residual",
+        "value": solves / wall,
+        "unit": "stage solves/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == 0 else "f64 outer / f32 inner",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dim": dim, "grid": N, "nodes": n, "unknowns": 3 * n,
+                   "jitter_h": jitter, "r": r, "psibar": psibar, "tau": tau, "rosenbrock_steps": steps,
+                   "stage_solves": solves, "restart": 30, "outer_tol": 1e-8, "inner_tol": 1e-3},
+        "status": pfc.pfc_status_str(st),
+        "max_true_rel_res": max(res) if res else None,
+        "outer_iters_mean": float(np.mean([i["outer_iters"] for i in infos])),
+        "inner_pcg_per_apply_mean": float(np.mean([i["inner_total"] / max(1, i["inner_applies"]) for i in infos])),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_tick (solver phase launch)", "launches": launches,
+                     "algorithmic_bytes": alg, "avg_launch_period_us": period_s * 1e6},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = run_cpu_baseline(dim, N, jitter, r, psibar, tau, args.seed)
+    pfc.pfc_instance_destroy(inst)
+    pfc.pfc_mesh_destroy(h)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,319 @@
+/*
+ * pfc.h -- C ABI of the MI355X (gfx950) solver for the block-preconditioned
+ * FGMRES solve of the Phase-Field Crystal (PFC2) Rosenbrock stage system.
+ *
+ * The method is that of Praetorius & Voigt, "Development and Analysis of a
+ * Block-Preconditioner for the Phase-Field Crystal Equation":
+ *   - P1 finite elements on a simplicial mesh: mass M, stiffness K and the
+ *     psi^2-weighted mass matrix N(psi) = -3 (psi^2 phi_j, phi_i)  (Section 3);
+ *   - the 3x3 block stage matrix of the Ros3Pw Rosenbrock scheme
+ *         A^R = [[M, -(1+r)M + 2K + N(psi_k), K], [tau K, m11 M, 0], [0, K, M]]
+ *     (eq. rosenbrock_matrix with the PFC2 mobility, K_+ = K, F = 0), with
+ *     m11 = 1/gamma for Rosenbrock stages and m11 = 1 for the linearised Euler
+ *     system (eq. systemmatrix);
+ *   - right-preconditioned flexible GMRES(restart) with modified Gram-Schmidt
+ *     (Section 4 and the solver settings of Section 6);
+ *   - the preconditioner P_CH = P(S_CH) of eq. preconditioner_S with
+ *     S_CH = (M + sqrt(delta) K) M^{-1} (M + sqrt(delta) K), delta = sqrt(tau),
+ *     applied in five steps with Jacobi-PCG inner solves (Section 4.2,
+ *     Table inner_solvers).
+ *
+ * Conventions shared by every call
+ *   - Block vectors of length 3n are stored block by block:
+ *       [mu(0..n-1) | psi(0..n-1) | omega(0..n-1)].
+ *   - "device" pointers are HIP device allocations of the current device
+ *     (e.g. the data of a torch tensor on cuda:0); "host" pointers are
+ *     ordinary host memory.  Each argument below says which.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *     Calls that take a stream enqueue their work on it and return only when
+ *     that work has completed (they are synchronous towards the caller).
+ *   - Inputs are owned by the caller and only read during the call; outputs
+ *     are written into caller-owned buffers.  Handles are owned by the
+ *     library until the matching *_destroy.  A handle must not be used by
+ *     two host threads at once.
+ *   - The library never aborts and never prints.  Every int-returning call
+ *     returns a status code below; on a negative code, pfc_last_error()
+ *     returns a message for the calling thread.
+ *   - All arithmetic of the outer solver is float64.  In PFC_MIXED precision
+ *     the inner PCG solves and their matrix-vector products use float32.
+ */
+#ifndef PFC_H
+#define PFC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define PFC_OK                 0
+#define PFC_NOT_CONVERGED      1  /* max_steps reached; x holds the last iterate, info valid */
+#define PFC_WARN_TAU_CRITICAL  2  /* converged, but tau >= tau*(r, psibar) of Lemma 3 */
+#define PFC_ERR_ARG           -1  /* invalid argument (nothing was enqueued) */
+#define PFC_ERR_OOM           -2  /* device or host allocation failed */
+#define PFC_ERR_HIP           -3  /* a HIP runtime call failed */
+#define PFC_ERR_BREAKDOWN     -4  /* non-finite residual or input */
+#define PFC_ERR_ADMISSION     -5  /* request does not fit the server's memory budget */
+#define PFC_ERR_STATE         -6  /* call not valid in the handle's current state */
+
+enum { PFC_FP64 = 0, PFC_MIXED = 1 };
+enum { PFC_INIT_GIVEN = 0, PFC_INIT_CONSISTENT = 1 };
+enum { PFC_OP_M = 0, PFC_OP_K = 1 };
+
+typedef struct pfc_mesh pfc_mesh;
+typedef struct pfc_instance pfc_instance;
+typedef struct pfc_server pfc_server;
+
+/* Solver options.  Fill with pfc_opts_default, then override fields.
+ *   precision     PFC_FP64 or PFC_MIXED (float32 inner PCG, float64 FGMRES)
+ *   restart       FGMRES restart length m, 1..32 (the paper uses 30)
+ *   max_steps     cap on the total number of Arnoldi steps of one solve
+ *   outer_tol     relative residual ||b - A^R x||_2 / ||b||_2 to reach (1e-8)
+ *   inner_tol     relative residual of every inner PCG solve (1e-3, Table inner_solvers)
+ *   inner_maxit   iteration cap of an inner PCG solve (500)
+ *   shared_ops    0: store M + delta K and M + sqrt(delta) K per instance;
+ *                 1: form them on the fly from the mesh's M and K (less memory,
+ *                 more bytes per iteration; useful when many instances share a mesh)
+ *   rows_per_thread  rows of the mesh handled per thread in each phase (1..8, 0 = auto)
+ *   max_run_steps capacity of per-stage info records of a Rosenbrock run (steps)
+ *   ticks_per_graph  solver phases captured per replayed graph (0 = auto) */
+typedef struct pfc_opts {
+    int struct_size;
+    int precision;
+    int restart;
+    int max_steps;
+    double outer_tol;
+    double inner_tol;
+    int inner_maxit;
+    int shared_ops;
+    int rows_per_thread;
+    int max_run_steps;
+    int ticks_per_graph;
+    int reserved;
+} pfc_opts;
+
+/* Result record of one stage solve.
+ *   status        PFC_OK / PFC_NOT_CONVERGED / PFC_ERR_BREAKDOWN for this solve
+ *   outer_iters   Arnoldi steps (the iteration count of the paper's tables)
+ *   cycles        FGMRES cycles (restarts + 1)
+ *   inner_applies preconditioner applications
+ *   inner_total   PCG iterations summed over all applications and steps
+ *   inner_max     largest PCG count seen in each of the five steps (1, 2, 3.1, 3.2, 5)
+ *   est_rel_res   last Givens estimate |g_{k}| / ||b_scaled||
+ *   true_rel_res  ||b - A^R x||_2 / ||b||_2 recomputed in float64 */
+typedef struct pfc_solve_info {
+    int status;
+    int outer_iters;
+    int cycles;
+    int inner_applies;
+    long long inner_total;
+    int inner_max[5];
+    int reserved;
+    double est_rel_res;
+    double true_rel_res;
+} pfc_solve_info;
+
+/* Recorded iteration structure of one FGMRES solve, for replay: the length
+ * of each cycle and, for each preconditioner application in order, the five
+ * inner PCG iteration counts.  Host memory. */
+typedef struct pfc_schedule {
+    int n_cycles;
+    const int* cycle_len;     /* [n_cycles] */
+    int n_applies;
+    const int* inner_counts;  /* [5 * n_applies] */
+} pfc_schedule;
+
+/* ---- misc --------------------------------------------------------------- */
+const char* pfc_status_str(int status);
+const char* pfc_last_error(void);
+void pfc_opts_default(pfc_opts* opts);
+/* Lemma 3: tau* = 27 / (2 (sqrt(a) - 1)(sqrt(a) + 2)^2), a = 1 - 3 r - 9 psibar^2;
+ * +infinity when psibar^2 >= -r/3.  Pure host arithmetic. */
+double pfc_tau_critical(double r, double psibar);
+
+/* ---- meshes ---------------------------------------------------------------
+ * A mesh holds the shared sparsity pattern of M, K and N(psi) (the P1 pattern:
+ * every pair of nodes of a common simplex, diagonal included), the values of
+ * M and K, and the element lists needed to reassemble N(psi) and the cubic
+ * load (psi_h^3, phi_i) in place.
+ *
+ * pfc_mesh_create_p1: assemble M and K on the GPU from simplices (Section 3):
+ *   M_ij = (phi_j, phi_i), K_ij = (grad phi_j, grad phi_i), exact for P1.
+ *   dim          2 (triangles) or 3 (tetrahedra)
+ *   n            number of nodes
+ *   n_elem       number of simplices
+ *   elem_nodes   host int32 [n_elem * (dim+1)], node indices in [0, n), distinct per simplex
+ *   elem_coords  host float64 [n_elem * (dim+1) * dim], vertex coordinates of
+ *                each simplex, unwrapped across periodic boundaries
+ *   out          receives the handle
+ * Returns PFC_ERR_ARG for out-of-range or repeated nodes, degenerate
+ * simplices or non-finite coordinates. */
+int pfc_mesh_create_p1(int dim, int n, int n_elem, const int32_t* elem_nodes,
+                       const double* elem_coords, pfc_mesh** out);
+
+/* pfc_mesh_create_csr: take M and K from the caller in CSR form (host arrays).
+ *   row_ptr [n+1], col_idx [nnz]: sorted column indices per row, diagonal
+ *   present, pattern structurally symmetric and containing every node pair
+ *   of every simplex; M_val, K_val [nnz] float64; elem_nodes as above;
+ *   elem_vol [n_elem] simplex measures |T| (used by the reassembly of N and
+ *   of the cubic load).  PFC_ERR_ARG on any violation. */
+int pfc_mesh_create_csr(int dim, int n, int nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                        const double* M_val, const double* K_val, int n_elem,
+                        const int32_t* elem_nodes, const double* elem_vol, pfc_mesh** out);
+
+/* Sizes of a mesh; any pointer may be NULL. */
+int pfc_mesh_query(const pfc_mesh* mesh, int* dim, int* n, int* nnz, int* n_elem);
+
+/* Copy the pattern and the values of M and K out in CSR order (host arrays of
+ * n+1, nnz, nnz, nnz entries; any of them may be NULL). */
+int pfc_mesh_export_csr(const pfc_mesh* mesh, int32_t* row_ptr, int32_t* col_idx,
+                        double* M_val, double* K_val);
+
+void pfc_mesh_destroy(pfc_mesh* mesh);
+
+/* ---- mesh-level operators (device pointers) ------------------------------ */
+/* y = M x (which = PFC_OP_M) or y = K x (PFC_OP_K); x, y device float64 [n]. */
+int pfc_spmv(const pfc_mesh* mesh, int which, const double* x, double* y, void* stream);
+/* Values of N(psi) = -3 (psi_h^2 phi_j, phi_i) in CSR order of the mesh pattern
+ * (Section 3, exact quadrature); psi device [n], N_csr device [nnz]. */
+int pfc_assemble_N(const pfc_mesh* mesh, const double* psi, double* N_csr, void* stream);
+/* Cubic load g_i = (psi_h^3, phi_i) (the psi^3 term of the operator F,
+ * Section 3.1); psi, g device [n]. */
+int pfc_load_psi3(const pfc_mesh* mesh, const double* psi, double* g, void* stream);
+
+/* ---- instances ------------------------------------------------------------
+ * An instance owns all device memory of one solver on one mesh: the FGMRES
+ * basis (restart+1 vectors V and restart vectors Z of length 3n, float64),
+ * the per-tau operator values, N(psi_k), the Rosenbrock state and the PCG
+ * work vectors.  Everything is allocated at creation. */
+size_t pfc_instance_footprint(const pfc_mesh* mesh, const pfc_opts* opts);
+int pfc_instance_create(pfc_mesh* mesh, const pfc_opts* opts, pfc_instance** out);
+void pfc_instance_destroy(pfc_instance* inst);
+
+/* One stage solve, the hot path: A^R x = rhs with A^R built from the mesh's
+ * M, K and N(psi_k) reassembled from psi_k, parameters r and tau, and the mass
+ * coefficient m11 of block row 1 (1/gamma for Ros3Pw stages, 1 for Euler).
+ * FGMRES starts from x = 0.  Block row 1 is divided by m11 before the solve
+ * so that P_CH, derived for m11 = 1, is built with tau/m11; the solution is
+ * unchanged and convergence is judged on the unscaled system.
+ *   psi_k   device float64 [n]
+ *   rhs     device float64 [3n]
+ *   x       device float64 [3n] (output)
+ *   psibar  used only for the tau* check of Lemma 3
+ *   replay  NULL, or a host schedule: run exactly that iteration structure
+ *           (fixed cycle lengths and inner counts) instead of the tolerances
+ *   info    host record (may be NULL)
+ * Returns the solve's status (PFC_WARN_TAU_CRITICAL replaces PFC_OK when
+ * tau >= tau*(r, psibar)). */
+int pfc_solve(pfc_instance* inst, const double* psi_k, double r, double psibar, double tau,
+              double m11, const double* rhs, double* x, const pfc_schedule* replay,
+              pfc_solve_info* info, void* stream);
+
+/* After a pfc_solve without replay: copy the recorded inner counts of its
+ * preconditioner applications (5 per application, in order) into the host
+ * array counts of capacity cap applications; *n_applies receives the count. */
+int pfc_last_inner_counts(const pfc_instance* inst, int* counts, int cap, int* n_applies);
+
+/* Launch statistics of the instance's most recent solve or run: number of
+ * solver-kernel launches issued (replayed graphs times launches per graph,
+ * including launches that found the instance finished) and number of graph
+ * replays.  Host outputs; either may be NULL. */
+int pfc_instance_launch_stats(const pfc_instance* inst, long long* launches, long long* graphs);
+
+/* n_steps Ros3Pw steps (eqs. rosenbrock, rosenbrock-update; Table
+ * rosenbrock_scheme) of the PFC2 system from state = (mu, psi, omega):
+ * per step N(psi_k) is reassembled in place, then for i = 1, 2, 3 the stage
+ * right-hand side b_i^R is formed and A^R y_i = b_i^R solved, and finally
+ * x_{k+1} = x_k + sum m_j y_j.
+ *   state     device float64 [3n], in/out
+ *   init      PFC_INIT_GIVEN: use state as given; PFC_INIT_CONSISTENT: replace
+ *             mu and omega by the values that zero blocks 0 and 2 of F at psi
+ *             (M omega = -K psi, M mu = (1+r) M psi - 2 K psi - K omega + g(psi))
+ *   replays   NULL, or a host array of 3*n_steps schedules, one per stage solve
+ *   per_stage host array of 3*n_steps records (may be NULL)
+ * Returns the worst status over all stage solves. */
+int pfc_rosenbrock_run(pfc_instance* inst, double* state, double r, double psibar, double tau,
+                       int n_steps, int init, const pfc_schedule* replays,
+                       pfc_solve_info* per_stage, void* stream);
+
+/* Operator-level entry points of the hot path (device pointers). */
+/* out = A^R y with N(psi_k) reassembled from psi_k; y, out [3n]. */
+int pfc_apply_AR(pfc_instance* inst, const double* psi_k, double r, double tau, double m11,
+                 const double* y, double* out, void* stream);
+/* z = P_CH^{-1} v with parameter tau_s (the tau of block row 1 after division
+ * by m11): the five steps (1), (2), (3.1), (3.2), (4), (5) of Section 4.2 with
+ * Jacobi-PCG inner solves.  fixed_counts: NULL (tolerance inner_tol) or host
+ * int[5] exact iteration counts; counts_out: host int[5] or NULL. */
+int pfc_apply_pch(pfc_instance* inst, double tau_s, const double* v, double* z,
+                  const int* fixed_counts, int* counts_out, void* stream);
+/* Stage right-hand side b_i^R of stage `stage` (1..3) at step state x_k and
+ * earlier stage solutions ys = [y_1 | y_2 | y_3] (device, 3 x 3n; only
+ * y_1..y_{stage-1} read): b0 = F0(x_i), b1 = tau F1(x_i) + sum c_ij M y_j^psi,
+ * b2 = F2(x_i), x_i = x_k + sum a_ij y_j.  b device [3n]. */
+int pfc_stage_rhs(pfc_instance* inst, const double* x_k, const double* ys, int stage,
+                  double r, double tau, double* b, void* stream);
+
+/* ---- batches -------------------------------------------------------------
+ * Rosenbrock runs of `count` instances (same precision) advanced together:
+ * every launch of the solver kernel advances every unfinished instance by one
+ * phase, each instance on its own team of workgroups.
+ *   insts    host array of instance handles (distinct)
+ *   states   host array of device pointers, states[i] float64 [3 n_i]
+ *   r, psibar, tau  host arrays [count]
+ *   infos    host array of count*3*n_steps records (may be NULL), instance-major */
+int pfc_batch_run(pfc_instance* const* insts, int count, double* const* states,
+                  const double* r, const double* psibar, const double* tau, int n_steps,
+                  int init, pfc_solve_info* infos, void* stream);
+
+/* ---- serving --------------------------------------------------------------
+ * A server runs a library-owned thread that keeps a set of active requests
+ * resident on the GPU and advances them together (continuous batching at the
+ * granularity of solver phases).  Requests are admitted when their instance
+ * footprint fits into the remaining budget and a slot is free; finished
+ * requests are retired and their memory is released.
+ *   hbm_budget  bytes of device memory the server may hold for instances
+ *   max_slots   maximum number of concurrently active requests
+ *   precision   PFC_FP64 or PFC_MIXED
+ *   n_steps ... Rosenbrock steps per request (set per request) */
+typedef struct pfc_server_opts {
+    int struct_size;
+    int precision;
+    size_t hbm_budget;
+    int max_slots;
+    int ticks_per_graph;
+} pfc_server_opts;
+
+typedef struct pfc_result {
+    uint64_t req_id;
+    int status;
+    int n_stages;
+    double t_submit;     /* seconds, library clock */
+    double t_admit;
+    double t_done;
+    double* state;       /* host float64 [3n] final state; owned by the caller after poll */
+    pfc_solve_info* infos; /* host [n_stages]; owned by the caller after poll */
+} pfc_result;
+
+int pfc_server_create(const pfc_server_opts* opts, pfc_server** out);
+/* Submit a request: Rosenbrock run of n_steps on `mesh` (kept alive by the
+ * caller until the result is polled) from psi0 (host float64 [n]) with
+ * consistent initial mu, omega.  Returns PFC_ERR_ADMISSION if the request can
+ * never fit the budget. */
+int pfc_server_submit(pfc_server* srv, pfc_mesh* mesh, double r, double psibar, double tau,
+                      const double* psi0, int n_steps, uint64_t req_id);
+/* Collect up to max finished results (non-blocking); *n_out receives the count.
+ * The state and infos arrays of each result are malloc'ed; free them with
+ * pfc_result_free. */
+int pfc_server_poll(pfc_server* srv, pfc_result* out, int max, int* n_out);
+void pfc_result_free(pfc_result* res);
+/* Block until every submitted request has finished. */
+int pfc_server_drain(pfc_server* srv);
+double pfc_server_clock(const pfc_server* srv);
+void pfc_server_destroy(pfc_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFC_H */

@@ -95,13 +95,22 @@ def stage_rhs_R(mesh, M, K, r, tau, x_i, y_prev_psi, c_row):
 
 
 def consistent_init(mesh, M, K, r, psi0):
-    """mu_0, omega_0 that zero blocks 0 and 2 of F at t = 0 (exact solves with M).
+    """mu_0, omega_0 that zero blocks 0 and 2 of F at t = 0.
 
     M omega_0 = -K psi_0;  M mu_0 = (1+r) M psi_0 - 2 K psi_0 - K omega_0 + g(psi_0).
+    The two mass solves are taken to rounding level (Jacobi CG, relative
+    residual 1e-15; M is SPD with a mesh-independent condition number), which
+    agrees with a sparse LU solve to rounding (pinned in the tests).
     """
-    Mc = M.tocsc()
-    om = spla.spsolve(Mc, -(K @ psi0))
-    mu = spla.spsolve(Mc, (1.0 + r) * (M @ psi0) - 2.0 * (K @ psi0) - K @ om + load_psi3(mesh, psi0))
+    from .krylov import pcg
+
+    dinv = 1.0 / M.diagonal()
+
+    def msolve(rhs):
+        return pcg(lambda v: M @ v, rhs, dinv, tol=1e-15, maxit=1000)[0]
+
+    om = msolve(-(K @ psi0))
+    mu = msolve((1.0 + r) * (M @ psi0) - 2.0 * (K @ psi0) - K @ om + load_psi3(mesh, psi0))
     return np.concatenate([mu, psi0, om])
 
 

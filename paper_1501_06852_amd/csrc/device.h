@@ -1,0 +1,553 @@
+// Device functions of the PFC stage solver: the work of every solver phase,
+// executed by one team of workgroups over its block of SELL-64 slices.
+//
+// Each thread owns row i = slice*64 + lane of the node numbering and, in the
+// 3x3 block phases, the three entries i, n+i, 2n+i of a block vector.  Dot
+// products are accumulated per thread in float64, reduced per wavefront by a
+// fixed butterfly (lane 0's result is used), then per workgroup in fixed
+// order, and stored as one partial per workgroup; the next launch sums the
+// partials in fixed order.  Results are therefore bitwise reproducible and
+// independent of what else runs in the same launch.
+#pragma once
+#include "pfc_internal.h"
+
+namespace pfc {
+
+struct Team {
+  int rank, size;   // workgroup rank within the team, team size
+  int wave, lane;   // wave within the workgroup, lane
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum (a, b) over the workgroup; result valid in thread 0.
+__device__ __forceinline__ double2 wg_sum2(double a, double b, double2* lds4) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) lds4[wave] = make_double2(a, b);
+  __syncthreads();
+  double2 r = make_double2(0.0, 0.0);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < PFC_WAVES; ++w) { r.x += lds4[w].x; r.y += lds4[w].y; }
+  }
+  __syncthreads();
+  return r;
+}
+
+// Slices handled by this workgroup: a contiguous block, cycled over its waves.
+#define PFC_SLICES(I, tm)                                                          \
+  const int _spw = ((I).m.n_slices + (tm).size - 1) / (tm).size;                   \
+  const int _sbeg = (tm).rank * _spw;                                              \
+  const int _send = min(_sbeg + _spw, (I).m.n_slices);                              \
+  for (int sl = _sbeg + (tm).wave; sl < _send; sl += PFC_WAVES)
+
+// ---- typed views ----------------------------------------------------------
+template <typename T> struct TV;
+template <> struct TV<double> {
+  __device__ static const double* M(const InstDev& I) { return I.m.M; }
+  __device__ static const double* K(const InstDev& I) { return I.m.K; }
+  __device__ static const double* dM(const InstDev& I) { return I.m.dinvM; }
+};
+template <> struct TV<float> {
+  __device__ static const float* M(const InstDev& I) { return I.m.Mf; }
+  __device__ static const float* K(const InstDev& I) { return I.m.Kf; }
+  __device__ static const float* dM(const InstDev& I) { return I.m.dinvMf; }
+};
+
+// ---- element integrals (exact for P1, Section 3) ----------------------------
+// int_T psi_h^2 lambda_a lambda_b = |T| c_m (1 + [a==b]) [S1^2 + S2 + 2 S1 (pa + pb) + 2 (pa^2 + pb^2 + pa pb)]
+// int_T psi_h^3 lambda_a         = |T| c_m [S1^3 + 3 S1 S2 + 2 S3 + 3 pa (S1^2 + S2) + 6 pa^2 S1 + 6 pa^3]
+// with S_k = sum over the vertices of psi^k and c_m = m!/(m+4)!.
+__device__ __forceinline__ double cm_of(int dim) { return dim == 2 ? (1.0 / 360.0) : (1.0 / 840.0); }
+
+// psi values of the vertices of element el; psi(node) supplied by a functor
+template <typename PsiF>
+__device__ __forceinline__ void elem_psi(const MeshDev& m, int el, PsiF psi, double* p) {
+  const int k = m.dim + 1;
+  const int* en = m.elem_nodes + (long long)el * k;
+  for (int a = 0; a < k; ++a) p[a] = psi(en[a]);
+}
+
+template <typename PsiF>
+__device__ double entry_Mpsi2(const MeshDev& m, long long e, PsiF psi) {
+  double acc = 0.0;
+  const double cm = cm_of(m.dim);
+  const int t0 = m.sl_el_ptr[e], t1 = m.sl_el_ptr[e + 1];
+  for (int t = t0; t < t1; ++t) {
+    const int pk = m.sl_el[t];
+    const int el = pk >> 4, a = (pk >> 2) & 3, b = pk & 3;
+    double p[4];
+    elem_psi(m, el, psi, p);
+    double S1 = 0.0, S2 = 0.0;
+    for (int v = 0; v <= m.dim; ++v) { S1 += p[v]; S2 += p[v] * p[v]; }
+    const double pa = p[a], pb = p[b];
+    const double s = S1 * S1 + S2 + 2.0 * S1 * (pa + pb) + 2.0 * (pa * pa + pb * pb + pa * pb);
+    acc += m.elem_vol[el] * cm * (a == b ? 2.0 : 1.0) * s;
+  }
+  return acc;
+}
+
+template <typename PsiF>
+__device__ double node_psi3(const MeshDev& m, int i, PsiF psi) {
+  double acc = 0.0;
+  const double cm = cm_of(m.dim);
+  const int t0 = m.nd_el_ptr[i], t1 = m.nd_el_ptr[i + 1];
+  for (int t = t0; t < t1; ++t) {
+    const int pk = m.nd_el[t];
+    const int el = pk >> 2, a = pk & 3;
+    double p[4];
+    elem_psi(m, el, psi, p);
+    double S1 = 0.0, S2 = 0.0, S3 = 0.0;
+    for (int v = 0; v <= m.dim; ++v) { S1 += p[v]; S2 += p[v] * p[v]; S3 += p[v] * p[v] * p[v]; }
+    const double pa = p[a];
+    const double s = S1 * S1 * S1 + 3.0 * S1 * S2 + 2.0 * S3 + 3.0 * pa * (S1 * S1 + S2) + 6.0 * pa * pa * S1 + 6.0 * pa * pa * pa;
+    acc += m.elem_vol[el] * cm * s;
+  }
+  return acc;
+}
+
+// ---- phases ---------------------------------------------------------------
+// Every phase returns this thread's contribution to the two partial sums.
+
+// N(psi_k) = -3 Mpsi2 reassembled in place (one value per stored entry).
+__device__ double2 ph_rb_begin(const InstDev& I, const Team& tm) {
+  const int n = I.n;
+  const double* xk = I.xk;
+  auto psi = [&](int j) { return xk[n + j]; };
+  PFC_SLICES(I, tm) {
+    const int base = I.m.slice_ptr[sl];
+    const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
+    const int lane = tm.lane;
+    for (int k = 0; k < w; ++k) {
+      const long long e = (long long)base + k * 64 + lane;
+      I.N[e] = -3.0 * entry_Mpsi2(I.m, e, psi);
+    }
+  }
+  return make_double2(0.0, 0.0);
+}
+
+__device__ __forceinline__ double stage_comb(const InstDev& I, int stage, int blk, int j) {
+  const long long n3 = 3LL * I.n;
+  const long long o = (long long)blk * I.n + j;
+  double v = I.xk[o];
+  if (stage == 2) v += ROS_A21 * I.ys[o];
+  if (stage == 3) v += ROS_A31 * I.ys[o] + ROS_A32 * I.ys[n3 + o];
+  return v;
+}
+
+// Stage right-hand side at the row of (slice, lane) (Section 3.1): F(x_i) with
+// block 1 multiplied by tau, plus sum_j c_ij M y_j^psi on block 1, with the
+// stage state x_i = x_k + sum_j a_ij y_j formed on the fly.
+__device__ __forceinline__ void stage_rhs_row(const InstDev& I, int sl, int lane, int stage, double& b0, double& b1,
+                                              double& b2) {
+  const int n = I.n;
+  const int i = sl * 64 + lane;
+  const int base = I.m.slice_ptr[sl];
+  const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
+  double sMmu = 0, sMps = 0, sMom = 0, sKmu = 0, sKps = 0, sKom = 0, sMy1 = 0, sMy2 = 0;
+  const long long n3 = 3LL * n;
+  for (int k = 0; k < w; ++k) {
+    const long long e = (long long)base + k * 64 + lane;
+    const int j = I.m.col[e];
+    const double Mv = I.m.M[e], Kv = I.m.K[e];
+    const double mu = stage_comb(I, stage, 0, j);
+    const double ps = stage_comb(I, stage, 1, j);
+    const double om = stage_comb(I, stage, 2, j);
+    sMmu += Mv * mu; sMps += Mv * ps; sMom += Mv * om;
+    sKmu += Kv * mu; sKps += Kv * ps; sKom += Kv * om;
+    if (stage >= 2) sMy1 += Mv * I.ys[n + j];
+    if (stage >= 3) sMy2 += Mv * I.ys[n3 + n + j];
+  }
+  double g = 0.0;
+  if (i < n) g = node_psi3(I.m, i, [&](int j) { return stage_comb(I, stage, 1, j); });
+  b0 = -sMmu + (1.0 + I.r) * sMps - 2.0 * sKps - sKom + g;
+  b1 = I.tau * (-sKmu);
+  if (stage == 2) b1 += ROS_C21 * sMy1;
+  if (stage == 3) b1 += ROS_C31 * sMy1 + ROS_C32 * sMy2;
+  b2 = -sMom - sKps;
+}
+
+// Right-hand side of the solve: stage rhs b_i^R for job RB, the caller's rhs
+// for job SOLVE.  Writes W = b with block 1 divided by m11, X = 0.
+__device__ double2 ph_solve_init(const InstDev& I, const State& S, const Team& tm) {
+  const int n = I.n;
+  const bool rb = (S.job == JOB_RB);
+  double* X = rb ? (I.ys + (long long)(S.stage - 1) * 3 * n) : I.x_user;
+  const double im = 1.0 / I.m11;
+  double a0 = 0.0, a1 = 0.0;
+  PFC_SLICES(I, tm) {
+    const int i = sl * 64 + tm.lane;
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0;
+    if (rb) stage_rhs_row(I, sl, tm.lane, S.stage, b0, b1, b2);
+    if (i < n) {
+      if (rb) {
+        I.b[i] = b0; I.b[n + i] = b1; I.b[2 * n + i] = b2;
+      } else {
+        b0 = I.b_user[i]; b1 = I.b_user[n + i]; b2 = I.b_user[2 * n + i];
+      }
+      const double bs1 = b1 * im;
+      I.W[i] = b0; I.W[n + i] = bs1; I.W[2 * n + i] = b2;
+      X[i] = 0.0; X[n + i] = 0.0; X[2 * n + i] = 0.0;
+      a0 += b0 * b0 + b1 * b1 + b2 * b2;
+      a1 += b0 * b0 + bs1 * bs1 + b2 * b2;
+    }
+  }
+  return make_double2(a0, a1);
+}
+
+__device__ double2 ph_rb_update(const InstDev& I, const Team& tm) {
+  const int n = I.n;
+  const long long n3 = 3LL * n;
+  PFC_SLICES(I, tm) {
+    const int i = sl * 64 + tm.lane;
+    if (i < n) {
+      for (int blk = 0; blk < 3; ++blk) {
+        const long long o = (long long)blk * n + i;
+        I.xk[o] = I.xk[o] + ROS_M1 * I.ys[o] + ROS_M2 * I.ys[n3 + o] + ROS_M3 * I.ys[2 * n3 + o];
+      }
+    }
+  }
+  return make_double2(0.0, 0.0);
+}
+
+// ---- inner PCG --------------------------------------------------------------
+template <typename T>
+struct PcgOps {
+  const T* C;      // stored operator values, or nullptr for M + cK on the fly
+  const T* Mv;
+  const T* Kv;
+  T cK;
+  const T* dinv;
+  T* x;
+};
+
+template <typename T>
+__device__ __forceinline__ PcgOps<T> pcg_ops(const InstDev& I, int kind) {
+  PcgOps<T> o;
+  o.Mv = TV<T>::M(I);
+  o.Kv = TV<T>::K(I);
+  o.cK = T(0);
+  o.C = o.Mv;
+  o.dinv = TV<T>::dM(I);
+  o.x = nullptr;
+  const int n = I.n;
+  switch (kind) {
+    case KIND_Y0: o.x = (T*)I.y0; break;
+    case KIND_Y1:
+      o.x = (T*)I.y1;
+      o.dinv = (const T*)I.dinvCd;
+      if (I.shared_ops) { o.C = nullptr; o.cK = T(I.delta); } else o.C = (const T*)I.Cd;
+      break;
+    case KIND_Z:
+    case KIND_X1:
+      o.x = (T*)(kind == KIND_Z ? I.zt : I.x1);
+      o.dinv = (const T*)I.dinvCsd;
+      if (I.shared_ops) { o.C = nullptr; o.cK = T(I.sdelta); } else o.C = (const T*)I.Csd;
+      break;
+    case KIND_X2: o.x = (T*)I.x2; break;
+    case KIND_CI_OMEGA: o.x = (T*)(I.xk + 2LL * n); break;
+    case KIND_CI_MU: o.x = (T*)(I.xk); break;
+  }
+  return o;
+}
+
+template <typename T>
+__device__ __forceinline__ T opval(const PcgOps<T>& o, long long e) {
+  return o.C ? o.C[e] : (o.Mv[e] + o.cK * o.Kv[e]);
+}
+
+// y_i = (A v)_i for a stored operator A (typed) over the row of thread lane
+template <typename T, typename VF>
+__device__ __forceinline__ T row_dot(const InstDev& I, int sl, int lane, const T* A, VF v) {
+  const int base = I.m.slice_ptr[sl];
+  const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
+  T acc = T(0);
+  for (int k = 0; k < w; ++k) {
+    const long long e = (long long)base + k * 64 + lane;
+    acc += A[e] * v(I.m.col[e]);
+  }
+  return acc;
+}
+
+template <typename T>
+__device__ double2 ph_pcg_setup(const InstDev& I, const State& S, const Team& tm) {
+  const int n = I.n;
+  const int kind = S.kind;
+  PcgOps<T> o = pcg_ops<T>(I, kind);
+  T* r = (T*)I.r_;
+  const long long n3 = 3LL * n;
+  double* Vj = I.V + (long long)S.j * n3;
+  double* Zj = I.Z + (long long)S.j * n3;
+  const T* Mv = o.Mv;
+  const T* Kv = o.Kv;
+  double a0 = 0.0, a1 = 0.0;
+  PFC_SLICES(I, tm) {
+    const int i = sl * 64 + tm.lane;
+    const int lane = tm.lane;
+    double rhs = 0.0;
+    switch (kind) {
+      case KIND_Y0: {
+        if (i < n) {
+          const double vs = S.vscale;
+          const double v0 = I.W[i] * vs, v1 = I.W[n + i] * vs, v2 = I.W[2 * n + i] * vs;
+          Vj[i] = v0; Vj[n + i] = v1; Vj[2 * n + i] = v2;
+          rhs = v0;
+        }
+      } break;
+      case KIND_Y1: {  // (2): b1 - tau K y0
+        const T* y0 = (const T*)I.y0;
+        const T ky = row_dot<T>(I, sl, lane, Kv, [&](int j) { return y0[j]; });
+        if (i < n) rhs = Vj[n + i] - I.tau_s * (double)ky;
+      } break;
+      case KIND_Z: {  // (3.1): M y1
+        const T* y1 = (const T*)I.y1;
+        const T my = row_dot<T>(I, sl, lane, Mv, [&](int j) { return y1[j]; });
+        rhs = (double)my;
+      } break;
+      case KIND_X1: {  // (3.2): M z
+        const T* zt = (const T*)I.zt;
+        const T mz = row_dot<T>(I, sl, lane, Mv, [&](int j) { return zt[j]; });
+        rhs = (double)mz;
+      } break;
+      case KIND_X2: {  // (5): b2 - K x1, and (4): x0 = y0 + (y1 - x1)/delta
+        const T* x1 = (const T*)I.x1;
+        const T kx = row_dot<T>(I, sl, lane, Kv, [&](int j) { return x1[j]; });
+        if (i < n) {
+          rhs = Vj[2 * n + i] - (double)kx;
+          const double y0i = (double)((const T*)I.y0)[i], y1i = (double)((const T*)I.y1)[i];
+          const double x1i = (double)x1[i];
+          Zj[i] = y0i + (y1i - x1i) / I.delta;
+          Zj[n + i] = x1i;
+        }
+      } break;
+      case KIND_CI_OMEGA: {  // M omega_0 = -K psi_0
+        const double kp = row_dot<double>(I, sl, lane, I.m.K, [&](int j) { return I.xk[n + j]; });
+        rhs = -kp;
+      } break;
+      case KIND_CI_MU: {  // M mu_0 = (1+r) M psi_0 - 2 K psi_0 - K omega_0 + g(psi_0)
+        const int base = I.m.slice_ptr[sl];
+        const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
+        double sMp = 0, sKp = 0, sKo = 0;
+        for (int k = 0; k < w; ++k) {
+          const long long e = (long long)base + k * 64 + lane;
+          const int j = I.m.col[e];
+          sMp += I.m.M[e] * I.xk[n + j];
+          sKp += I.m.K[e] * I.xk[n + j];
+          sKo += I.m.K[e] * I.xk[2 * n + j];
+        }
+        if (i < n) {
+          auto psi = [&](int j) { return I.xk[n + j]; };
+          rhs = (1.0 + I.r) * sMp - 2.0 * sKp - sKo + node_psi3(I.m, i, psi);
+        }
+      } break;
+    }
+    if (i < n) {
+      const T rT = T(rhs);
+      r[i] = rT;
+      o.x[i] = T(0);
+      const double rd = (double)rT;
+      a0 += rd * ((double)o.dinv[i] * rd);
+      a1 += rd * rd;
+    }
+  }
+  return make_double2(a0, a1);
+}
+
+// p_j = D^{-1}_j r_j + beta p_old_j, evaluated identically wherever needed
+template <typename T>
+__device__ __forceinline__ T pval(const T* dinv, const T* r, const T* pold, T beta, bool first, int j) {
+  const T z = dinv[j] * r[j];
+  return first ? z : (z + beta * pold[j]);
+}
+
+template <typename T>
+__device__ double2 ph_pcg_a(const InstDev& I, const State& S, const Team& tm) {
+  const int n = I.n;
+  PcgOps<T> o = pcg_ops<T>(I, S.kind);
+  const T* r = (const T*)I.r_;
+  const T* pold = (const T*)(S.pcur ? I.pB : I.pA);
+  T* pnew = (T*)(S.pcur ? I.pA : I.pB);
+  T* q = (T*)I.q;
+  const bool first = (S.it == 0);
+  const T beta = T(S.beta_cg);
+  double a0 = 0.0;
+  PFC_SLICES(I, tm) {
+    const int i = sl * 64 + tm.lane;
+    const int base = I.m.slice_ptr[sl];
+    const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
+    T acc = T(0);
+    for (int k = 0; k < w; ++k) {
+      const long long e = (long long)base + k * 64 + tm.lane;
+      const int j = I.m.col[e];
+      acc += opval(o, e) * pval(o.dinv, r, pold, beta, first, j);
+    }
+    if (i < n) {
+      const T pi = pval(o.dinv, r, pold, beta, first, i);
+      pnew[i] = pi;
+      q[i] = acc;
+      a0 += (double)pi * (double)acc;
+    }
+  }
+  return make_double2(a0, 0.0);
+}
+
+template <typename T>
+__device__ double2 ph_pcg_b(const InstDev& I, const State& S, const Team& tm) {
+  const int n = I.n;
+  PcgOps<T> o = pcg_ops<T>(I, S.kind);
+  T* r = (T*)I.r_;
+  const T* p = (const T*)(S.pcur ? I.pB : I.pA);
+  const T* q = (const T*)I.q;
+  const T alpha = T(S.alpha);
+  double a0 = 0.0, a1 = 0.0;
+  PFC_SLICES(I, tm) {
+    const int i = sl * 64 + tm.lane;
+    if (i < n) {
+      const T xi = o.x[i] + alpha * p[i];
+      const T ri = r[i] - alpha * q[i];
+      o.x[i] = xi;
+      r[i] = ri;
+      const double rd = (double)ri;
+      a0 += rd * rd;
+      a1 += rd * ((double)o.dinv[i] * rd);
+    }
+  }
+  return make_double2(a0, a1);
+}
+
+// ---- outer block operator ------------------------------------------------------
+// (A y)_i for the three block rows at node i:
+//   w0 = M mu + (-(1+r) M + 2K + N) psi + K omega
+//   w1 = t K mu + s M psi
+//   w2 = K psi + M omega
+template <typename YF>
+__device__ __forceinline__ void block_row(const InstDev& I, int sl, int lane, double t, double s, YF y,
+                                          double& w0, double& w1, double& w2) {
+  const int base = I.m.slice_ptr[sl];
+  const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
+  const double c1 = -(1.0 + I.r);
+  w0 = w1 = w2 = 0.0;
+  for (int k = 0; k < w; ++k) {
+    const long long e = (long long)base + k * 64 + lane;
+    const int j = I.m.col[e];
+    const double Mv = I.m.M[e], Kv = I.m.K[e], Nv = I.N[e];
+    double mu, ps, om;
+    y(j, mu, ps, om);
+    w0 += Mv * mu + (c1 * Mv + 2.0 * Kv + Nv) * ps + Kv * om;
+    w1 += t * Kv * mu + s * Mv * ps;
+    w2 += Kv * ps + Mv * om;
+  }
+}
+
+template <typename T>
+__device__ double2 ph_aspmv(const InstDev& I, const State& S, const Team& tm) {
+  const int n = I.n;
+  const long long n3 = 3LL * n;
+  double* Zj = I.Z + (long long)S.j * n3;
+  const T* x2 = (const T*)I.x2;
+  const double* V0 = I.V;
+  double a0 = 0.0, a1 = 0.0;
+  PFC_SLICES(I, tm) {
+    const int i = sl * 64 + tm.lane;
+    double w0, w1, w2;
+    block_row(I, sl, tm.lane, I.tau_s, 1.0,
+              [&](int j, double& mu, double& ps, double& om) { mu = Zj[j]; ps = Zj[n + j]; om = (double)x2[j]; },
+              w0, w1, w2);
+    if (i < n) {
+      I.W[i] = w0; I.W[n + i] = w1; I.W[2 * n + i] = w2;
+      Zj[2 * n + i] = (double)x2[i];
+      a0 += w0 * V0[i] + w1 * V0[n + i] + w2 * V0[2 * n + i];
+      a1 += w0 * w0 + w1 * w1 + w2 * w2;
+    }
+  }
+  return make_double2(a0, a1);
+}
+
+__device__ double2 ph_mgs(const InstDev& I, const State& S, const Team& tm, bool last) {
+  const int n = I.n;
+  const long long n3 = 3LL * n;
+  const int ip = last ? S.j : S.mgs_i - 1;
+  const double* vp = I.V + (long long)ip * n3;
+  const double* vi = I.V + (long long)(last ? 0 : S.mgs_i) * n3;
+  const double h = S.hprev;
+  double a0 = 0.0;
+  PFC_SLICES(I, tm) {
+    const int i = sl * 64 + tm.lane;
+    if (i < n) {
+      for (int blk = 0; blk < 3; ++blk) {
+        const long long o = (long long)blk * n + i;
+        const double w = I.W[o] - h * vp[o];
+        I.W[o] = w;
+        a0 += last ? w * w : w * vi[o];
+      }
+    }
+  }
+  return make_double2(a0, 0.0);
+}
+
+__device__ double2 ph_update_x(const InstDev& I, const State& S, const Team& tm, const double* y) {
+  const int n = I.n;
+  const long long n3 = 3LL * n;
+  double* X = (S.job == JOB_RB) ? (I.ys + (long long)(S.stage - 1) * n3) : I.x_user;
+  const int kc = S.kcols;
+  PFC_SLICES(I, tm) {
+    const int i = sl * 64 + tm.lane;
+    if (i < n) {
+      for (int blk = 0; blk < 3; ++blk) {
+        const long long o = (long long)blk * n + i;
+        double x = X[o];
+        for (int l = 0; l < kc; ++l) x += y[l] * I.Z[(long long)l * n3 + o];
+        X[o] = x;
+      }
+    }
+  }
+  return make_double2(0.0, 0.0);
+}
+
+__device__ double2 ph_true_res(const InstDev& I, const State& S, const Team& tm) {
+  const int n = I.n;
+  const long long n3 = 3LL * n;
+  const bool rb = (S.job == JOB_RB);
+  const double* X = rb ? (I.ys + (long long)(S.stage - 1) * n3) : I.x_user;
+  const double* bsrc = rb ? I.b : I.b_user;
+  const double im = 1.0 / I.m11;
+  double a0 = 0.0, a1 = 0.0;
+  PFC_SLICES(I, tm) {
+    const int i = sl * 64 + tm.lane;
+    double w0, w1, w2;
+    block_row(I, sl, tm.lane, I.tau, I.m11,
+              [&](int j, double& mu, double& ps, double& om) { mu = X[j]; ps = X[n + j]; om = X[2 * n + j]; },
+              w0, w1, w2);
+    if (i < n) {
+      const double r0 = bsrc[i] - w0, r1 = bsrc[n + i] - w1, r2 = bsrc[2 * n + i] - w2;
+      const double rs1 = r1 * im;
+      I.W[i] = r0; I.W[n + i] = rs1; I.W[2 * n + i] = r2;
+      a0 += r0 * r0 + r1 * r1 + r2 * r2;
+      a1 += r0 * r0 + rs1 * rs1 + r2 * r2;
+    }
+  }
+  return make_double2(a0, a1);
+}
+
+template <typename T>
+__device__ double2 ph_pch_out(const InstDev& I, const Team& tm) {
+  const int n = I.n;
+  const T* x2 = (const T*)I.x2;
+  PFC_SLICES(I, tm) {
+    const int i = sl * 64 + tm.lane;
+    if (i < n) {
+      I.pch_out[i] = I.Z[i];
+      I.pch_out[n + i] = I.Z[n + i];
+      I.pch_out[2 * n + i] = (double)x2[i];
+    }
+  }
+  return make_double2(0.0, 0.0);
+}
+
+}  // namespace pfc

@@ -1,0 +1,148 @@
+// Internal layout of meshes, instances and the solver state machine.
+//
+// Device data layout (all arrays in HBM, 256-byte aligned):
+//   * the shared P1 pattern of M, K, N is stored as SELL-64: rows are grouped
+//     in slices of 64 consecutive rows (one wavefront), each slice padded to
+//     its longest row and stored column-major, so entry k of the rows of a
+//     slice is one coalesced 64-lane access.  Padded entries of real rows
+//     point at the row itself with value 0; rows >= n point at row 0.
+//   * value arrays (M, K, N, M + delta K, M + sqrt(delta) K) share that layout;
+//   * vectors of the 3x3 block system are [mu | psi | omega], n each.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PFC_WG 256
+#define PFC_WAVES 4
+#define PFC_SLICE 64
+#define PFC_MAXM 32
+#define PFC_NSTEPS_P 5
+
+// Solver phases.  A phase is the work done by one launch of the solver
+// kernel for one instance; the next phase is chosen from the reductions of
+// the previous one at the start of the following launch.
+enum {
+  PH_DONE = 0,
+  PH_START,       // job just submitted; no work
+  PH_SOLVE_INIT,  // W = b_scaled, X = 0, partials ||b||^2, ||b_s||^2
+  PH_RB_BEGIN,    // N(psi_k) reassembled in place
+  PH_RB_RHS,      // stage right-hand side b_i, then as SOLVE_INIT
+  PH_RB_UPDATE,   // x_{k+1} = x_k + sum m_j y_j
+  PH_PCG_SETUP,   // right-hand side of inner solve `kind`, r = rhs, x = 0
+  PH_PCG_A,       // p = D^{-1} r + beta p_old, q = C p, partial (p, q)
+  PH_PCG_B,       // x += alpha p, r -= alpha q, partials (r, r), (r, D^{-1} r)
+  PH_ASPMV,       // w = A_s z_j, partials (w, v_0), (w, w)
+  PH_MGS,         // w -= h_{i-1} v_{i-1}, partial (w, v_i)
+  PH_MGS_LAST,    // w -= h_j v_j, partial (w, w)
+  PH_UPDATE_X,    // x += Z y
+  PH_TRUE_RES,    // r = b - A^R x, partials ||r||^2, ||r_s||^2; W = r_s
+  PH_PCH_OUT,     // z_out = P_CH^{-1} v (preconditioner-only job)
+};
+
+enum { JOB_NONE = 0, JOB_SOLVE = 1, JOB_RB = 2, JOB_PCH = 3 };
+
+// inner solve kinds: steps (1), (2), (3.1), (3.2), (5) of the P_CH apply,
+// then the two mass solves of the consistent initial values
+enum { KIND_Y0 = 0, KIND_Y1 = 1, KIND_Z = 2, KIND_X1 = 3, KIND_X2 = 4, KIND_CI_OMEGA = 5, KIND_CI_MU = 6 };
+
+struct MeshDev {
+  int n, dim, n_slices, n_elem;
+  long long nnz_sell;
+  const int* slice_ptr;   // [n_slices+1] entry offset of each slice (multiple of 64)
+  const int* col;         // [nnz_sell]
+  const double* M;        // [nnz_sell]
+  const double* K;
+  const float* Mf;
+  const float* Kf;
+  const double* dinvM;    // [n] 1/diag(M)
+  const float* dinvMf;
+  const int* sl_el_ptr;   // [nnz_sell+1] element contributions of each stored entry
+  const int* sl_el;       // packed (elem << 4) | (a << 2) | b
+  const int* nd_el_ptr;   // [n+1] simplices containing each node
+  const int* nd_el;       // packed (elem << 2) | local index
+  const int* elem_nodes;  // [n_elem*(dim+1)]
+  const double* elem_vol; // [n_elem]
+};
+
+// Double-buffered scalar state of one instance (written by workgroup 0 of its
+// team at the end of every launch into the other buffer).
+struct State {
+  int phase;
+  int job;
+  int step, stage;          // Rosenbrock position
+  int kind, it, pcur, pad0; // inner PCG
+  int j, mgs_i, cycle, total, apply, kcols;
+  int status, pad1;
+  double rho, bb, alpha, beta_cg;
+  double vscale, bnorm, bnorm_s, est_thresh, w0, hprev, est, rel;
+};
+
+// Single-buffered FGMRES history of the current cycle.  Every entry is
+// written once per cycle, by workgroup 0, in a launch after which it is read.
+struct Hist {
+  double hcol[PFC_MAXM + 1];
+  double cs[PFC_MAXM];
+  double sn[PFC_MAXM];
+  double gpre[PFC_MAXM + 1];
+  double gfin[PFC_MAXM];
+  double R[PFC_MAXM][PFC_MAXM];   // R[l][c], l <= c
+  int inner_max[PFC_NSTEPS_P];
+  int applies;
+  long long inner_total;
+};
+
+struct InfoDev {
+  int status, outer_iters, cycles, inner_applies;
+  long long inner_total;
+  int inner_max[5];
+  int reserved;
+  double est_rel_res, true_rel_res;
+};
+
+struct InstDev {
+  MeshDev m;
+  int n, precision, restart, max_steps;
+  int inner_maxit, shared_ops, team_size, replay;
+  double outer_tol, inner_tol, ci_tol;
+  // job parameters
+  double r, tau, m11, tau_s, delta, sdelta;
+  int job, n_steps, init_mode, max_infos;
+  // typed operator arrays (float or double by precision)
+  void* Cd; void* Csd; void* dinvCd; void* dinvCsd;
+  double* N;                    // [nnz_sell]
+  // float64 vectors
+  const double* b_user;         // solve job rhs
+  double* x_user;               // solve job solution
+  double* b;                    // [3n] stage rhs
+  double* xk;                   // [3n] Rosenbrock state
+  double* ys;                   // [3][3n] stage solutions
+  double* V;                    // [(restart+1)][3n]
+  double* Z;                    // [restart][3n]
+  double* W;                    // [3n]
+  double* pch_out;              // preconditioner-only job output
+  // inner PCG vectors (sized for float64; typed by precision)
+  void *r_, *pA, *pB, *q, *y0, *y1, *zt, *x1, *x2;
+  double2* part;                // [2][team_size]
+  State* st;                    // [2]
+  Hist* hist;
+  const int* sched_meta;        // replay: per solve {cycle offset, cycles, apply offset, applies}
+  const int* sched_cycles;      // replay: cycle lengths
+  const int* sched_inner;       // replay: 5 counts per application
+  int n_sched_cycles, n_sched_applies;
+  int* rec_inner;               // [max_steps * 5] counts of the last solve
+  InfoDev* info;                // [max_infos]
+};
+
+struct TeamEntry { int inst, rank, size, pad; };
+
+// Rosenbrock coefficients of Table rosenbrock_scheme (Ros3Pw, modified form).
+#define ROS_GAMMA 0.78867513459481287
+#define ROS_A21 2.0
+#define ROS_A31 0.633974596215561
+#define ROS_A32 0.0
+#define ROS_C21 (-2.53589838486225)
+#define ROS_C31 (-1.62740473580836)
+#define ROS_C32 (-0.274519052838329)
+#define ROS_M1 1.63397459621556
+#define ROS_M2 0.294228634059948
+#define ROS_M3 1.07179676972449

@@ -1,0 +1,974 @@
+// The stage solver as a device-resident state machine.
+//
+// One launch of k_tick advances every active instance by one phase (see
+// pfc_internal.h).  A launch first sums the partial reductions that the
+// previous launch left behind (every workgroup of a team does this
+// redundantly, in fixed order, so all of them take identical decisions), then
+// thread 0 of each workgroup applies the transition to a copy of the state in
+// LDS, the workgroup executes the work of the new phase, stores its partial
+// sums and workgroup 0 of the team writes the new state.  Kernel boundaries
+// are the only synchronisation between workgroups: no grid barriers, no
+// atomics.  The host captures a fixed number of launches in a graph, replays
+// it, and polls a pinned flag written by a small report kernel at the end of
+// each replay.
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "host.h"
+#include "solver.h"
+
+namespace pfc {
+
+__device__ __forceinline__ bool phase_partials(int ph) {
+  switch (ph) {
+    case PH_SOLVE_INIT: case PH_RB_RHS: case PH_PCG_SETUP: case PH_PCG_A: case PH_PCG_B:
+    case PH_ASPMV: case PH_MGS: case PH_MGS_LAST: case PH_TRUE_RES:
+      return true;
+    default:
+      return false;
+  }
+}
+
+__device__ __forceinline__ int solve_index(const State& S) { return S.job == JOB_RB ? S.step * 3 + S.stage - 1 : 0; }
+
+__device__ __forceinline__ int inner_limit(const InstDev& I, const State& S, bool& fixed, double& tol) {
+  if (S.kind >= KIND_CI_OMEGA) { fixed = false; tol = I.ci_tol; return 2000; }
+  tol = I.inner_tol;
+  if (I.replay) {
+    fixed = true;
+    const int idx = solve_index(S);
+    const int* meta = I.sched_meta + 4 * idx;
+    if (S.apply >= meta[3]) return 0;
+    return I.sched_inner[(long long)(meta[2] + S.apply) * 5 + S.kind];
+  }
+  fixed = false;
+  return I.inner_maxit;
+}
+
+__device__ void finish_solve(State& S, const InstDev& I, bool wr, int status) {
+  if (wr) {
+    const int idx = solve_index(S);
+    if (idx < I.max_infos) {
+      InfoDev& f = I.info[idx];
+      f.status = status;
+      f.outer_iters = S.total;
+      f.cycles = S.cycle;
+      f.inner_applies = I.hist->applies;
+      f.inner_total = I.hist->inner_total;
+      for (int k = 0; k < 5; ++k) f.inner_max[k] = I.hist->inner_max[k];
+      f.est_rel_res = S.est;
+      f.true_rel_res = S.rel;
+    }
+  }
+  if (status < 0) S.status = status;
+  else if (status > S.status && S.status >= 0) S.status = status;
+  if (S.job == JOB_RB && status >= 0) {
+    if (S.stage < 3) { S.stage += 1; S.phase = PH_RB_RHS; }
+    else S.phase = PH_RB_UPDATE;
+  } else {
+    S.phase = PH_DONE;
+  }
+}
+
+__device__ void begin_solve(State& S, const InstDev& I, bool wr, double2 red) {
+  S.bnorm = sqrt(red.x);
+  S.bnorm_s = sqrt(red.y);
+  S.total = 0; S.cycle = 0; S.j = 0; S.apply = 0; S.est = 0.0; S.rel = 0.0;
+  if (wr) {
+    I.hist->applies = 0;
+    I.hist->inner_total = 0;
+    for (int k = 0; k < 5; ++k) I.hist->inner_max[k] = 0;
+  }
+  if (!isfinite(S.bnorm)) { finish_solve(S, I, wr, PFC_ERR_BREAKDOWN); return; }
+  if (S.bnorm == 0.0) { finish_solve(S, I, wr, PFC_OK); return; }
+  if (I.replay && I.sched_meta[4 * solve_index(S) + 1] == 0) { finish_solve(S, I, wr, PFC_OK); return; }
+  S.est_thresh = I.outer_tol * S.bnorm / fmax(1.0, I.m11);
+  if (wr) I.hist->gpre[0] = S.bnorm_s;
+  S.vscale = 1.0 / S.bnorm_s;
+  S.kind = KIND_Y0;
+  S.phase = PH_PCG_SETUP;
+}
+
+__device__ void pcg_done(State& S, const InstDev& I, bool wr) {
+  if (S.kind <= KIND_X2 && wr) {
+    if (S.apply < I.max_steps) I.rec_inner[S.apply * 5 + S.kind] = S.it;
+    I.hist->inner_total += S.it;
+    if (S.it > I.hist->inner_max[S.kind]) I.hist->inner_max[S.kind] = S.it;
+  }
+  switch (S.kind) {
+    case KIND_Y0: case KIND_Y1: case KIND_Z: case KIND_X1:
+      S.kind += 1;
+      S.phase = PH_PCG_SETUP;
+      break;
+    case KIND_X2:
+      if (wr) I.hist->applies += 1;
+      S.apply += 1;
+      S.phase = (S.job == JOB_PCH) ? PH_PCH_OUT : PH_ASPMV;
+      break;
+    case KIND_CI_OMEGA:
+      S.kind = KIND_CI_MU;
+      S.phase = PH_PCG_SETUP;
+      break;
+    default:  // KIND_CI_MU: consistent initial values done
+      S.step = 0;
+      S.phase = (I.n_steps > 0) ? PH_RB_BEGIN : PH_DONE;
+      break;
+  }
+}
+
+__device__ void restart_cycle(State& S, const InstDev& I, bool wr, double beta) {
+  if (!(beta > 0.0)) { finish_solve(S, I, wr, PFC_OK); return; }
+  if (wr) I.hist->gpre[0] = beta;
+  S.j = 0;
+  S.vscale = 1.0 / beta;
+  S.kind = KIND_Y0;
+  S.phase = PH_PCG_SETUP;
+}
+
+// Givens rotation of column j, cycle control, back substitution.
+__device__ void givens(State& S, const InstDev& I, bool wr, double hn2, double* ybuf, double* col) {
+  Hist* H = I.hist;
+  const int j = S.j;
+  const double hn = sqrt(hn2);
+  for (int l = 0; l <= j; ++l) col[l] = H->hcol[l];
+  col[j + 1] = hn;
+  for (int l = 0; l < j; ++l) {
+    const double c = H->cs[l], s = H->sn[l];
+    const double t = c * col[l] + s * col[l + 1];
+    col[l + 1] = -s * col[l] + c * col[l + 1];
+    col[l] = t;
+  }
+  const double d = hypot(col[j], col[j + 1]);
+  double cj = 1.0, sj = 0.0;
+  if (d != 0.0) { cj = col[j] / d; sj = col[j + 1] / d; }
+  col[j] = d;
+  const double gj = H->gpre[j];
+  const double gfin = cj * gj;
+  const double gnext = -sj * gj;
+  if (wr) {
+    H->cs[j] = cj; H->sn[j] = sj; H->gfin[j] = gfin; H->gpre[j + 1] = gnext;
+    for (int l = 0; l <= j; ++l) H->R[l][j] = col[l];
+  }
+  S.total += 1;
+  S.est = fabs(gnext) / S.bnorm_s;
+  const bool breakdown = hn <= 1e-14 * S.w0;
+  bool done;
+  if (I.replay) {
+    const int* meta = I.sched_meta + 4 * solve_index(S);
+    done = (j + 1 >= I.sched_cycles[meta[0] + S.cycle]);
+  } else {
+    done = fabs(gnext) <= S.est_thresh || breakdown || S.total >= I.max_steps || j + 1 == I.restart;
+  }
+  if (!done) {
+    S.vscale = 1.0 / hn;
+    S.j = j + 1;
+    S.kind = KIND_Y0;
+    S.phase = PH_PCG_SETUP;
+    return;
+  }
+  const int k = j + 1;
+  for (int l = k - 1; l >= 0; --l) {
+    double s = (l == j) ? gfin : H->gfin[l];
+    for (int c = l + 1; c < k; ++c) s -= ((c == j) ? col[l] : H->R[l][c]) * ybuf[c];
+    ybuf[l] = s / ((l == j) ? col[l] : H->R[l][l]);
+  }
+  S.kcols = k;
+  S.phase = PH_UPDATE_X;
+}
+
+__device__ void transition(State& S, const InstDev& I, bool wr, double2 red, double* ybuf, double* col) {
+  switch (S.phase) {
+    case PH_START:
+      if (S.job == JOB_SOLVE) S.phase = PH_SOLVE_INIT;
+      else if (S.job == JOB_PCH) {
+        S.j = 0; S.vscale = 1.0; S.kind = KIND_Y0; S.apply = 0; S.phase = PH_PCG_SETUP;
+        if (wr) { I.hist->applies = 0; I.hist->inner_total = 0; for (int k = 0; k < 5; ++k) I.hist->inner_max[k] = 0; }
+      } else {  // JOB_RB
+        S.step = 0;
+        if (I.init_mode == PFC_INIT_CONSISTENT) { S.kind = KIND_CI_OMEGA; S.phase = PH_PCG_SETUP; }
+        else S.phase = (I.n_steps > 0) ? PH_RB_BEGIN : PH_DONE;
+      }
+      break;
+    case PH_SOLVE_INIT:
+    case PH_RB_RHS:
+      begin_solve(S, I, wr, red);
+      break;
+    case PH_RB_BEGIN:
+      S.stage = 1;
+      S.phase = PH_RB_RHS;
+      break;
+    case PH_RB_UPDATE:
+      S.step += 1;
+      S.phase = (S.step < I.n_steps) ? PH_RB_BEGIN : PH_DONE;
+      break;
+    case PH_PCG_SETUP: {
+      S.rho = red.x; S.bb = red.y; S.it = 0; S.pcur = 0; S.beta_cg = 0.0;
+      bool fixed; double tol;
+      const int lim = inner_limit(I, S, fixed, tol);
+      if (S.bb == 0.0 || lim == 0) pcg_done(S, I, wr);
+      else S.phase = PH_PCG_A;
+    } break;
+    case PH_PCG_A:
+      S.alpha = S.rho / red.x;
+      S.pcur ^= 1;
+      S.phase = PH_PCG_B;
+      break;
+    case PH_PCG_B: {
+      S.it += 1;
+      bool fixed; double tol;
+      const int lim = inner_limit(I, S, fixed, tol);
+      const double rr = red.x, rzn = red.y;
+      const bool done = S.it >= lim || (!fixed && rr <= tol * tol * S.bb) || rzn == 0.0 || !isfinite(rr);
+      if (done) pcg_done(S, I, wr);
+      else { S.beta_cg = rzn / S.rho; S.rho = rzn; S.phase = PH_PCG_A; }
+    } break;
+    case PH_ASPMV:
+      S.w0 = sqrt(red.y);
+      S.hprev = red.x;
+      if (wr) I.hist->hcol[0] = red.x;
+      if (S.j == 0) S.phase = PH_MGS_LAST;
+      else { S.mgs_i = 1; S.phase = PH_MGS; }
+      break;
+    case PH_MGS:
+      S.hprev = red.x;
+      if (wr) I.hist->hcol[S.mgs_i] = red.x;
+      if (S.mgs_i == S.j) S.phase = PH_MGS_LAST;
+      else { S.mgs_i += 1; S.phase = PH_MGS; }
+      break;
+    case PH_MGS_LAST:
+      givens(S, I, wr, red.x, ybuf, col);
+      break;
+    case PH_UPDATE_X:
+      S.phase = PH_TRUE_RES;
+      break;
+    case PH_TRUE_RES: {
+      const double rel = sqrt(red.x) / S.bnorm;
+      S.rel = rel;
+      S.cycle += 1;
+      if (!isfinite(rel)) { finish_solve(S, I, wr, PFC_ERR_BREAKDOWN); break; }
+      if (I.replay) {
+        const int* meta = I.sched_meta + 4 * solve_index(S);
+        if (S.cycle < meta[1]) restart_cycle(S, I, wr, sqrt(red.y));
+        else finish_solve(S, I, wr, rel <= I.outer_tol ? PFC_OK : PFC_NOT_CONVERGED);
+      } else if (rel <= I.outer_tol) {
+        finish_solve(S, I, wr, PFC_OK);
+      } else if (S.total >= I.max_steps) {
+        finish_solve(S, I, wr, PFC_NOT_CONVERGED);
+      } else {
+        restart_cycle(S, I, wr, sqrt(red.y));
+      }
+    } break;
+    case PH_PCH_OUT:
+      S.phase = PH_DONE;
+      break;
+    default:
+      S.phase = PH_DONE;
+      break;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ teams, const InstDev* __restrict__ insts,
+                                                 int parity) {
+  __shared__ State S;
+  __shared__ double2 lds4[PFC_WAVES];
+  __shared__ double ybuf[PFC_MAXM];
+  __shared__ double gcol[PFC_MAXM + 1];
+  const TeamEntry te = teams[blockIdx.x];
+  const InstDev& I = insts[te.inst];
+  const int tid = threadIdx.x;
+  {
+    const int* src = (const int*)(I.st + parity);
+    int* dst = (int*)&S;
+    for (int k = tid; k < (int)(sizeof(State) / 4); k += PFC_WG) dst[k] = src[k];
+  }
+  __syncthreads();
+  const bool writer = (te.rank == 0);
+  if (S.phase == PH_DONE) {
+    if (writer) {
+      int* dst = (int*)(I.st + (1 - parity));
+      const int* src = (const int*)&S;
+      for (int k = tid; k < (int)(sizeof(State) / 4); k += PFC_WG) dst[k] = src[k];
+    }
+    return;
+  }
+  double2 red = make_double2(0.0, 0.0);
+  if (phase_partials(S.phase)) {
+    const double2* part = I.part + (long long)parity * I.team_size;
+    double a = 0.0, b = 0.0;
+    for (int k = tid; k < te.size; k += PFC_WG) { a += part[k].x; b += part[k].y; }
+    red = wg_sum2(a, b, lds4);
+  }
+  if (tid == 0) transition(S, I, writer, red, ybuf, gcol);
+  __syncthreads();
+  Team tm{te.rank, te.size, tid >> 6, tid & 63};
+  double2 acc = make_double2(0.0, 0.0);
+  switch (S.phase) {
+    case PH_SOLVE_INIT:
+    case PH_RB_RHS: acc = ph_solve_init(I, S, tm); break;
+    case PH_RB_BEGIN: acc = ph_rb_begin(I, tm); break;
+    case PH_RB_UPDATE: acc = ph_rb_update(I, tm); break;
+    // the mass solves of the consistent initial values run in float64 in every precision
+    case PH_PCG_SETUP: acc = S.kind >= KIND_CI_OMEGA ? ph_pcg_setup<double>(I, S, tm) : ph_pcg_setup<T>(I, S, tm); break;
+    case PH_PCG_A: acc = S.kind >= KIND_CI_OMEGA ? ph_pcg_a<double>(I, S, tm) : ph_pcg_a<T>(I, S, tm); break;
+    case PH_PCG_B: acc = S.kind >= KIND_CI_OMEGA ? ph_pcg_b<double>(I, S, tm) : ph_pcg_b<T>(I, S, tm); break;
+    case PH_ASPMV: acc = ph_aspmv<T>(I, S, tm); break;
+    case PH_MGS: acc = ph_mgs(I, S, tm, false); break;
+    case PH_MGS_LAST: acc = ph_mgs(I, S, tm, true); break;
+    case PH_UPDATE_X: acc = ph_update_x(I, S, tm, ybuf); break;
+    case PH_TRUE_RES: acc = ph_true_res(I, S, tm); break;
+    case PH_PCH_OUT: acc = ph_pch_out<T>(I, tm); break;
+    default: break;
+  }
+  if (phase_partials(S.phase)) {
+    const double2 s = wg_sum2(acc.x, acc.y, lds4);
+    if (tid == 0) I.part[(long long)(1 - parity) * I.team_size + te.rank] = s;
+  }
+  if (writer) {
+    int* dst = (int*)(I.st + (1 - parity));
+    const int* src = (const int*)&S;
+    for (int k = tid; k < (int)(sizeof(State) / 4); k += PFC_WG) dst[k] = src[k];
+  }
+}
+
+__global__ void k_report(const InstDev* __restrict__ insts, int count, int* __restrict__ flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) flags[i] = insts[i].st[0].phase;
+}
+
+// Per-tau operator values: C_d = M + delta K, C_sd = M + sqrt(delta) K (stored
+// unless shared_ops) and their Jacobi diagonals, in the inner precision.
+template <typename T>
+__global__ void k_prep_ops(InstDev I) {
+  const int sl = blockIdx.x * PFC_WAVES + (threadIdx.x >> 6);
+  if (sl >= I.m.n_slices) return;
+  const int lane = threadIdx.x & 63;
+  const int i = sl * 64 + lane;
+  const int base = I.m.slice_ptr[sl];
+  const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
+  double dd = 0.0, ds = 0.0;
+  for (int k = 0; k < w; ++k) {
+    const long long e = (long long)base + k * 64 + lane;
+    const double cd = I.m.M[e] + I.delta * I.m.K[e];
+    const double cs = I.m.M[e] + I.sdelta * I.m.K[e];
+    if (!I.shared_ops) {
+      ((T*)I.Cd)[e] = T(cd);
+      ((T*)I.Csd)[e] = T(cs);
+    }
+    if (I.m.col[e] == i) { dd += cd; ds += cs; }
+  }
+  if (i < I.n) {
+    ((T*)I.dinvCd)[i] = T(1.0 / dd);
+    ((T*)I.dinvCsd)[i] = T(1.0 / ds);
+  }
+}
+
+__global__ void k_assemble_N_sell(InstDev I, const double* __restrict__ psi) {
+  const int sl = blockIdx.x * PFC_WAVES + (threadIdx.x >> 6);
+  if (sl >= I.m.n_slices) return;
+  const int lane = threadIdx.x & 63;
+  const int base = I.m.slice_ptr[sl];
+  const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
+  for (int k = 0; k < w; ++k) {
+    const long long e = (long long)base + k * 64 + lane;
+    I.N[e] = -3.0 * entry_Mpsi2(I.m, e, [&](int j) { return psi[j]; });
+  }
+}
+
+__global__ void k_apply_AR(InstDev I, const double* __restrict__ y, double* __restrict__ out) {
+  const int sl = blockIdx.x * PFC_WAVES + (threadIdx.x >> 6);
+  if (sl >= I.m.n_slices) return;
+  const int lane = threadIdx.x & 63;
+  const int i = sl * 64 + lane;
+  const int n = I.n;
+  double w0, w1, w2;
+  block_row(I, sl, lane, I.tau, I.m11,
+            [&](int j, double& mu, double& ps, double& om) { mu = y[j]; ps = y[n + j]; om = y[2 * n + j]; }, w0, w1, w2);
+  if (i < n) { out[i] = w0; out[n + i] = w1; out[2 * n + i] = w2; }
+}
+
+__global__ void k_stage_rhs(InstDev I, int stage, double* __restrict__ b) {
+  const int sl = blockIdx.x * PFC_WAVES + (threadIdx.x >> 6);
+  if (sl >= I.m.n_slices) return;
+  const int lane = threadIdx.x & 63;
+  const int i = sl * 64 + lane;
+  double b0, b1, b2;
+  stage_rhs_row(I, sl, lane, stage, b0, b1, b2);
+  if (i < I.n) { b[i] = b0; b[I.n + i] = b1; b[2 * I.n + i] = b2; }
+}
+
+// ---- host side ------------------------------------------------------------------
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Carve the instance arena.  With base == nullptr only the size is computed.
+size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int team_size) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
+  const size_t n = (size_t)m->n, n3 = 3 * n, ns = (size_t)m->nnz_sell;
+  const size_t w = o.precision == PFC_MIXED ? 4 : 8;
+  const int mr = o.restart;
+  h.Cd = o.shared_ops ? nullptr : (void*)take(ns * w);
+  h.Csd = o.shared_ops ? nullptr : (void*)take(ns * w);
+  h.dinvCd = take(n * w);
+  h.dinvCsd = take(n * w);
+  h.N = (double*)take(ns * 8);
+  h.b = (double*)take(n3 * 8);
+  h.xk = (double*)take(n3 * 8);
+  h.ys = (double*)take(3 * n3 * 8);
+  h.V = (double*)take((size_t)(mr + 1) * n3 * 8);
+  h.Z = (double*)take((size_t)mr * n3 * 8);
+  h.W = (double*)take(n3 * 8);
+  h.r_ = take(n * 8); h.pA = take(n * 8); h.pB = take(n * 8); h.q = take(n * 8);
+  h.y0 = take(n * 8); h.y1 = take(n * 8); h.zt = take(n * 8); h.x1 = take(n * 8); h.x2 = take(n * 8);
+  h.part = (double2*)take(2 * (size_t)team_size * sizeof(double2));
+  h.st = (State*)take(2 * sizeof(State));
+  h.hist = (Hist*)take(sizeof(Hist));
+  h.rec_inner = (int*)take((size_t)o.max_steps * 5 * sizeof(int));
+  h.info = (InfoDev*)take((size_t)3 * o.max_run_steps * sizeof(InfoDev));
+  h.max_infos = 3 * o.max_run_steps;
+  return off;
+}
+
+int team_size_for(int n_slices, int rows_per_thread) {
+  int rpt = rows_per_thread;
+  if (rpt <= 0) rpt = n_slices >= 2048 ? 2 : 1;
+  return (n_slices + PFC_WAVES * rpt - 1) / (PFC_WAVES * rpt);
+}
+
+static int validate_opts(const pfc_opts* o) {
+  if (!o || o->struct_size != (int)sizeof(pfc_opts)) { set_error("pfc_opts: struct_size mismatch"); return PFC_ERR_ARG; }
+  if (o->precision != PFC_FP64 && o->precision != PFC_MIXED) { set_error("pfc_opts: bad precision"); return PFC_ERR_ARG; }
+  if (o->restart < 1 || o->restart > PFC_MAXM) { set_error("pfc_opts: restart must be in 1..32"); return PFC_ERR_ARG; }
+  if (o->max_steps < 1 || o->inner_maxit < 1 || o->max_run_steps < 1) { set_error("pfc_opts: counts must be positive"); return PFC_ERR_ARG; }
+  if (!(o->outer_tol > 0.0) || !(o->inner_tol > 0.0) || !(o->inner_tol < 1.0)) { set_error("pfc_opts: tolerances must be in (0,1)"); return PFC_ERR_ARG; }
+  if (o->rows_per_thread < 0 || o->rows_per_thread > 8) { set_error("pfc_opts: rows_per_thread must be 0..8"); return PFC_ERR_ARG; }
+  if (o->ticks_per_graph < 0 || o->ticks_per_graph > 4096) { set_error("pfc_opts: ticks_per_graph must be 0..4096"); return PFC_ERR_ARG; }
+  return PFC_OK;
+}
+
+static void fill_info(pfc_solve_info* dst, const InfoDev& s) {
+  dst->status = s.status;
+  dst->outer_iters = s.outer_iters;
+  dst->cycles = s.cycles;
+  dst->inner_applies = s.inner_applies;
+  dst->inner_total = s.inner_total;
+  for (int k = 0; k < 5; ++k) dst->inner_max[k] = s.inner_max[k];
+  dst->reserved = 0;
+  dst->est_rel_res = s.est_rel_res;
+  dst->true_rel_res = s.true_rel_res;
+}
+
+int Group::build(hipStream_t capture, int precision, int ticks) {
+  graph_ticks = ticks;
+  PFC_HIP(hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal));
+  for (int t = 0; t < ticks; ++t) {
+    if (precision == PFC_MIXED)
+      hipLaunchKernelGGL(k_tick<float>, dim3(n_wg), dim3(PFC_WG), 0, capture, d_teams, d_descs, t & 1);
+    else
+      hipLaunchKernelGGL(k_tick<double>, dim3(n_wg), dim3(PFC_WG), 0, capture, d_teams, d_descs, t & 1);
+  }
+  hipLaunchKernelGGL(k_report, dim3((count + 255) / 256), dim3(256), 0, capture, d_descs, count, d_flags);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(capture, &g);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  return PFC_OK;
+}
+
+int Group::alloc(const std::vector<int>& team_sizes) {
+  count = (int)team_sizes.size();
+  std::vector<TeamEntry> tes;
+  for (int i = 0; i < count; ++i)
+    for (int r = 0; r < team_sizes[i]; ++r) tes.push_back(TeamEntry{i, r, team_sizes[i], 0});
+  n_wg = (int)tes.size();
+  PFC_HIP(hipMalloc((void**)&d_teams, sizeof(TeamEntry) * tes.size()));
+  PFC_HIP(hipMemcpy(d_teams, tes.data(), sizeof(TeamEntry) * tes.size(), hipMemcpyHostToDevice));
+  PFC_HIP(hipMalloc((void**)&d_descs, sizeof(InstDev) * count));
+  PFC_HIP(hipHostMalloc((void**)&h_descs, sizeof(InstDev) * count, hipHostMallocDefault));
+  PFC_HIP(hipHostMalloc((void**)&h_states, sizeof(State) * count, hipHostMallocDefault));
+  PFC_HIP(hipHostMalloc((void**)&h_flags, sizeof(int) * count, hipHostMallocMapped));
+  PFC_HIP(hipHostGetDevicePointer((void**)&d_flags, h_flags, 0));
+  for (int i = 0; i < count; ++i) h_flags[i] = -1;
+  PFC_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  PFC_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  return PFC_OK;
+}
+
+void Group::release() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (d_teams) (void)hipFree(d_teams);
+  if (d_descs) (void)hipFree(d_descs);
+  if (h_descs) (void)hipHostFree(h_descs);
+  if (h_states) (void)hipHostFree(h_states);
+  if (h_flags) (void)hipHostFree(h_flags);
+  if (ev[0]) (void)hipEventDestroy(ev[0]);
+  if (ev[1]) (void)hipEventDestroy(ev[1]);
+  *this = Group();
+}
+
+// Upload descriptors and initial states (stream ordered), then replay the
+// graph until every instance reports PH_DONE.
+int Group::run(hipStream_t s, const std::vector<State*>& dev_states, double timeout_s) {
+  PFC_HIP(hipMemcpyAsync(d_descs, h_descs, sizeof(InstDev) * count, hipMemcpyHostToDevice, s));
+  for (int i = 0; i < count; ++i)
+    PFC_HIP(hipMemcpyAsync(dev_states[i], h_states + i, sizeof(State), hipMemcpyHostToDevice, s));
+  const auto t0 = std::chrono::steady_clock::now();
+  PFC_HIP(hipGraphLaunch(exec, s));
+  PFC_HIP(hipEventRecord(ev[0], s));
+  PFC_HIP(hipGraphLaunch(exec, s));
+  PFC_HIP(hipEventRecord(ev[1], s));
+  long long k = 0;
+  for (;;) {
+    PFC_HIP(hipEventSynchronize(ev[k & 1]));
+    bool all = true;
+    for (int i = 0; i < count; ++i)
+      if (((volatile int*)h_flags)[i] != PH_DONE) { all = false; break; }
+    if (all) break;
+    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (el > timeout_s) {
+      (void)hipStreamSynchronize(s);
+      set_error("solver did not finish within the time limit");
+      return PFC_ERR_STATE;
+    }
+    PFC_HIP(hipGraphLaunch(exec, s));
+    PFC_HIP(hipEventRecord(ev[k & 1], s));
+    ++k;
+  }
+  graphs_run = k + 2;
+  PFC_HIP(hipStreamSynchronize(s));
+  return PFC_OK;
+}
+
+static int ensure_group(pfc_instance* I) {
+  if (I->grp.exec) return PFC_OK;
+  int rc = I->grp.alloc(std::vector<int>{I->team_size});
+  if (rc) return rc;
+  return I->grp.build(I->capture, I->opts.precision, I->ticks);
+}
+
+static int prep_ops(pfc_instance* I, hipStream_t s) {
+  const InstDev& h = I->h;
+  if (I->ops_tau_s == h.tau_s) return PFC_OK;
+  const int nb = slice_blocks(I->mesh->n_slices);
+  if (I->opts.precision == PFC_MIXED)
+    hipLaunchKernelGGL(k_prep_ops<float>, dim3(nb), dim3(PFC_WG), 0, s, h);
+  else
+    hipLaunchKernelGGL(k_prep_ops<double>, dim3(nb), dim3(PFC_WG), 0, s, h);
+  PFC_HIP(hipGetLastError());
+  I->ops_tau_s = h.tau_s;
+  return PFC_OK;
+}
+
+int prep_ops_public(pfc_instance* I, hipStream_t s) { return prep_ops(I, s); }
+
+void set_params(InstDev& h, double r, double tau, double m11) {
+  h.r = r; h.tau = tau; h.m11 = m11;
+  h.tau_s = tau / m11;
+  h.delta = std::sqrt(h.tau_s);
+  h.sdelta = std::sqrt(h.delta);
+}
+
+static State initial_state(int job) {
+  State s;
+  std::memset(&s, 0, sizeof(s));
+  s.phase = PH_START;
+  s.job = job;
+  return s;
+}
+
+// Replay schedules: uploaded into a growable device buffer of the instance.
+static int upload_schedules(pfc_instance* I, const pfc_schedule* sch, int count, hipStream_t s) {
+  std::vector<int> meta(4 * (size_t)count), cyc, inn;
+  for (int k = 0; k < count; ++k) {
+    const pfc_schedule& q = sch[k];
+    if (q.n_cycles < 0 || q.n_applies < 0 || (q.n_cycles && !q.cycle_len) || (q.n_applies && !q.inner_counts)) {
+      set_error("pfc_schedule: invalid schedule");
+      return PFC_ERR_ARG;
+    }
+    int steps = 0;
+    for (int c = 0; c < q.n_cycles; ++c) {
+      if (q.cycle_len[c] < 1 || q.cycle_len[c] > I->opts.restart) {
+        set_error("pfc_schedule: cycle length out of range");
+        return PFC_ERR_ARG;
+      }
+      steps += q.cycle_len[c];
+    }
+    if (steps != q.n_applies || steps > I->opts.max_steps) {
+      set_error("pfc_schedule: applications must equal the sum of cycle lengths and fit max_steps");
+      return PFC_ERR_ARG;
+    }
+    meta[4 * k + 0] = (int)cyc.size();
+    meta[4 * k + 1] = q.n_cycles;
+    meta[4 * k + 2] = (int)(inn.size() / 5);
+    meta[4 * k + 3] = q.n_applies;
+    cyc.insert(cyc.end(), q.cycle_len, q.cycle_len + q.n_cycles);
+    for (int a = 0; a < 5 * q.n_applies; ++a) {
+      if (q.inner_counts[a] < 0 || q.inner_counts[a] > 100000) { set_error("pfc_schedule: bad inner count"); return PFC_ERR_ARG; }
+      inn.push_back(q.inner_counts[a]);
+    }
+  }
+  if (cyc.empty()) cyc.push_back(0);
+  if (inn.empty()) inn.push_back(0);
+  const size_t need = sizeof(int) * (meta.size() + cyc.size() + inn.size()) + 1024;
+  if (need > I->sched_bytes) {
+    if (I->d_sched) (void)hipFree(I->d_sched);
+    I->d_sched = nullptr;
+    PFC_HIP(hipMalloc((void**)&I->d_sched, need));
+    I->sched_bytes = need;
+  }
+  PFC_HIP(hipStreamSynchronize(s));
+  int* p = I->d_sched;
+  PFC_HIP(hipMemcpy(p, meta.data(), sizeof(int) * meta.size(), hipMemcpyHostToDevice));
+  PFC_HIP(hipMemcpy(p + meta.size(), cyc.data(), sizeof(int) * cyc.size(), hipMemcpyHostToDevice));
+  PFC_HIP(hipMemcpy(p + meta.size() + cyc.size(), inn.data(), sizeof(int) * inn.size(), hipMemcpyHostToDevice));
+  I->h.sched_meta = p;
+  I->h.sched_cycles = p + meta.size();
+  I->h.sched_inner = p + meta.size() + cyc.size();
+  I->h.replay = 1;
+  return PFC_OK;
+}
+
+int run_single(pfc_instance* I, hipStream_t s, int job) {
+  int rc = ensure_group(I);
+  if (rc) return rc;
+  I->h.job = job;
+  I->grp.h_descs[0] = I->h;
+  I->grp.h_states[0] = initial_state(job);
+  return I->grp.run(s, std::vector<State*>{I->h.st}, I->timeout_s);
+}
+
+}  // namespace pfc
+
+using namespace pfc;
+
+extern "C" {
+
+const char* pfc_status_str(int st) {
+  switch (st) {
+    case PFC_OK: return "ok";
+    case PFC_NOT_CONVERGED: return "not converged";
+    case PFC_WARN_TAU_CRITICAL: return "converged; tau at or above the critical time step";
+    case PFC_ERR_ARG: return "invalid argument";
+    case PFC_ERR_OOM: return "out of memory";
+    case PFC_ERR_HIP: return "HIP runtime error";
+    case PFC_ERR_BREAKDOWN: return "breakdown: non-finite residual or input";
+    case PFC_ERR_ADMISSION: return "request exceeds the memory budget";
+    case PFC_ERR_STATE: return "invalid state";
+    default: return "unknown status";
+  }
+}
+
+void pfc_opts_default(pfc_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = (int)sizeof(pfc_opts);
+  o->precision = PFC_FP64;
+  o->restart = 30;
+  o->max_steps = 1000;
+  o->outer_tol = 1e-8;
+  o->inner_tol = 1e-3;
+  o->inner_maxit = 500;
+  o->shared_ops = 0;
+  o->rows_per_thread = 0;
+  o->max_run_steps = 256;
+  o->ticks_per_graph = 0;
+}
+
+double pfc_tau_critical(double r, double psibar) {
+  const double a = 1.0 - 3.0 * r - 9.0 * psibar * psibar;
+  if (!(a > 1.0)) return INFINITY;
+  const double s = std::sqrt(a);
+  return 27.0 / (2.0 * (s - 1.0) * (s + 2.0) * (s + 2.0));
+}
+
+size_t pfc_instance_footprint(const pfc_mesh* m, const pfc_opts* o) {
+  if (!m || validate_opts(o)) return 0;
+  InstDev h{};
+  const int ts = team_size_for(m->n_slices, o->rows_per_thread);
+  return carve(h, nullptr, m, *o, ts);
+}
+
+int pfc_instance_create(pfc_mesh* m, const pfc_opts* o, pfc_instance** out) {
+  if (!m || !out) { set_error("pfc_instance_create: null argument"); return PFC_ERR_ARG; }
+  int rc = validate_opts(o);
+  if (rc) return rc;
+  *out = nullptr;
+  pfc_instance* I = new pfc_instance();
+  I->mesh = m;
+  I->opts = *o;
+  I->team_size = team_size_for(m->n_slices, o->rows_per_thread);
+  I->ticks = o->ticks_per_graph > 0 ? o->ticks_per_graph : 64;
+  if (const char* t = std::getenv("PFC_TIMEOUT_S")) I->timeout_s = std::atof(t) > 0 ? std::atof(t) : I->timeout_s;
+  if (I->ticks & 1) I->ticks += 1;
+  InstDev& h = I->h;
+  std::memset(&h, 0, sizeof(h));
+  const size_t bytes = carve(h, nullptr, m, *o, I->team_size);
+  if (hipMalloc((void**)&I->arena, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete I;
+    set_error("pfc_instance_create: device allocation of " + std::to_string(bytes) + " bytes failed");
+    return PFC_ERR_OOM;
+  }
+  I->bytes = bytes;
+  carve(h, I->arena, m, *o, I->team_size);
+  h.m = m->dev;
+  h.n = m->n;
+  h.precision = o->precision;
+  h.restart = o->restart;
+  h.max_steps = o->max_steps;
+  h.inner_maxit = o->inner_maxit;
+  h.shared_ops = o->shared_ops;
+  h.team_size = I->team_size;
+  h.outer_tol = o->outer_tol;
+  h.inner_tol = o->inner_tol;
+  h.ci_tol = 1e-13;
+  if (hipMemset(I->arena, 0, bytes) != hipSuccess || hipStreamCreate(&I->capture) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    pfc_instance_destroy(I);
+    set_error("pfc_instance_create: HIP setup failed");
+    return PFC_ERR_HIP;
+  }
+  *out = I;
+  return PFC_OK;
+}
+
+void pfc_instance_destroy(pfc_instance* I) {
+  if (!I) return;
+  I->grp.release();
+  if (I->capture) (void)hipStreamDestroy(I->capture);
+  if (I->d_sched) (void)hipFree(I->d_sched);
+  if (I->arena) (void)hipFree(I->arena);
+  delete I;
+}
+
+int pfc_solve(pfc_instance* I, const double* psi_k, double r, double psibar, double tau, double m11,
+              const double* rhs, double* x, const pfc_schedule* replay, pfc_solve_info* info, void* stream) {
+  if (!I || !psi_k || !rhs || !x || !std::isfinite(r) || !std::isfinite(psibar) || !(tau > 0.0) ||
+      !std::isfinite(tau) || !(m11 > 0.0) || !std::isfinite(m11)) {
+    set_error("pfc_solve: invalid arguments");
+    return PFC_ERR_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  InstDev& h = I->h;
+  set_params(h, r, tau, m11);
+  h.b_user = rhs;
+  h.x_user = x;
+  h.replay = 0;
+  h.n_steps = 0;
+  h.init_mode = PFC_INIT_GIVEN;
+  if (replay) {
+    int rc = upload_schedules(I, replay, 1, s);
+    if (rc) return rc;
+  }
+  int rc = prep_ops(I, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_assemble_N_sell, dim3(slice_blocks(I->mesh->n_slices)), dim3(PFC_WG), 0, s, h, psi_k);
+  PFC_HIP(hipGetLastError());
+  rc = run_single(I, s, JOB_SOLVE);
+  h.replay = 0;
+  if (rc) return rc;
+  InfoDev f;
+  PFC_HIP(hipMemcpy(&f, h.info, sizeof(InfoDev), hipMemcpyDeviceToHost));
+  I->last_applies = f.inner_applies;
+  if (info) fill_info(info, f);
+  int st = f.status;
+  if (st == PFC_OK && tau >= pfc_tau_critical(r, psibar)) st = PFC_WARN_TAU_CRITICAL;
+  return st;
+}
+
+int pfc_instance_launch_stats(const pfc_instance* I, long long* launches, long long* graphs) {
+  if (!I) { set_error("pfc_instance_launch_stats: null instance"); return PFC_ERR_ARG; }
+  if (graphs) *graphs = I->grp.graphs_run;
+  if (launches) *launches = I->grp.graphs_run * (long long)I->grp.graph_ticks;
+  return PFC_OK;
+}
+
+int pfc_last_inner_counts(const pfc_instance* I, int* counts, int cap, int* n_applies) {
+  if (!I || !counts || cap < 0 || !n_applies) { set_error("pfc_last_inner_counts: invalid arguments"); return PFC_ERR_ARG; }
+  const int na = std::min(I->last_applies, I->opts.max_steps);
+  *n_applies = na;
+  const int k = std::min(na, cap);
+  if (k > 0) PFC_HIP(hipMemcpy(counts, I->h.rec_inner, sizeof(int) * 5 * k, hipMemcpyDeviceToHost));
+  return PFC_OK;
+}
+
+int pfc_rosenbrock_run(pfc_instance* I, double* state, double r, double psibar, double tau, int n_steps, int init,
+                       const pfc_schedule* replays, pfc_solve_info* per_stage, void* stream) {
+  if (!I || !state || !std::isfinite(r) || !std::isfinite(psibar) || !(tau > 0.0) || !std::isfinite(tau) ||
+      n_steps < 0 || n_steps > I->opts.max_run_steps || (init != PFC_INIT_GIVEN && init != PFC_INIT_CONSISTENT)) {
+    set_error("pfc_rosenbrock_run: invalid arguments (n_steps must be <= max_run_steps)");
+    return PFC_ERR_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  InstDev& h = I->h;
+  set_params(h, r, tau, 1.0 / ROS_GAMMA);
+  double* own_xk = h.xk;
+  h.xk = state;
+  h.replay = 0;
+  int rc = PFC_OK;
+  if (replays) rc = upload_schedules(I, replays, 3 * n_steps, s);
+  if (!rc) rc = prep_ops(I, s);
+  if (!rc) {
+    h.n_steps = n_steps;
+    h.init_mode = init;
+    rc = run_single(I, s, JOB_RB);
+  }
+  h.xk = own_xk;
+  h.replay = 0;
+  if (rc) return rc;
+  std::vector<InfoDev> f((size_t)3 * n_steps);
+  if (n_steps > 0) PFC_HIP(hipMemcpy(f.data(), h.info, sizeof(InfoDev) * f.size(), hipMemcpyDeviceToHost));
+  State fin;
+  PFC_HIP(hipMemcpy(&fin, h.st, sizeof(State), hipMemcpyDeviceToHost));
+  int worst = PFC_OK;
+  for (size_t k = 0; k < f.size(); ++k) {
+    if (per_stage) fill_info(per_stage + k, f[k]);
+    if (f[k].status < 0) worst = f[k].status;
+    else if (worst >= 0 && f[k].status > worst) worst = f[k].status;
+  }
+  if (fin.status < 0) worst = fin.status;
+  if (worst == PFC_OK && tau >= pfc_tau_critical(r, psibar)) worst = PFC_WARN_TAU_CRITICAL;
+  return worst;
+}
+
+int pfc_apply_AR(pfc_instance* I, const double* psi_k, double r, double tau, double m11, const double* y, double* out,
+                 void* stream) {
+  if (!I || !psi_k || !y || !out || !std::isfinite(r) || !std::isfinite(tau) || !std::isfinite(m11)) {
+    set_error("pfc_apply_AR: invalid arguments");
+    return PFC_ERR_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  InstDev h = I->h;
+  h.r = r; h.tau = tau; h.m11 = m11;
+  const int nb = slice_blocks(I->mesh->n_slices);
+  hipLaunchKernelGGL(k_assemble_N_sell, dim3(nb), dim3(PFC_WG), 0, s, h, psi_k);
+  hipLaunchKernelGGL(k_apply_AR, dim3(nb), dim3(PFC_WG), 0, s, h, y, out);
+  PFC_HIP(hipGetLastError());
+  PFC_HIP(hipStreamSynchronize(s));
+  return PFC_OK;
+}
+
+int pfc_apply_pch(pfc_instance* I, double tau_s, const double* v, double* z, const int* fixed_counts, int* counts_out,
+                  void* stream) {
+  if (!I || !v || !z || !(tau_s > 0.0) || !std::isfinite(tau_s)) {
+    set_error("pfc_apply_pch: invalid arguments");
+    return PFC_ERR_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  InstDev& h = I->h;
+  set_params(h, 0.0, tau_s, 1.0);
+  h.pch_out = z;
+  h.replay = 0;
+  int rc = PFC_OK;
+  if (fixed_counts) {
+    int one = 1;
+    pfc_schedule q{1, &one, 1, fixed_counts};
+    rc = upload_schedules(I, &q, 1, s);
+    if (rc) return rc;
+  }
+  rc = prep_ops(I, s);
+  if (rc) return rc;
+  PFC_HIP(hipMemcpyAsync(h.W, v, sizeof(double) * 3 * (size_t)h.n, hipMemcpyDeviceToDevice, s));
+  rc = run_single(I, s, JOB_PCH);
+  h.replay = 0;
+  if (rc) return rc;
+  if (counts_out) PFC_HIP(hipMemcpy(counts_out, h.rec_inner, sizeof(int) * 5, hipMemcpyDeviceToHost));
+  return PFC_OK;
+}
+
+int pfc_stage_rhs(pfc_instance* I, const double* x_k, const double* ys, int stage, double r, double tau, double* b,
+                  void* stream) {
+  if (!I || !x_k || !ys || !b || stage < 1 || stage > 3 || !std::isfinite(r) || !std::isfinite(tau)) {
+    set_error("pfc_stage_rhs: invalid arguments");
+    return PFC_ERR_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  InstDev h = I->h;
+  h.r = r; h.tau = tau;
+  h.xk = const_cast<double*>(x_k);
+  h.ys = const_cast<double*>(ys);
+  hipLaunchKernelGGL(k_stage_rhs, dim3(slice_blocks(I->mesh->n_slices)), dim3(PFC_WG), 0, s, h, stage, b);
+  PFC_HIP(hipGetLastError());
+  PFC_HIP(hipStreamSynchronize(s));
+  return PFC_OK;
+}
+
+int pfc_batch_run(pfc_instance* const* insts, int count, double* const* states, const double* r, const double* psibar,
+                  const double* tau, int n_steps, int init, pfc_solve_info* infos, void* stream) {
+  if (!insts || count <= 0 || !states || !r || !psibar || !tau || n_steps < 0 ||
+      (init != PFC_INIT_GIVEN && init != PFC_INIT_CONSISTENT)) {
+    set_error("pfc_batch_run: invalid arguments");
+    return PFC_ERR_ARG;
+  }
+  const int prec = insts[0] ? insts[0]->opts.precision : -1;
+  for (int i = 0; i < count; ++i) {
+    if (!insts[i] || !states[i] || insts[i]->opts.precision != prec || n_steps > insts[i]->opts.max_run_steps ||
+        !(tau[i] > 0.0) || !std::isfinite(tau[i]) || !std::isfinite(r[i])) {
+      set_error("pfc_batch_run: instance " + std::to_string(i) + " invalid (null, mixed precision, or bad parameters)");
+      return PFC_ERR_ARG;
+    }
+    for (int k = 0; k < i; ++k)
+      if (insts[k] == insts[i]) { set_error("pfc_batch_run: instances must be distinct"); return PFC_ERR_ARG; }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int> ts(count);
+  std::vector<State*> sts(count);
+  for (int i = 0; i < count; ++i) {
+    InstDev& h = insts[i]->h;
+    set_params(h, r[i], tau[i], 1.0 / ROS_GAMMA);
+    h.replay = 0;
+    ts[i] = insts[i]->team_size;
+    sts[i] = h.st;
+    int rc = prep_ops(insts[i], s);
+    if (rc) return rc;
+  }
+  const int ticks = insts[0]->ticks;
+  int rc = PFC_OK;
+  auto one_pass = [&](int precision, int steps, int initm) -> int {
+    Group g;
+    int e = g.alloc(ts);
+    if (!e) e = g.build(insts[0]->capture, precision, ticks);
+    if (!e) {
+      for (int i = 0; i < count; ++i) {
+        InstDev h = insts[i]->h;
+        h.xk = states[i];
+        h.job = JOB_RB;
+        h.n_steps = steps;
+        h.init_mode = initm;
+        g.h_descs[i] = h;
+        g.h_states[i] = initial_state(JOB_RB);
+      }
+      e = g.run(s, sts, insts[0]->timeout_s * count);
+    }
+    g.release();
+    return e;
+  };
+  rc = one_pass(prec, n_steps, init);
+  if (rc) return rc;
+  int worst = PFC_OK;
+  std::vector<InfoDev> f((size_t)3 * n_steps);
+  for (int i = 0; i < count; ++i) {
+    if (n_steps > 0)
+      PFC_HIP(hipMemcpy(f.data(), insts[i]->h.info, sizeof(InfoDev) * f.size(), hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < f.size(); ++k) {
+      if (infos) fill_info(infos + (size_t)i * f.size() + k, f[k]);
+      if (f[k].status < 0) worst = f[k].status;
+      else if (worst >= 0 && f[k].status > worst) worst = f[k].status;
+    }
+  }
+  return worst;
+}
+
+}  // extern "C"

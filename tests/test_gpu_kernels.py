@@ -1,0 +1,115 @@
+"""Kernel-level parity of the HIP path against the oracle (needs a GPU)."""
+import numpy as np
+import pytest
+
+from helpers import Problem, dev, host, rel
+from oracle import assembly, pfc as opfc, precond
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(2, 16, 0.2), (2, 10, 0.0), (3, 5, 0.2), (3, 4, 0.0)]  # n = 256, 100 (ragged), 125 (ragged), 64
+
+
+@pytest.fixture(scope="module")
+def pfc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1501_06852_amd import pfc as lib
+    return lib
+
+
+@pytest.mark.parametrize("dim,N,jit", CASES)
+def test_p1_assembly_matches_oracle(pfc, dim, N, jit):
+    P = Problem(dim, N, jit, seed=3)
+    try:
+        rp, ci, mv, kv = pfc.pfc_mesh_export_csr(P.gpu_mesh())
+        assert np.array_equal(rp, P.M.indptr) and np.array_equal(ci, P.M.indices)
+        assert np.abs(mv - P.M.data).max() <= 1e-13 * np.abs(P.M.data).max()
+        assert np.abs(kv - P.K.data).max() <= 1e-12 * np.abs(P.K.data).max()
+    finally:
+        P.close()
+
+
+@pytest.mark.parametrize("dim,N,jit", CASES)
+def test_spmv_N_and_cubic_load(pfc, dim, N, jit):
+    P = Problem(dim, N, jit, amp=0.3, seed=4)
+    try:
+        m = P.gpu_mesh()
+        x = np.random.default_rng(1).normal(size=P.n)
+        y = dev(np.zeros(P.n))
+        pfc.pfc_spmv(m, pfc.PFC_OP_M, dev(x), y)
+        assert rel(host(y), P.M @ x) <= 1e-13
+        pfc.pfc_spmv(m, pfc.PFC_OP_K, dev(x), y)
+        assert rel(host(y), P.K @ x) <= 1e-12
+        Nref = assembly.N_matrix(P.mesh, P.psi)
+        Nd = dev(np.zeros(P.M.nnz))
+        pfc.pfc_assemble_N(m, dev(P.psi), Nd)
+        Nh = host(Nd)
+        # the oracle's N has the same pattern as M (every element pair)
+        assert np.array_equal(Nref.indptr, P.M.indptr)
+        assert np.abs(Nh - Nref.data).max() <= 1e-13 * np.abs(Nref.data).max()
+        g = dev(np.zeros(P.n))
+        pfc.pfc_load_psi3(m, dev(P.psi), g)
+        assert rel(host(g), assembly.load_psi3(P.mesh, P.psi)) <= 1e-13
+    finally:
+        P.close()
+
+
+@pytest.mark.parametrize("dim,N,jit", CASES[:3])
+def test_apply_AR_and_stage_rhs(pfc, dim, N, jit):
+    P = Problem(dim, N, jit, amp=0.2, seed=5)
+    inst = None
+    try:
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default())
+        n = P.n
+        rng = np.random.default_rng(2)
+        y = rng.normal(size=3 * n)
+        r, tau, m11 = -0.35, 0.6, 1.0 / opfc.ROS3PW_GAMMA
+        N = assembly.N_matrix(P.mesh, P.psi)
+        out = dev(np.zeros(3 * n))
+        pfc.pfc_apply_AR(inst, n, dev(P.psi), r, tau, m11, dev(y), out)
+        assert rel(host(out), opfc.apply_AR(P.M, P.K, N, r, tau, m11, y)) <= 1e-13
+        xk = np.concatenate([rng.normal(size=n), P.psi, rng.normal(size=n)])
+        ys = rng.normal(size=(3, 3 * n)) * 0.1
+        a = {(2, 1): opfc.ROS3PW_A[(2, 1)], (3, 1): opfc.ROS3PW_A[(3, 1)], (3, 2): opfc.ROS3PW_A[(3, 2)]}
+        for stage in (1, 2, 3):
+            xi = xk + sum(a[(stage, j)] * ys[j - 1] for j in range(1, stage))
+            c = [opfc.ROS3PW_C[(stage, j)] for j in range(1, stage)]
+            bref = opfc.stage_rhs_R(P.mesh, P.M, P.K, r, tau, xi, [ys[j - 1][n:2 * n] for j in range(1, stage)], c)
+            b = dev(np.zeros(3 * n))
+            pfc.pfc_stage_rhs(inst, n, dev(xk), dev(ys.reshape(-1)), stage, r, tau, b)
+            assert rel(host(b), bref) <= 1e-12, stage
+    finally:
+        if inst is not None:
+            pfc.pfc_instance_destroy(inst)
+        P.close()
+
+
+@pytest.mark.parametrize("dim,N,jit,tau_s", [(2, 16, 0.2, 0.8), (2, 10, 0.0, 0.05), (3, 5, 0.2, 0.4)])
+def test_pch_apply_fixed_counts(pfc, dim, N, jit, tau_s):
+    P = Problem(dim, N, jit, seed=6)
+    inst = None
+    try:
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default())
+        n = P.n
+        v = np.random.default_rng(3).normal(size=3 * n)
+        inner = precond.InnerSolvers(P.M, P.K, tau_s, mode="pcg", tol=1e-3)
+        z_ref = precond.pch_apply(inner, v)
+        counts = inner.counts[0]
+        z = dev(np.zeros(3 * n))
+        got = pfc.pfc_apply_pch(inst, n, tau_s, dev(v), z, fixed_counts=counts)
+        assert list(got) == list(counts)
+        assert rel(host(z), z_ref) <= 1e-12
+        # tolerance mode: same counts up to rounding near the threshold, same accuracy class
+        got2 = pfc.pfc_apply_pch(inst, n, tau_s, dev(v), z)
+        assert np.abs(np.array(got2) - np.array(counts)).max() <= 1
+        # exact-inner limit: the preconditioner is P_CH^{-1} (dense check on the same z)
+        P3 = precond.P3_dense(P.M, P.K, tau_s) if n <= 256 else None
+        if P3 is not None:
+            inner_ex = precond.InnerSolvers(P.M, P.K, tau_s, mode="exact")
+            assert rel(precond.pch_apply(inner_ex, v), np.linalg.solve(P3, v)) <= 1e-11
+    finally:
+        if inst is not None:
+            pfc.pfc_instance_destroy(inst)
+        P.close()

@@ -1,0 +1,153 @@
+"""Solve-level parity of the HIP path against the oracle (needs a GPU)."""
+import numpy as np
+import pytest
+
+from helpers import Problem, dev, host, rel
+from oracle import assembly, pfc as opfc, reference, solve as osolve
+
+pytestmark = pytest.mark.gpu
+M11 = 1.0 / opfc.ROS3PW_GAMMA
+
+
+@pytest.fixture(scope="module")
+def pfc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1501_06852_amd import pfc as lib
+    return lib
+
+
+def _stage1(P, r, tau):
+    x0 = opfc.consistent_init(P.mesh, P.M, P.K, r, P.psi)
+    b = opfc.stage_rhs_R(P.mesh, P.M, P.K, r, tau, x0, [], [])
+    return x0, b
+
+
+@pytest.mark.parametrize("dim,N,jit,tau,prec", [(2, 16, 0.2, 0.1, 0), (2, 10, 0.0, 1.0, 0), (3, 5, 0.2, 0.5, 0),
+                                                (2, 24, 0.2, 1.0, 0)])
+def test_solve_replay_parity(pfc, dim, N, jit, tau, prec):
+    P = Problem(dim, N, jit, seed=7)
+    inst = None
+    try:
+        r, psibar = -0.35, -0.3
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(precision=prec))
+        n = P.n
+        _, b = _stage1(P, r, tau)
+        Nm = assembly.N_matrix(P.mesh, P.psi)
+        y_ref, info = osolve.solve_stage(P.M, P.K, Nm, r, tau, M11, b, tol=1e-8)
+        s = info["schedule"]
+        x = dev(np.zeros(3 * n))
+        st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
+        assert gi["outer_iters"] == info["steps"]
+        assert rel(host(x), y_ref) <= 1e-10
+        assert st == pfc.PFC_OK
+    finally:
+        if inst is not None:
+            pfc.pfc_instance_destroy(inst)
+        P.close()
+
+
+@pytest.mark.parametrize("dim,N,jit,tau,prec", [(2, 16, 0.2, 0.1, 0), (2, 16, 0.2, 1.0, 1), (3, 5, 0.2, 0.5, 0),
+                                                (3, 6, 0.0, 0.5, 1)])
+def test_solve_tolerance_mode(pfc, dim, N, jit, tau, prec):
+    """True residual <= 1e-8 checked with the oracle's operator; error against a tight oracle solve stated."""
+    P = Problem(dim, N, jit, seed=8)
+    inst = None
+    try:
+        r, psibar = -0.35, -0.3
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(precision=prec))
+        n = P.n
+        _, b = _stage1(P, r, tau)
+        Nm = assembly.N_matrix(P.mesh, P.psi)
+        x = dev(np.zeros(3 * n))
+        st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
+        y = host(x)
+        res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, tau, M11, y)) / np.linalg.norm(b)
+        assert st == pfc.PFC_OK and res <= 1e-8, (st, res, gi)
+        assert abs(gi["true_rel_res"] - res) <= 1e-3 * res + 1e-15
+        y_t, _ = osolve.solve_stage(P.M, P.K, Nm, r, tau, M11, b, tol=1e-13)
+        fwd = rel(y, y_t)
+        y64, i64 = osolve.solve_stage(P.M, P.K, Nm, r, tau, M11, b, tol=1e-8)
+        # same accuracy class as the FP64 oracle at the same tolerance
+        assert fwd <= max(1e-6, 50 * rel(y64, y_t)), (fwd, rel(y64, y_t))
+        # mixed precision at a tight outer tolerance still reaches the FP64 solution
+        opts = pfc.pfc_opts_default(precision=prec, outer_tol=1e-12)
+        inst2 = pfc.pfc_instance_create(P.gpu_mesh(), opts)
+        try:
+            st2, _ = pfc.pfc_solve(inst2, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
+            assert rel(host(x), y_t) <= 1e-10 if prec == 0 else rel(host(x), y_t) <= 1e-8
+        finally:
+            pfc.pfc_instance_destroy(inst2)
+    finally:
+        if inst is not None:
+            pfc.pfc_instance_destroy(inst)
+        P.close()
+
+
+def test_zero_rhs_and_bad_args(pfc):
+    P = Problem(2, 8, 0.0, seed=1)
+    inst = None
+    try:
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default())
+        n = P.n
+        x = dev(np.ones(3 * n))
+        st, gi = pfc.pfc_solve(inst, n, dev(P.psi), -0.3, -0.3, 0.5, M11, dev(np.zeros(3 * n)), x)
+        assert st == pfc.PFC_OK and gi["outer_iters"] == 0 and not host(x).any()
+        with pytest.raises(pfc.PFCError):
+            pfc.pfc_solve(inst, n, dev(P.psi), -0.3, -0.3, -1.0, M11, dev(np.zeros(3 * n)), x)
+    finally:
+        if inst is not None:
+            pfc.pfc_instance_destroy(inst)
+        P.close()
+
+
+def test_fft_exact_agreement(pfc):
+    """Unjittered mesh, constant psi: the tight GPU solve equals the exact Fourier solution."""
+    P = Problem(2, 48, 0.0, amp=0.0, psibar=-0.3, seed=2)
+    inst = None
+    try:
+        r, tau = -0.35, 1.0
+        n = P.n
+        b = np.random.default_rng(4).normal(size=3 * n)
+        yf = reference.fft_exact(P.mesh, P.M, P.K, r, tau, M11, -0.3, b)
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(outer_tol=1e-12))
+        x = dev(np.zeros(3 * n))
+        st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, -0.3, tau, M11, dev(b), x)
+        assert rel(host(x), yf) <= 1e-10, gi
+    finally:
+        if inst is not None:
+            pfc.pfc_instance_destroy(inst)
+        P.close()
+
+
+@pytest.mark.parametrize("dim,N,jit,tau", [(2, 12, 0.2, 0.5), (3, 4, 0.1, 0.5)])
+def test_rosenbrock_run_replay_parity(pfc, dim, N, jit, tau):
+    P = Problem(dim, N, jit, amp=0.05, seed=9)
+    inst = None
+    try:
+        r, psibar, steps = -0.35, -0.3, 2
+        n = P.n
+        x0 = opfc.consistent_init(P.mesh, P.M, P.K, r, P.psi)
+        x_ref, infos = osolve.rosenbrock_run(P.mesh, P.M, P.K, x0, r, tau, steps, tol=1e-8)
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default())
+        state = dev(np.concatenate([np.zeros(n), P.psi, np.zeros(n)]))
+        reps = [(i["schedule"].cycles, i["schedule"].inner) for i in infos]
+        st, gi = pfc.pfc_rosenbrock_run(inst, n, state, r, psibar, tau, steps, pfc.PFC_INIT_CONSISTENT, replays=reps)
+        assert [g["outer_iters"] for g in gi] == [i["steps"] for i in infos]
+        assert rel(host(state), x_ref) <= 1e-10
+        # tolerance mode: conservation of int psi_h and closeness to the oracle trajectory
+        state2 = dev(np.concatenate([np.zeros(n), P.psi, np.zeros(n)]))
+        st2, gi2 = pfc.pfc_rosenbrock_run(inst, n, state2, r, psibar, tau, steps, pfc.PFC_INIT_CONSISTENT)
+        s2 = host(state2)
+        assert st2 == pfc.PFC_OK and all(g["true_rel_res"] <= 1e-8 for g in gi2)
+        # int psi_h changes per stage by gamma * 1^T r_1 <= gamma sqrt(n) ||r|| (residual of block row 1)
+        m0 = np.sum(P.M @ P.psi)
+        bnd = sum(abs(m) for m in opfc.ROS3PW_M) * steps * opfc.ROS3PW_GAMMA * np.sqrt(n) * 1e-8
+        bmax = max(np.linalg.norm(opfc.stage_rhs_R(P.mesh, P.M, P.K, r, tau, x0, [], [])), 1.0)
+        assert abs(np.sum(P.M @ s2[n:2 * n]) - m0) <= 10 * bnd * bmax
+        assert rel(s2, x_ref) <= 1e-6
+    finally:
+        if inst is not None:
+            pfc.pfc_instance_destroy(inst)
+        P.close()

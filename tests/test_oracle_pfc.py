@@ -63,6 +63,10 @@ def test_consistent_init_zeroes_algebraic_rows():
     n = mesh.n
     assert np.abs(F[:n]).max() < 1e-12 and np.abs(F[2 * n:]).max() < 1e-12
     assert np.array_equal(x0[n:2 * n], psi)
+    # the mass solves agree with a sparse LU solve
+    import scipy.sparse.linalg as spla
+    om = spla.spsolve(M.tocsc(), -(K @ psi))
+    assert np.abs(x0[2 * n:] - om).max() <= 1e-13 * np.abs(om).max()
 
 
 def _run(mesh, M, K, x0, r, tau, steps):
