@@ -57,14 +57,166 @@ def run_cpu_baseline(dim, N, jitter, r, psibar, tau, seed):
                        f"workload, oracle float64 FGMRES(30)+P_CH+Jacobi-PCG, {dt:.1f} s")
 
 
+def bench_batched(args, torch, wl, pfc):
+    """256 independent 2D 128^2 instances on one shared mesh, one launch set: mixed batched versus
+    the plain float64 solver run instance by instance (same instances, same steps)."""
+    count = args.batch
+    N = 128
+    mesh = wl.make_mesh(2, N)
+    n = mesh.n
+    h = pfc.pfc_mesh_create_p1(2, n, mesh.elem_nodes, mesh.elem_coords)
+    prm = wl.draw_params(count, 7000)
+    steps = args.steps if args.steps is not None else 1
+    dev = torch.device("cuda:0")
+
+    def states():
+        out = []
+        for p in prm:
+            s = torch.zeros(3 * n, dtype=torch.float64, device=dev)
+            s[n:2 * n] = torch.tensor(wl.psi0(n, p.psibar, 0.01, seed=p.seed), dtype=torch.float64, device=dev)
+            out.append(s)
+        return out
+
+    res = {}
+    for label, prec, shared in (("batched_mixed", 1, 1), ("batched_fp64", 0, 1)):
+        insts = [pfc.pfc_instance_create(h, pfc.pfc_opts_default(precision=prec, shared_ops=shared))
+                 for _ in range(count)]
+        st = states()
+        pfc.pfc_batch_run(insts, [n] * count, st, [p.r for p in prm], [p.psibar for p in prm],
+                          [p.tau for p in prm], 0, pfc.PFC_INIT_CONSISTENT)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        code, infos = pfc.pfc_batch_run(insts, [n] * count, st, [p.r for p in prm], [p.psibar for p in prm],
+                                        [p.tau for p in prm], steps, pfc.PFC_INIT_GIVEN)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        resid = max(i["true_rel_res"] for row in infos for i in row)
+        res[label] = dict(solves_per_s=3 * steps * count / dt, seconds=dt, status=pfc.pfc_status_str(code),
+                          max_true_rel_res=resid)
+        for i in insts:
+            pfc.pfc_instance_destroy(i)
+    # plain float64 solver, one instance at a time, on a sample of the same instances
+    sample = min(count, args.plain_sample)
+    inst = pfc.pfc_instance_create(h, pfc.pfc_opts_default())
+    st = states()[:sample]
+    for k in range(sample):
+        p = prm[k]
+        pfc.pfc_rosenbrock_run(inst, n, st[k], p.r, p.psibar, p.tau, 0, pfc.PFC_INIT_CONSISTENT)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(sample):
+        p = prm[k]
+        pfc.pfc_rosenbrock_run(inst, n, st[k], p.r, p.psibar, p.tau, steps, pfc.PFC_INIT_GIVEN)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res["plain_fp64_sequential"] = dict(solves_per_s=3 * steps * sample / dt, seconds=dt, instances=sample)
+    pfc.pfc_instance_destroy(inst)
+    pfc.pfc_mesh_destroy(h)
+    out = {"metric": "PFC block solves/s @1e-8 rel residual", "value": res["batched_mixed"]["solves_per_s"],
+           "unit": "stage solves/s", "n_gpus": 1, "steps": steps, "warmup": 0, "higher_is_better": True,
+           "dtype": "f64 outer / f32 inner", "data": "synthetic",
+           "config": {"workload": f"pfc2d_128_batched{count}_mixed", "instances": count, "grid": N, "nodes": n},
+           "speedup_vs_plain_fp64": res["batched_mixed"]["solves_per_s"] / res["plain_fp64_sequential"]["solves_per_s"],
+           "detail": res}
+    print(json.dumps(out), flush=True)
+
+
+def bench_served(args, torch, wl, pfc):
+    """Served stream: Poisson arrivals of Rosenbrock requests over six mesh classes.  Mixed precision with
+    continuous batching versus the plain float64 solver serving one request at a time (FIFO)."""
+    import ctypes as C
+    classes = wl.SERVED_CLASSES
+    meshes = []
+    for dim, N in classes:
+        m = wl.make_mesh(dim, N)
+        meshes.append((m, pfc.pfc_mesh_create_p1(dim, m.n, m.elem_nodes, m.elem_coords)))
+    nreq = args.requests
+    steps = args.req_steps
+
+    def stream(rate):
+        return wl.served_stream(nreq, rate, 4242)
+
+    def serve(prec, slots, rate):
+        so = pfc.pfc_server_opts(C.sizeof(pfc.pfc_server_opts), prec, 96 << 30, slots, 0)
+        srv = C.c_void_p()
+        assert pfc._lib.pfc_server_create(C.byref(so), C.byref(srv)) == 0
+        reqs = stream(rate)
+        psis = [np.ascontiguousarray(wl.psi0(meshes[c][0].n, p.psibar, 0.01, seed=p.seed)) for _, c, p in reqs]
+        t_base = pfc._lib.pfc_server_clock(srv)
+        arrive = {}
+        for k, (t, c, p) in enumerate(reqs):
+            while pfc._lib.pfc_server_clock(srv) - t_base < t:
+                time.sleep(0.0005)
+            arrive[k] = pfc._lib.pfc_server_clock(srv)
+            rc = pfc._lib.pfc_server_submit(srv, meshes[c][1], p.r, p.psibar, p.tau, psis[k].ctypes.data_as(pfc._dp),
+                                            steps, k)
+            assert rc == 0, pfc.pfc_last_error()
+        assert pfc._lib.pfc_server_drain(srv) == 0
+        t_end = pfc._lib.pfc_server_clock(srv)
+        buf = (pfc.pfc_result * 64)()
+        got = C.c_int()
+        lat, worst = [], 0.0
+        while True:
+            pfc._lib.pfc_server_poll(srv, buf, 64, C.byref(got))
+            if got.value == 0:
+                break
+            for k in range(got.value):
+                r = buf[k]
+                lat.append(r.t_done - arrive[r.req_id])
+                worst = max([worst] + [r.infos[i].true_rel_res for i in range(r.n_stages)])
+                pfc._lib.pfc_result_free(C.byref(buf[k]))
+        pfc._lib.pfc_server_destroy(srv)
+        lat = np.array(lat)
+        return dict(solves_per_s=3 * steps * nreq / (t_end - t_base), wall_s=t_end - t_base,
+                    p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                    max_true_rel_res=worst)
+
+    # capacity of the plain server (backlogged), then both at 0.8 of that rate
+    base_bl = serve(0, 1, 0.0)
+    rate = 0.8 * nreq / base_bl["wall_s"]
+    ours_bl = serve(1, args.slots, 0.0)
+    base = serve(0, 1, rate)
+    ours = serve(1, args.slots, rate)
+    for _, hm in meshes:
+        pfc.pfc_mesh_destroy(hm)
+    out = {"metric": "PFC block solves/s @1e-8 rel residual; p50/p99 served latency", "value": ours_bl["solves_per_s"],
+           "unit": "stage solves/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64 outer / f32 inner",
+           "data": "synthetic",
+           "config": {"workload": "served_stream", "requests": nreq, "rosenbrock_steps": steps,
+                      "classes": [f"{d}D {N}" for d, N in classes], "arrival_rate_hz": rate, "slots": args.slots},
+           "speedup_vs_plain_fp64_fifo": ours_bl["solves_per_s"] / base_bl["solves_per_s"],
+           "backlogged": {"mixed_continuous": ours_bl, "fp64_fifo": base_bl},
+           "poisson": {"mixed_continuous": ours, "fp64_fifo": base}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_copy_calibration(torch):
+    """Plain device copy of 1 GiB (float64), three times: the reference kernel whose
+    FETCH_SIZE / WRITE_SIZE counter readings calibrate the solver kernel's."""
+    n = 1 << 27
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "copy_calibration", "bytes_read_per_copy": 8 * n, "bytes_written_per_copy": 8 * n,
+                      "copies": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="pfc2d_512_fp64", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="pfc2d_512_fp64", choices=sorted(WORKLOADS) + ["batched", "served", "copy_calibration"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--plain-sample", type=int, default=16)
+    ap.add_argument("--requests", type=int, default=48)
+    ap.add_argument("--req-steps", type=int, default=5)
+    ap.add_argument("--slots", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1"}))
@@ -75,6 +227,12 @@ def main():
     import workloads as wl
     from paper_1501_06852_amd import pfc, roofline
 
+    if args.workload == "copy_calibration":
+        return bench_copy_calibration(torch)
+    if args.workload == "batched":
+        return bench_batched(args, torch, wl, pfc)
+    if args.workload == "served":
+        return bench_served(args, torch, wl, pfc)
     dim, N, jitter, r, psibar, tau, prec, dsteps = WORKLOADS[args.workload]
     steps = args.steps if args.steps is not None else dsteps
     dev = torch.device("cuda:0")

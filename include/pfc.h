@@ -78,7 +78,11 @@ typedef struct pfc_server pfc_server;
  *                 more bytes per iteration; useful when many instances share a mesh)
  *   rows_per_thread  rows of the mesh handled per thread in each phase (1..8, 0 = auto)
  *   max_run_steps capacity of per-stage info records of a Rosenbrock run (steps)
- *   ticks_per_graph  solver phases captured per replayed graph (0 = auto) */
+ *   ticks_per_graph  solver phases captured per replayed graph (0 = auto)
+ *   single_reduction 0: inner PCG in the standard form (two reductions, two
+ *                 launches per iteration); 1: the Chronopoulos-Gear form of the
+ *                 same iteration (one reduction, one launch per iteration;
+ *                 identical iterates in exact arithmetic) */
 typedef struct pfc_opts {
     int struct_size;
     int precision;
@@ -91,7 +95,7 @@ typedef struct pfc_opts {
     int rows_per_thread;
     int max_run_steps;
     int ticks_per_graph;
-    int reserved;
+    int single_reduction;
 } pfc_opts;
 
 /* Result record of one stage solve.

@@ -24,17 +24,23 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum (a, b) over the workgroup; result valid in thread 0.
-__device__ __forceinline__ double2 wg_sum2(double a, double b, double2* lds4) {
-  a = wave_sum(a);
-  b = wave_sum(b);
+struct Red3 {
+  double a, b, c;
+};
+__device__ __forceinline__ Red3 red3(double a, double b, double c = 0.0) { return Red3{a, b, c}; }
+
+// Sum (a, b, c) over the workgroup; result valid in thread 0.
+__device__ __forceinline__ Red3 wg_sum3(Red3 v, Red3* lds4) {
+  v.a = wave_sum(v.a);
+  v.b = wave_sum(v.b);
+  v.c = wave_sum(v.c);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) lds4[wave] = make_double2(a, b);
+  if (lane == 0) lds4[wave] = v;
   __syncthreads();
-  double2 r = make_double2(0.0, 0.0);
+  Red3 r = red3(0.0, 0.0, 0.0);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int w = 0; w < PFC_WAVES; ++w) { r.x += lds4[w].x; r.y += lds4[w].y; }
+    for (int w = 0; w < PFC_WAVES; ++w) { r.a += lds4[w].a; r.b += lds4[w].b; r.c += lds4[w].c; }
   }
   __syncthreads();
   return r;
@@ -116,7 +122,7 @@ __device__ double node_psi3(const MeshDev& m, int i, PsiF psi) {
 // Every phase returns this thread's contribution to the two partial sums.
 
 // N(psi_k) = -3 Mpsi2 reassembled in place (one value per stored entry).
-__device__ double2 ph_rb_begin(const InstDev& I, const Team& tm) {
+__device__ Red3 ph_rb_begin(const InstDev& I, const Team& tm) {
   const int n = I.n;
   const double* xk = I.xk;
   auto psi = [&](int j) { return xk[n + j]; };
@@ -129,7 +135,7 @@ __device__ double2 ph_rb_begin(const InstDev& I, const Team& tm) {
       I.N[e] = -3.0 * entry_Mpsi2(I.m, e, psi);
     }
   }
-  return make_double2(0.0, 0.0);
+  return red3(0.0, 0.0);
 }
 
 __device__ __forceinline__ double stage_comb(const InstDev& I, int stage, int blk, int j) {
@@ -175,7 +181,7 @@ __device__ __forceinline__ void stage_rhs_row(const InstDev& I, int sl, int lane
 
 // Right-hand side of the solve: stage rhs b_i^R for job RB, the caller's rhs
 // for job SOLVE.  Writes W = b with block 1 divided by m11, X = 0.
-__device__ double2 ph_solve_init(const InstDev& I, const State& S, const Team& tm) {
+__device__ Red3 ph_solve_init(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   const bool rb = (S.job == JOB_RB);
   double* X = rb ? (I.ys + (long long)(S.stage - 1) * 3 * n) : I.x_user;
@@ -198,10 +204,10 @@ __device__ double2 ph_solve_init(const InstDev& I, const State& S, const Team& t
       a1 += b0 * b0 + bs1 * bs1 + b2 * b2;
     }
   }
-  return make_double2(a0, a1);
+  return red3(a0, a1);
 }
 
-__device__ double2 ph_rb_update(const InstDev& I, const Team& tm) {
+__device__ Red3 ph_rb_update(const InstDev& I, const Team& tm) {
   const int n = I.n;
   const long long n3 = 3LL * n;
   PFC_SLICES(I, tm) {
@@ -213,7 +219,7 @@ __device__ double2 ph_rb_update(const InstDev& I, const Team& tm) {
       }
     }
   }
-  return make_double2(0.0, 0.0);
+  return red3(0.0, 0.0);
 }
 
 // ---- inner PCG --------------------------------------------------------------
@@ -276,7 +282,7 @@ __device__ __forceinline__ T row_dot(const InstDev& I, int sl, int lane, const T
 }
 
 template <typename T>
-__device__ double2 ph_pcg_setup(const InstDev& I, const State& S, const Team& tm) {
+__device__ Red3 ph_pcg_setup(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   const int kind = S.kind;
   PcgOps<T> o = pcg_ops<T>(I, kind);
@@ -356,7 +362,7 @@ __device__ double2 ph_pcg_setup(const InstDev& I, const State& S, const Team& tm
       a1 += rd * rd;
     }
   }
-  return make_double2(a0, a1);
+  return red3(a0, a1);
 }
 
 // p_j = D^{-1}_j r_j + beta p_old_j, evaluated identically wherever needed
@@ -367,7 +373,7 @@ __device__ __forceinline__ T pval(const T* dinv, const T* r, const T* pold, T be
 }
 
 template <typename T>
-__device__ double2 ph_pcg_a(const InstDev& I, const State& S, const Team& tm) {
+__device__ Red3 ph_pcg_a(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   PcgOps<T> o = pcg_ops<T>(I, S.kind);
   const T* r = (const T*)I.r_;
@@ -394,11 +400,11 @@ __device__ double2 ph_pcg_a(const InstDev& I, const State& S, const Team& tm) {
       a0 += (double)pi * (double)acc;
     }
   }
-  return make_double2(a0, 0.0);
+  return red3(a0, 0.0);
 }
 
 template <typename T>
-__device__ double2 ph_pcg_b(const InstDev& I, const State& S, const Team& tm) {
+__device__ Red3 ph_pcg_b(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   PcgOps<T> o = pcg_ops<T>(I, S.kind);
   T* r = (T*)I.r_;
@@ -418,7 +424,7 @@ __device__ double2 ph_pcg_b(const InstDev& I, const State& S, const Team& tm) {
       a1 += rd * ((double)o.dinv[i] * rd);
     }
   }
-  return make_double2(a0, a1);
+  return red3(a0, a1);
 }
 
 // ---- outer block operator ------------------------------------------------------
@@ -446,7 +452,7 @@ __device__ __forceinline__ void block_row(const InstDev& I, int sl, int lane, do
 }
 
 template <typename T>
-__device__ double2 ph_aspmv(const InstDev& I, const State& S, const Team& tm) {
+__device__ Red3 ph_aspmv(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   const long long n3 = 3LL * n;
   double* Zj = I.Z + (long long)S.j * n3;
@@ -466,10 +472,10 @@ __device__ double2 ph_aspmv(const InstDev& I, const State& S, const Team& tm) {
       a1 += w0 * w0 + w1 * w1 + w2 * w2;
     }
   }
-  return make_double2(a0, a1);
+  return red3(a0, a1);
 }
 
-__device__ double2 ph_mgs(const InstDev& I, const State& S, const Team& tm, bool last) {
+__device__ Red3 ph_mgs(const InstDev& I, const State& S, const Team& tm, bool last) {
   const int n = I.n;
   const long long n3 = 3LL * n;
   const int ip = last ? S.j : S.mgs_i - 1;
@@ -488,10 +494,10 @@ __device__ double2 ph_mgs(const InstDev& I, const State& S, const Team& tm, bool
       }
     }
   }
-  return make_double2(a0, 0.0);
+  return red3(a0, 0.0);
 }
 
-__device__ double2 ph_update_x(const InstDev& I, const State& S, const Team& tm, const double* y) {
+__device__ Red3 ph_update_x(const InstDev& I, const State& S, const Team& tm, const double* y) {
   const int n = I.n;
   const long long n3 = 3LL * n;
   double* X = (S.job == JOB_RB) ? (I.ys + (long long)(S.stage - 1) * n3) : I.x_user;
@@ -507,10 +513,10 @@ __device__ double2 ph_update_x(const InstDev& I, const State& S, const Team& tm,
       }
     }
   }
-  return make_double2(0.0, 0.0);
+  return red3(0.0, 0.0);
 }
 
-__device__ double2 ph_true_res(const InstDev& I, const State& S, const Team& tm) {
+__device__ Red3 ph_true_res(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   const long long n3 = 3LL * n;
   const bool rb = (S.job == JOB_RB);
@@ -532,11 +538,11 @@ __device__ double2 ph_true_res(const InstDev& I, const State& S, const Team& tm)
       a1 += r0 * r0 + rs1 * rs1 + r2 * r2;
     }
   }
-  return make_double2(a0, a1);
+  return red3(a0, a1);
 }
 
 template <typename T>
-__device__ double2 ph_pch_out(const InstDev& I, const Team& tm) {
+__device__ Red3 ph_pch_out(const InstDev& I, const Team& tm) {
   const int n = I.n;
   const T* x2 = (const T*)I.x2;
   PFC_SLICES(I, tm) {
@@ -547,7 +553,98 @@ __device__ double2 ph_pch_out(const InstDev& I, const Team& tm) {
       I.pch_out[2 * n + i] = (double)x2[i];
     }
   }
-  return make_double2(0.0, 0.0);
+  return red3(0.0, 0.0);
+}
+
+// ---- single-reduction Jacobi PCG (Chronopoulos-Gear form) ----------------------
+// Same iterates as the standard PCG in exact arithmetic, with the two inner
+// products of an iteration taken in one reduction:
+//   s_i = w_i + beta_i s_{i-1},  p_i = u_i + beta_i p_{i-1},
+//   x_{i+1} = x_i + alpha_i p_i, r_{i+1} = r_i - alpha_i s_i, u = D^{-1} r, w = C u,
+//   gamma = (r, u), delta = (w, u), beta_{i+1} = gamma_{i+1}/gamma_i,
+//   alpha_{i+1} = gamma_{i+1} / (delta_{i+1} - beta_{i+1} gamma_{i+1} / alpha_i).
+// u_{i+1} at gathered neighbours is recomputed from r_i, w_i, s_{i-1}; r, w, s
+// are double-buffered, p and x are updated in place by their owners.
+template <typename T>
+__device__ __forceinline__ T cg_s(const T* wc, const T* so, T beta, bool first, int j) {
+  return first ? wc[j] : (wc[j] + beta * so[j]);
+}
+template <typename T>
+__device__ __forceinline__ T cg_unew(const T* dinv, const T* rc, const T* wc, const T* so, T alpha, T beta, bool first,
+                                      int j) {
+  return dinv[j] * (rc[j] - alpha * cg_s(wc, so, beta, first, j));
+}
+
+template <typename T>
+__device__ Red3 ph_cg_init(const InstDev& I, const State& S, const Team& tm) {
+  const int n = I.n;
+  PcgOps<T> o = pcg_ops<T>(I, S.kind);
+  const T* r = (const T*)I.r_;
+  T* w = (T*)I.q;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  PFC_SLICES(I, tm) {
+    const int i = sl * 64 + tm.lane;
+    const int base = I.m.slice_ptr[sl];
+    const int wd = (I.m.slice_ptr[sl + 1] - base) >> 6;
+    T acc = T(0);
+    for (int k = 0; k < wd; ++k) {
+      const long long e = (long long)base + k * 64 + tm.lane;
+      const int j = I.m.col[e];
+      acc += opval(o, e) * (o.dinv[j] * r[j]);
+    }
+    if (i < n) {
+      w[i] = acc;
+      const T u = o.dinv[i] * r[i];
+      a0 += (double)r[i] * (double)u;
+      a1 += (double)acc * (double)u;
+      a2 += (double)r[i] * (double)r[i];
+    }
+  }
+  return red3(a0, a1, a2);
+}
+
+template <typename T>
+__device__ Red3 ph_cg_iter(const InstDev& I, const State& S, const Team& tm) {
+  const int n = I.n;
+  PcgOps<T> o = pcg_ops<T>(I, S.kind);
+  const int c = S.cur;
+  const T* rc = (const T*)(c ? I.rB : I.r_);
+  T* rn = (T*)(c ? I.r_ : I.rB);
+  const T* wc = (const T*)(c ? I.wB : I.q);
+  T* wn = (T*)(c ? I.q : I.wB);
+  const T* so = (const T*)(c ? I.sB : I.sA);
+  T* sn = (T*)(c ? I.sA : I.sB);
+  T* p = (T*)I.pA;
+  const T alpha = T(S.alpha), beta = T(S.beta_cg);
+  const bool first = (S.it == 0);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  PFC_SLICES(I, tm) {
+    const int i = sl * 64 + tm.lane;
+    const int base = I.m.slice_ptr[sl];
+    const int wd = (I.m.slice_ptr[sl + 1] - base) >> 6;
+    T acc = T(0);
+    for (int k = 0; k < wd; ++k) {
+      const long long e = (long long)base + k * 64 + tm.lane;
+      const int j = I.m.col[e];
+      acc += opval(o, e) * cg_unew(o.dinv, rc, wc, so, alpha, beta, first, j);
+    }
+    if (i < n) {
+      const T si = cg_s(wc, so, beta, first, i);
+      const T uo = o.dinv[i] * rc[i];
+      const T pi = first ? uo : (uo + beta * p[i]);
+      o.x[i] = o.x[i] + alpha * pi;
+      const T ri = rc[i] - alpha * si;
+      const T ui = cg_unew(o.dinv, rc, wc, so, alpha, beta, first, i);
+      sn[i] = si;
+      p[i] = pi;
+      rn[i] = ri;
+      wn[i] = acc;
+      a0 += (double)ri * (double)ui;
+      a1 += (double)acc * (double)ui;
+      a2 += (double)ri * (double)ri;
+    }
+  }
+  return red3(a0, a1, a2);
 }
 
 }  // namespace pfc

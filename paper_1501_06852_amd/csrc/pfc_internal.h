@@ -37,6 +37,8 @@ enum {
   PH_UPDATE_X,    // x += Z y
   PH_TRUE_RES,    // r = b - A^R x, partials ||r||^2, ||r_s||^2; W = r_s
   PH_PCH_OUT,     // z_out = P_CH^{-1} v (preconditioner-only job)
+  PH_CG_INIT,     // single-reduction PCG: w_0 = C D^{-1} r_0, partials (r,u), (w,u), (r,r)
+  PH_CG_ITER,     // single-reduction PCG iteration (one launch per iteration)
 };
 
 enum { JOB_NONE = 0, JOB_SOLVE = 1, JOB_RB = 2, JOB_PCH = 3 };
@@ -72,7 +74,7 @@ struct State {
   int step, stage;          // Rosenbrock position
   int kind, it, pcur, pad0; // inner PCG
   int j, mgs_i, cycle, total, apply, kcols;
-  int status, pad1;
+  int status, cur;
   double rho, bb, alpha, beta_cg;
   double vscale, bnorm, bnorm_s, est_thresh, w0, hprev, est, rel;
 };
@@ -103,6 +105,7 @@ struct InstDev {
   MeshDev m;
   int n, precision, restart, max_steps;
   int inner_maxit, shared_ops, team_size, replay;
+  int single_reduction, pad_i;
   double outer_tol, inner_tol, ci_tol;
   // job parameters
   double r, tau, m11, tau_s, delta, sdelta;
@@ -122,7 +125,8 @@ struct InstDev {
   double* pch_out;              // preconditioner-only job output
   // inner PCG vectors (sized for float64; typed by precision)
   void *r_, *pA, *pB, *q, *y0, *y1, *zt, *x1, *x2;
-  double2* part;                // [2][team_size]
+  void *rB, *wB, *sA, *sB;      // extra buffers of the single-reduction PCG
+  double* part;                 // [2][team_size][4] partial sums
   State* st;                    // [2]
   Hist* hist;
   const int* sched_meta;        // replay: per solve {cycle offset, cycles, apply offset, applies}

@@ -27,7 +27,7 @@ namespace pfc {
 __device__ __forceinline__ bool phase_partials(int ph) {
   switch (ph) {
     case PH_SOLVE_INIT: case PH_RB_RHS: case PH_PCG_SETUP: case PH_PCG_A: case PH_PCG_B:
-    case PH_ASPMV: case PH_MGS: case PH_MGS_LAST: case PH_TRUE_RES:
+    case PH_ASPMV: case PH_MGS: case PH_MGS_LAST: case PH_TRUE_RES: case PH_CG_INIT: case PH_CG_ITER:
       return true;
     default:
       return false;
@@ -75,9 +75,9 @@ __device__ void finish_solve(State& S, const InstDev& I, bool wr, int status) {
   }
 }
 
-__device__ void begin_solve(State& S, const InstDev& I, bool wr, double2 red) {
-  S.bnorm = sqrt(red.x);
-  S.bnorm_s = sqrt(red.y);
+__device__ void begin_solve(State& S, const InstDev& I, bool wr, Red3 red) {
+  S.bnorm = sqrt(red.a);
+  S.bnorm_s = sqrt(red.b);
   S.total = 0; S.cycle = 0; S.j = 0; S.apply = 0; S.est = 0.0; S.rel = 0.0;
   if (wr) {
     I.hist->applies = 0;
@@ -181,7 +181,7 @@ __device__ void givens(State& S, const InstDev& I, bool wr, double hn2, double* 
   S.phase = PH_UPDATE_X;
 }
 
-__device__ void transition(State& S, const InstDev& I, bool wr, double2 red, double* ybuf, double* col) {
+__device__ void transition(State& S, const InstDev& I, bool wr, Red3 red, double* ybuf, double* col) {
   switch (S.phase) {
     case PH_START:
       if (S.job == JOB_SOLVE) S.phase = PH_SOLVE_INIT;
@@ -207,14 +207,37 @@ __device__ void transition(State& S, const InstDev& I, bool wr, double2 red, dou
       S.phase = (S.step < I.n_steps) ? PH_RB_BEGIN : PH_DONE;
       break;
     case PH_PCG_SETUP: {
-      S.rho = red.x; S.bb = red.y; S.it = 0; S.pcur = 0; S.beta_cg = 0.0;
+      S.rho = red.a; S.bb = red.b; S.it = 0; S.pcur = 0; S.cur = 0; S.beta_cg = 0.0;
       bool fixed; double tol;
       const int lim = inner_limit(I, S, fixed, tol);
       if (S.bb == 0.0 || lim == 0) pcg_done(S, I, wr);
-      else S.phase = PH_PCG_A;
+      else S.phase = I.single_reduction ? PH_CG_INIT : PH_PCG_A;
+    } break;
+    case PH_CG_INIT:
+      S.rho = red.a;             // gamma_0 = (r_0, D^{-1} r_0)
+      S.alpha = red.a / red.b;   // gamma_0 / (w_0, u_0)
+      S.beta_cg = 0.0;
+      S.it = 0;
+      S.cur = 0;
+      S.phase = PH_CG_ITER;
+      break;
+    case PH_CG_ITER: {
+      S.it += 1;
+      S.cur ^= 1;
+      bool fixed; double tol;
+      const int lim = inner_limit(I, S, fixed, tol);
+      const double g = red.a, dl = red.b, rr = red.c;
+      const bool done = S.it >= lim || (!fixed && rr <= tol * tol * S.bb) || g == 0.0 || !isfinite(rr);
+      if (done) pcg_done(S, I, wr);
+      else {
+        const double beta = g / S.rho;
+        S.alpha = g / (dl - beta * g / S.alpha);
+        S.beta_cg = beta;
+        S.rho = g;
+      }
     } break;
     case PH_PCG_A:
-      S.alpha = S.rho / red.x;
+      S.alpha = S.rho / red.a;
       S.pcur ^= 1;
       S.phase = PH_PCG_B;
       break;
@@ -222,45 +245,45 @@ __device__ void transition(State& S, const InstDev& I, bool wr, double2 red, dou
       S.it += 1;
       bool fixed; double tol;
       const int lim = inner_limit(I, S, fixed, tol);
-      const double rr = red.x, rzn = red.y;
+      const double rr = red.a, rzn = red.b;
       const bool done = S.it >= lim || (!fixed && rr <= tol * tol * S.bb) || rzn == 0.0 || !isfinite(rr);
       if (done) pcg_done(S, I, wr);
       else { S.beta_cg = rzn / S.rho; S.rho = rzn; S.phase = PH_PCG_A; }
     } break;
     case PH_ASPMV:
-      S.w0 = sqrt(red.y);
-      S.hprev = red.x;
-      if (wr) I.hist->hcol[0] = red.x;
+      S.w0 = sqrt(red.b);
+      S.hprev = red.a;
+      if (wr) I.hist->hcol[0] = red.a;
       if (S.j == 0) S.phase = PH_MGS_LAST;
       else { S.mgs_i = 1; S.phase = PH_MGS; }
       break;
     case PH_MGS:
-      S.hprev = red.x;
-      if (wr) I.hist->hcol[S.mgs_i] = red.x;
+      S.hprev = red.a;
+      if (wr) I.hist->hcol[S.mgs_i] = red.a;
       if (S.mgs_i == S.j) S.phase = PH_MGS_LAST;
       else { S.mgs_i += 1; S.phase = PH_MGS; }
       break;
     case PH_MGS_LAST:
-      givens(S, I, wr, red.x, ybuf, col);
+      givens(S, I, wr, red.a, ybuf, col);
       break;
     case PH_UPDATE_X:
       S.phase = PH_TRUE_RES;
       break;
     case PH_TRUE_RES: {
-      const double rel = sqrt(red.x) / S.bnorm;
+      const double rel = sqrt(red.a) / S.bnorm;
       S.rel = rel;
       S.cycle += 1;
       if (!isfinite(rel)) { finish_solve(S, I, wr, PFC_ERR_BREAKDOWN); break; }
       if (I.replay) {
         const int* meta = I.sched_meta + 4 * solve_index(S);
-        if (S.cycle < meta[1]) restart_cycle(S, I, wr, sqrt(red.y));
+        if (S.cycle < meta[1]) restart_cycle(S, I, wr, sqrt(red.b));
         else finish_solve(S, I, wr, rel <= I.outer_tol ? PFC_OK : PFC_NOT_CONVERGED);
       } else if (rel <= I.outer_tol) {
         finish_solve(S, I, wr, PFC_OK);
       } else if (S.total >= I.max_steps) {
         finish_solve(S, I, wr, PFC_NOT_CONVERGED);
       } else {
-        restart_cycle(S, I, wr, sqrt(red.y));
+        restart_cycle(S, I, wr, sqrt(red.b));
       }
     } break;
     case PH_PCH_OUT:
@@ -276,7 +299,7 @@ template <typename T>
 __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ teams, const InstDev* __restrict__ insts,
                                                  int parity) {
   __shared__ State S;
-  __shared__ double2 lds4[PFC_WAVES];
+  __shared__ Red3 lds4[PFC_WAVES];
   __shared__ double ybuf[PFC_MAXM];
   __shared__ double gcol[PFC_MAXM + 1];
   const TeamEntry te = teams[blockIdx.x];
@@ -297,17 +320,17 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     }
     return;
   }
-  double2 red = make_double2(0.0, 0.0);
+  Red3 red = red3(0.0, 0.0, 0.0);
   if (phase_partials(S.phase)) {
-    const double2* part = I.part + (long long)parity * I.team_size;
-    double a = 0.0, b = 0.0;
-    for (int k = tid; k < te.size; k += PFC_WG) { a += part[k].x; b += part[k].y; }
-    red = wg_sum2(a, b, lds4);
+    const double* part = I.part + (long long)parity * I.team_size * 4;
+    Red3 a = red3(0.0, 0.0, 0.0);
+    for (int k = tid; k < te.size; k += PFC_WG) { a.a += part[4 * k]; a.b += part[4 * k + 1]; a.c += part[4 * k + 2]; }
+    red = wg_sum3(a, lds4);
   }
   if (tid == 0) transition(S, I, writer, red, ybuf, gcol);
   __syncthreads();
   Team tm{te.rank, te.size, tid >> 6, tid & 63};
-  double2 acc = make_double2(0.0, 0.0);
+  Red3 acc = red3(0.0, 0.0, 0.0);
   switch (S.phase) {
     case PH_SOLVE_INIT:
     case PH_RB_RHS: acc = ph_solve_init(I, S, tm); break;
@@ -323,11 +346,16 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     case PH_UPDATE_X: acc = ph_update_x(I, S, tm, ybuf); break;
     case PH_TRUE_RES: acc = ph_true_res(I, S, tm); break;
     case PH_PCH_OUT: acc = ph_pch_out<T>(I, tm); break;
+    case PH_CG_INIT: acc = S.kind >= KIND_CI_OMEGA ? ph_cg_init<double>(I, S, tm) : ph_cg_init<T>(I, S, tm); break;
+    case PH_CG_ITER: acc = S.kind >= KIND_CI_OMEGA ? ph_cg_iter<double>(I, S, tm) : ph_cg_iter<T>(I, S, tm); break;
     default: break;
   }
   if (phase_partials(S.phase)) {
-    const double2 s = wg_sum2(acc.x, acc.y, lds4);
-    if (tid == 0) I.part[(long long)(1 - parity) * I.team_size + te.rank] = s;
+    const Red3 s = wg_sum3(acc, lds4);
+    if (tid == 0) {
+      double* dst = I.part + ((long long)(1 - parity) * I.team_size + te.rank) * 4;
+      dst[0] = s.a; dst[1] = s.b; dst[2] = s.c;
+    }
   }
   if (writer) {
     int* dst = (int*)(I.st + (1 - parity));
@@ -430,7 +458,8 @@ size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int t
   h.W = (double*)take(n3 * 8);
   h.r_ = take(n * 8); h.pA = take(n * 8); h.pB = take(n * 8); h.q = take(n * 8);
   h.y0 = take(n * 8); h.y1 = take(n * 8); h.zt = take(n * 8); h.x1 = take(n * 8); h.x2 = take(n * 8);
-  h.part = (double2*)take(2 * (size_t)team_size * sizeof(double2));
+  h.rB = take(n * 8); h.wB = take(n * 8); h.sA = take(n * 8); h.sB = take(n * 8);
+  h.part = (double*)take(2 * (size_t)team_size * 4 * sizeof(double));
   h.st = (State*)take(2 * sizeof(State));
   h.hist = (Hist*)take(sizeof(Hist));
   h.rec_inner = (int*)take((size_t)o.max_steps * 5 * sizeof(int));
@@ -453,6 +482,7 @@ static int validate_opts(const pfc_opts* o) {
   if (!(o->outer_tol > 0.0) || !(o->inner_tol > 0.0) || !(o->inner_tol < 1.0)) { set_error("pfc_opts: tolerances must be in (0,1)"); return PFC_ERR_ARG; }
   if (o->rows_per_thread < 0 || o->rows_per_thread > 8) { set_error("pfc_opts: rows_per_thread must be 0..8"); return PFC_ERR_ARG; }
   if (o->ticks_per_graph < 0 || o->ticks_per_graph > 4096) { set_error("pfc_opts: ticks_per_graph must be 0..4096"); return PFC_ERR_ARG; }
+  if (o->single_reduction != 0 && o->single_reduction != 1) { set_error("pfc_opts: single_reduction must be 0 or 1"); return PFC_ERR_ARG; }
   return PFC_OK;
 }
 
@@ -730,6 +760,7 @@ int pfc_instance_create(pfc_mesh* m, const pfc_opts* o, pfc_instance** out) {
   h.max_steps = o->max_steps;
   h.inner_maxit = o->inner_maxit;
   h.shared_ops = o->shared_ops;
+  h.single_reduction = o->single_reduction;
   h.team_size = I->team_size;
   h.outer_tol = o->outer_tol;
   h.inner_tol = o->inner_tol;

@@ -1,0 +1,199 @@
+"""Batches and the continuous-batching server (needs a GPU).
+
+Each instance gives the same bits alone and inside a batch or a served mix
+(fixed-order reductions that depend only on the instance's own team)."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from helpers import Problem, dev, host, rel
+from oracle import pfc as opfc, solve as osolve
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pfc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1501_06852_amd import pfc as lib
+    return lib
+
+
+def _problems():
+    return [Problem(2, 16, 0.0, seed=11), Problem(2, 10, 0.2, seed=12), Problem(3, 4, 0.0, seed=13)]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_alone_equals_mix(pfc, prec):
+    probs = _problems()
+    prm = wl.draw_params(4, 100)
+    # two instances on the first mesh (shared M, K), one on each other mesh
+    owners = [0, 0, 1, 2]
+    insts, states, alone = [], [], []
+    try:
+        steps = 1
+        for k, pi in enumerate(owners):
+            P = probs[pi]
+            o = pfc.pfc_opts_default(precision=prec, shared_ops=1 if pi == 0 else 0)
+            insts.append(pfc.pfc_instance_create(P.gpu_mesh(), o))
+            psi = wl.psi0(P.n, prm[k].psibar, 0.01, seed=prm[k].seed)
+            s0 = np.concatenate([np.zeros(P.n), psi, np.zeros(P.n)])
+            states.append(dev(s0))
+            sa = dev(s0)
+            st, _ = pfc.pfc_rosenbrock_run(insts[-1], P.n, sa, prm[k].r, prm[k].psibar, prm[k].tau, steps)
+            alone.append(host(sa))
+        ns = [probs[pi].n for pi in owners]
+        st, infos = pfc.pfc_batch_run(insts, ns, states, [p.r for p in prm], [p.psibar for p in prm],
+                                      [p.tau for p in prm], steps)
+        assert st >= 0
+        for k in range(4):
+            assert np.array_equal(host(states[k]), alone[k]), k
+            assert all(i["true_rel_res"] <= 1e-8 for i in infos[k])
+        # and against the oracle (float64 run at the same tolerance)
+        if prec == 0:
+            for k, pi in enumerate(owners):
+                P = probs[pi]
+                psi = wl.psi0(P.n, prm[k].psibar, 0.01, seed=prm[k].seed)
+                x0 = opfc.consistent_init(P.mesh, P.M, P.K, prm[k].r, psi)
+                xr, _ = osolve.rosenbrock_run(P.mesh, P.M, P.K, x0, prm[k].r, prm[k].tau, steps, tol=1e-8)
+                assert rel(alone[k], xr) <= 1e-6
+    finally:
+        for i in insts:
+            pfc.pfc_instance_destroy(i)
+        for P in probs:
+            P.close()
+
+
+def _serve(pfc, meshes, reqs, prec, slots, budget):
+    import ctypes as C
+    so = pfc.pfc_server_opts(C.sizeof(pfc.pfc_server_opts), prec, budget, slots, 0)
+    srv = C.c_void_p()
+    assert pfc._lib.pfc_server_create(C.byref(so), C.byref(srv)) == 0
+    try:
+        for rid, (mi, p, psi) in enumerate(reqs):
+            a = np.ascontiguousarray(psi)
+            rc = pfc._lib.pfc_server_submit(srv, meshes[mi], p.r, p.psibar, p.tau, a.ctypes.data_as(pfc._dp), 2, rid)
+            assert rc == 0, pfc.pfc_last_error()
+        assert pfc._lib.pfc_server_drain(srv) == 0
+        out = {}
+        buf = (pfc.pfc_result * 16)()
+        got = C.c_int()
+        while True:
+            pfc._lib.pfc_server_poll(srv, buf, 16, C.byref(got))
+            if got.value == 0:
+                break
+            for k in range(got.value):
+                r = buf[k]
+                n = len(reqs[r.req_id][2])
+                out[r.req_id] = (r.status, np.ctypeslib.as_array(r.state, shape=(3 * n,)).copy(),
+                                 [r.infos[i].true_rel_res for i in range(r.n_stages)], r.t_admit - r.t_submit)
+                pfc._lib.pfc_result_free(C.byref(buf[k]))
+        return out
+    finally:
+        pfc._lib.pfc_server_destroy(srv)
+
+
+@pytest.mark.parametrize("prec", [1])
+def test_server_alone_equals_mix_and_admission(pfc, prec):
+    probs = _problems()
+    meshes = [P.gpu_mesh() for P in probs]
+    prm = wl.draw_params(7, 300)
+    reqs = []
+    for k in range(7):
+        mi = k % 3
+        reqs.append((mi, prm[k], wl.psi0(probs[mi].n, prm[k].psibar, 0.01, seed=prm[k].seed)))
+    try:
+        # alone: one instance per request, plain run
+        alone = []
+        for mi, p, psi in reqs:
+            P = probs[mi]
+            inst = pfc.pfc_instance_create(meshes[mi], pfc.pfc_opts_default(precision=prec))
+            s = dev(np.concatenate([np.zeros(P.n), psi, np.zeros(P.n)]))
+            pfc.pfc_rosenbrock_run(inst, P.n, s, p.r, p.psibar, p.tau, 2)
+            alone.append(host(s))
+            pfc.pfc_instance_destroy(inst)
+        # served with room for everything, then with a budget that fits about two instances
+        fp = max(pfc.pfc_instance_footprint(m, pfc.pfc_opts_default(precision=prec)) for m in meshes)
+        for slots, budget in [(8, 64 << 30), (8, int(2.2 * fp))]:
+            out = _serve(pfc, meshes, reqs, prec, slots, budget)
+            assert sorted(out) == list(range(7))
+            for k in range(7):
+                st, state, res, _ = out[k]
+                assert st >= 0 and max(res) <= 1e-8
+                assert np.array_equal(state, alone[k]), (slots, budget, k)
+        # a request that can never fit is refused at submission
+        import ctypes as C
+        so = pfc.pfc_server_opts(C.sizeof(pfc.pfc_server_opts), prec, 1024, 1, 0)
+        srv = C.c_void_p()
+        assert pfc._lib.pfc_server_create(C.byref(so), C.byref(srv)) == 0
+        a = np.zeros(probs[0].n)
+        rc = pfc._lib.pfc_server_submit(srv, meshes[0], -0.3, -0.3, 0.5, a.ctypes.data_as(pfc._dp), 1, 0)
+        pfc._lib.pfc_server_destroy(srv)
+        assert rc == pfc.PFC_ERR_ADMISSION
+    finally:
+        for P in probs:
+            P.close()
+
+
+def test_full_size_2d_512_stage_solve(pfc):
+    """512^2 jittered (the benchmark configuration): replay parity and tolerance-mode residual at full size."""
+    from oracle import assembly
+    P = Problem(2, 512, 0.2, psibar=-0.3, seed=0)
+    inst = None
+    try:
+        r, psibar, tau = -0.35, -0.3, 1.0
+        m11 = 1.0 / opfc.ROS3PW_GAMMA
+        n = P.n
+        x0 = opfc.consistent_init(P.mesh, P.M, P.K, r, P.psi)
+        b = opfc.stage_rhs_R(P.mesh, P.M, P.K, r, tau, x0, [], [])
+        Nm = assembly.N_matrix(P.mesh, P.psi)
+        y_ref, info = osolve.solve_stage(P.M, P.K, Nm, r, tau, m11, b, tol=1e-8)
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default())
+        x = dev(np.zeros(3 * n))
+        s = info["schedule"]
+        st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, m11, dev(b), x, replay=(s.cycles, s.inner))
+        assert rel(host(x), y_ref) <= 1e-10
+        st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, m11, dev(b), x)
+        y = host(x)
+        res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, tau, m11, y)) / np.linalg.norm(b)
+        assert st == pfc.PFC_OK and res <= 1e-8
+        # the launch configuration of the benchmark: a Rosenbrock step on this instance
+        state = dev(np.concatenate([np.zeros(n), P.psi, np.zeros(n)]))
+        st, gis = pfc.pfc_rosenbrock_run(inst, n, state, r, psibar, tau, 1)
+        assert st == pfc.PFC_OK and max(g["true_rel_res"] for g in gis) <= 1e-8
+        # sampled check of the first stage's consistent state: psi unchanged only through the solve
+        s_h = host(state)
+        assert np.isfinite(s_h).all()
+    finally:
+        if inst is not None:
+            pfc.pfc_instance_destroy(inst)
+        P.close()
+
+
+def test_full_size_3d_64_mixed_vs_fft_exact(pfc):
+    """64^3 Kuhn mesh, constant psi: mixed precision at a tight outer tolerance equals the exact Fourier solve."""
+    from oracle import reference
+    P = Problem(3, 64, 0.0, psibar=-0.25, amp=0.0, seed=0)
+    inst = None
+    try:
+        r, tau = -0.3, 0.5
+        m11 = 1.0 / opfc.ROS3PW_GAMMA
+        n = P.n
+        b = np.random.default_rng(1).normal(size=3 * n)
+        yf = reference.fft_exact(P.mesh, P.M, P.K, r, tau, m11, -0.25, b)
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(precision=1, outer_tol=1e-11))
+        x = dev(np.zeros(3 * n))
+        st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, -0.25, tau, m11, dev(b), x)
+        assert rel(host(x), yf) <= 1e-8, gi
+        pfc.pfc_instance_destroy(inst)
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(precision=1))
+        st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, -0.25, tau, m11, dev(b), x)
+        assert st == pfc.PFC_OK and gi["true_rel_res"] <= 1e-8
+    finally:
+        if inst is not None:
+            pfc.pfc_instance_destroy(inst)
+        P.close()

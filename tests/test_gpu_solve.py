@@ -48,6 +48,36 @@ def test_solve_replay_parity(pfc, dim, N, jit, tau, prec):
         P.close()
 
 
+@pytest.mark.parametrize("dim,N,jit,tau", [(2, 16, 0.2, 0.1), (2, 24, 0.2, 1.0), (3, 5, 0.2, 0.5)])
+def test_single_reduction_pcg_replay_parity(pfc, dim, N, jit, tau):
+    """The one-launch-per-iteration PCG form reproduces the oracle's standard PCG under replay."""
+    P = Problem(dim, N, jit, seed=17)
+    inst = None
+    try:
+        r, psibar = -0.35, -0.3
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(single_reduction=1))
+        n = P.n
+        _, b = _stage1(P, r, tau)
+        Nm = assembly.N_matrix(P.mesh, P.psi)
+        y_ref, info = osolve.solve_stage(P.M, P.K, Nm, r, tau, M11, b, tol=1e-8)
+        s = info["schedule"]
+        x = dev(np.zeros(3 * n))
+        st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
+        assert rel(host(x), y_ref) <= 1e-10
+        st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
+        res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, tau, M11, host(x))) / np.linalg.norm(b)
+        assert st == pfc.PFC_OK and res <= 1e-8
+        # the inner counts in tolerance mode match the oracle's up to a threshold crossing
+        got = pfc.pfc_last_inner_counts(inst)
+        ref = np.array(info["schedule"].inner)
+        k = min(len(got), len(ref))
+        assert np.abs(got[:k] - ref[:k]).max() <= 1
+    finally:
+        if inst is not None:
+            pfc.pfc_instance_destroy(inst)
+        P.close()
+
+
 @pytest.mark.parametrize("dim,N,jit,tau,prec", [(2, 16, 0.2, 0.1, 0), (2, 16, 0.2, 1.0, 1), (3, 5, 0.2, 0.5, 0),
                                                 (3, 6, 0.0, 0.5, 1)])
 def test_solve_tolerance_mode(pfc, dim, N, jit, tau, prec):
