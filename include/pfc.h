@@ -242,6 +242,22 @@ int pfc_rosenbrock_run(pfc_instance* inst, double* state, double r, double psiba
                        int n_steps, int init, const pfc_schedule* replays,
                        pfc_solve_info* per_stage, void* stream);
 
+/* Adaptive Ros3Pw run from t = 0 to t_end (Section 3.1: embedded solution
+ * x_hat = x_k + sum mhat_j y_j of Table rosenbrock_scheme, order 2).  After each
+ * step, err = RMS over the psi block of (psi_{k+1} - psi_hat) / (atol + rtol
+ * max(|psi_k|, |psi_{k+1}|)); the step is accepted if err <= 1 (otherwise the
+ * state is restored), and tau <- tau * min(5, max(0.2, 0.9 err^(-1/3))).  The
+ * last step is shortened to end at t_end.
+ *   state       device float64 [3n], in/out
+ *   tau0        first trial step; max_attempts caps accepted + rejected steps
+ *   taus        host array of capacity max_attempts: accepted step sizes in order
+ *   n_accepted, n_rejected  host outputs
+ * Returns PFC_NOT_CONVERGED if t_end was not reached within max_attempts, a
+ * negative code on failure, otherwise the worst stage-solve status. */
+int pfc_rosenbrock_adaptive(pfc_instance* inst, double* state, double r, double psibar, double tau0, double t_end,
+                            double rtol, double atol, int max_attempts, int init, double* taus, int* n_accepted,
+                            int* n_rejected, void* stream);
+
 /* Operator-level entry points of the hot path (device pointers). */
 /* out = A^R y with N(psi_k) reassembled from psi_k; y, out [3n]. */
 int pfc_apply_AR(pfc_instance* inst, const double* psi_k, double r, double tau, double m11,

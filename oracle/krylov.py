@@ -69,7 +69,7 @@ class Schedule:
 
 def fgmres(apply_A, apply_P, b, tol=1e-8, restart=30, max_steps=1000,
            true_residual=None, est_scale=1.0, replay: Schedule | None = None,
-           breakdown_tol=1e-14):
+           breakdown_tol=1e-14, record=None):
     """Right-preconditioned FGMRES(restart) with modified Gram-Schmidt, x_0 = 0.
 
     A cycle ends when the Givens estimate |g_{j+1}| <= tol*||b||*est_scale,
@@ -78,7 +78,8 @@ def fgmres(apply_A, apply_P, b, tol=1e-8, restart=30, max_steps=1000,
     x += Z y, and the true relative residual (true_residual(x), default
     ||b - A x|| / ||b||) decides convergence; otherwise the next cycle
     starts from r = b - A x.  With `replay`, cycle lengths follow the record
-    and no early stop happens.
+    and no early stop happens.  With `record` (a list), the first cycle's
+    V, Z and unrotated Hessenberg matrix are appended to it.
 
     Returns (x, info) with info = dict(steps, cycles, rel_res, est, converged).
     """
@@ -105,6 +106,7 @@ def fgmres(apply_A, apply_P, b, tol=1e-8, restart=30, max_steps=1000,
         V = [r / beta]
         Z = []
         H = np.zeros((m + 1, m))
+        Hraw = np.zeros((m + 1, m))
         cs = np.zeros(m)
         sn = np.zeros(m)
         g = np.zeros(m + 1)
@@ -122,6 +124,8 @@ def fgmres(apply_A, apply_P, b, tol=1e-8, restart=30, max_steps=1000,
                 w = w - H[i, j] * V[i]
             hn = float(np.linalg.norm(w))
             H[j + 1, j] = hn
+            if record is not None and cyc == 0:
+                Hraw[:j + 2, j] = H[:j + 2, j]
             for i in range(j):  # earlier rotations
                 t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
                 H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
@@ -151,6 +155,8 @@ def fgmres(apply_A, apply_P, b, tol=1e-8, restart=30, max_steps=1000,
             y[i] = (g[i] - H[i, i + 1:k] @ y[i + 1:k]) / H[i, i]
         for i in range(k):
             x += y[i] * Z[i]
+        if record is not None and cyc == 0:
+            record.append((list(V), list(Z), Hraw[:k + 1, :k].copy()))
         info["cycles"].append(k)
         info["est"] = abs(g[k]) / nb
         cyc += 1

@@ -53,6 +53,23 @@ __device__ __forceinline__ Red3 wg_sum3(Red3 v, Red3* lds4) {
   const int _send = min(_sbeg + _spw, (I).m.n_slices);                              \
   for (int sl = _sbeg + (tm).wave; sl < _send; sl += PFC_WAVES)
 
+// Row loops over the entries of a slice: the P1 meshes of this solver have 7
+// (2D) or 15 (3D) entries per row; for those widths the loop is unrolled (fully
+// for 7, in chunks of 5 for 15, to stay within the register budget) so that a
+// wave issues the index, value and gather loads of many entries at once.
+template <typename F>
+__device__ __forceinline__ void for_width(int w, F f) {
+  if (w == 7) {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) f(k);
+  } else if (w == 15) {
+#pragma unroll 5
+    for (int k = 0; k < 15; ++k) f(k);
+  } else {
+    for (int k = 0; k < w; ++k) f(k);
+  }
+}
+
 // ---- typed views ----------------------------------------------------------
 template <typename T> struct TV;
 template <> struct TV<double> {
@@ -274,10 +291,10 @@ __device__ __forceinline__ T row_dot(const InstDev& I, int sl, int lane, const T
   const int base = I.m.slice_ptr[sl];
   const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
   T acc = T(0);
-  for (int k = 0; k < w; ++k) {
+  for_width(w, [&](int k) {
     const long long e = (long long)base + k * 64 + lane;
     acc += A[e] * v(I.m.col[e]);
-  }
+  });
   return acc;
 }
 
@@ -388,11 +405,11 @@ __device__ Red3 ph_pcg_a(const InstDev& I, const State& S, const Team& tm) {
     const int base = I.m.slice_ptr[sl];
     const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
     T acc = T(0);
-    for (int k = 0; k < w; ++k) {
+    for_width(w, [&](int k) {
       const long long e = (long long)base + k * 64 + tm.lane;
       const int j = I.m.col[e];
       acc += opval(o, e) * pval(o.dinv, r, pold, beta, first, j);
-    }
+    });
     if (i < n) {
       const T pi = pval(o.dinv, r, pold, beta, first, i);
       pnew[i] = pi;
@@ -439,7 +456,7 @@ __device__ __forceinline__ void block_row(const InstDev& I, int sl, int lane, do
   const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
   const double c1 = -(1.0 + I.r);
   w0 = w1 = w2 = 0.0;
-  for (int k = 0; k < w; ++k) {
+  for_width(w, [&](int k) {
     const long long e = (long long)base + k * 64 + lane;
     const int j = I.m.col[e];
     const double Mv = I.m.M[e], Kv = I.m.K[e], Nv = I.N[e];
@@ -448,7 +465,7 @@ __device__ __forceinline__ void block_row(const InstDev& I, int sl, int lane, do
     w0 += Mv * mu + (c1 * Mv + 2.0 * Kv + Nv) * ps + Kv * om;
     w1 += t * Kv * mu + s * Mv * ps;
     w2 += Kv * ps + Mv * om;
-  }
+  });
 }
 
 template <typename T>
@@ -587,11 +604,11 @@ __device__ Red3 ph_cg_init(const InstDev& I, const State& S, const Team& tm) {
     const int base = I.m.slice_ptr[sl];
     const int wd = (I.m.slice_ptr[sl + 1] - base) >> 6;
     T acc = T(0);
-    for (int k = 0; k < wd; ++k) {
+    for_width(wd, [&](int k) {
       const long long e = (long long)base + k * 64 + tm.lane;
       const int j = I.m.col[e];
       acc += opval(o, e) * (o.dinv[j] * r[j]);
-    }
+    });
     if (i < n) {
       w[i] = acc;
       const T u = o.dinv[i] * r[i];
@@ -623,11 +640,11 @@ __device__ Red3 ph_cg_iter(const InstDev& I, const State& S, const Team& tm) {
     const int base = I.m.slice_ptr[sl];
     const int wd = (I.m.slice_ptr[sl + 1] - base) >> 6;
     T acc = T(0);
-    for (int k = 0; k < wd; ++k) {
+    for_width(wd, [&](int k) {
       const long long e = (long long)base + k * 64 + tm.lane;
       const int j = I.m.col[e];
       acc += opval(o, e) * cg_unew(o.dinv, rc, wc, so, alpha, beta, first, j);
-    }
+    });
     if (i < n) {
       const T si = cg_s(wc, so, beta, first, i);
       const T uo = o.dinv[i] * rc[i];

@@ -12,8 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define PFC_WG 256
-#define PFC_WAVES 4
+#define PFC_WG 1024
+#define PFC_WAVES 16
 #define PFC_SLICE 64
 #define PFC_MAXM 32
 #define PFC_NSTEPS_P 5
@@ -123,6 +123,8 @@ struct InstDev {
   double* Z;                    // [restart][3n]
   double* W;                    // [3n]
   double* pch_out;              // preconditioner-only job output
+  double* xbak;                 // [3n] state before an adaptive step attempt
+  double* errpart;              // [n_slices] partial sums of the embedded error
   // inner PCG vectors (sized for float64; typed by precision)
   void *r_, *pA, *pB, *q, *y0, *y1, *zt, *x1, *x2;
   void *rB, *wB, *sA, *sB;      // extra buffers of the single-reduction PCG
@@ -150,3 +152,6 @@ struct TeamEntry { int inst, rank, size, pad; };
 #define ROS_M1 1.63397459621556
 #define ROS_M2 0.294228634059948
 #define ROS_M3 1.07179676972449
+#define ROS_MH1 1.99444650053487
+#define ROS_MH2 0.654700538379252
+#define ROS_MH3 1.07179676972449

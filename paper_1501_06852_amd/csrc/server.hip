@@ -154,10 +154,10 @@ int rebuild(pfc_server* S) {
   for (Request* q : S->active) ts.push_back(q->inst->team_size);
   int rc = S->grp.alloc(ts);
   if (rc) return rc;
+  for (size_t i = 0; i < S->active.size(); ++i) S->grp.h_descs[i] = S->active[i]->inst->h;
   const int ticks = S->o.ticks_per_graph > 0 ? S->o.ticks_per_graph : 64;
   rc = S->grp.build(S->active[0]->inst->capture, S->o.precision, ticks + (ticks & 1));
   if (rc) return rc;
-  for (size_t i = 0; i < S->active.size(); ++i) S->grp.h_descs[i] = S->active[i]->inst->h;
   PFC_HIP(hipMemcpyAsync(S->grp.d_descs, S->grp.h_descs, sizeof(InstDev) * S->active.size(), hipMemcpyHostToDevice,
                          S->stream));
   // only requests that just joined start from PH_START; the others continue

@@ -295,40 +295,79 @@ __device__ void transition(State& S, const InstDev& I, bool wr, Red3 red, double
   }
 }
 
-template <typename T>
+#ifdef PFC_TICK_TIMING
+// optional instrumentation (separate build only): wall-clock stamps of one workgroup per launch
+__device__ unsigned long long* g_trace = nullptr;
+__device__ unsigned long long g_trace_n = 0;
+__device__ unsigned long long g_trace_cap = 0;
+#define PFC_STAMP(v) unsigned long long v = wall_clock64()
+#else
+#define PFC_STAMP(v)
+#endif
+
+// One solver launch.  SINGLE: the launch serves one instance and receives its
+// state and partial-sum buffers as kernel arguments (preloaded into scalar
+// registers), so the first memory round trip already fetches the state.
+// Otherwise each workgroup looks up its team and instance descriptor.
+template <typename T, bool SINGLE>
 __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ teams, const InstDev* __restrict__ insts,
-                                                 int parity) {
+                                                 const State* st_in_arg, State* st_out_arg, const double* part_in_arg,
+                                                 double* part_out_arg, int parity) {
   __shared__ State S;
+  __shared__ InstDev sI;
   __shared__ Red3 lds4[PFC_WAVES];
   __shared__ double ybuf[PFC_MAXM];
   __shared__ double gcol[PFC_MAXM + 1];
-  const TeamEntry te = teams[blockIdx.x];
-  const InstDev& I = insts[te.inst];
+  PFC_STAMP(t_entry);
   const int tid = threadIdx.x;
-  {
-    const int* src = (const int*)(I.st + parity);
-    int* dst = (int*)&S;
-    for (int k = tid; k < (int)(sizeof(State) / 4); k += PFC_WG) dst[k] = src[k];
+  TeamEntry te;
+  const InstDev* gI;
+  const State* st_in;
+  State* st_out;
+  const double* part_in;
+  double* part_out;
+  if (SINGLE) {
+    te.inst = 0; te.rank = blockIdx.x; te.size = gridDim.x; te.pad = 0;
+    gI = insts;
+    st_in = st_in_arg; st_out = st_out_arg; part_in = part_in_arg; part_out = part_out_arg;
+  } else {
+    te = teams[blockIdx.x];
+    gI = insts + te.inst;
+    st_in = gI->st + parity; st_out = gI->st + (1 - parity);
+    part_in = gI->part + (long long)parity * te.size * 4;
+    part_out = gI->part + (long long)(1 - parity) * te.size * 4;
   }
+  // one round trip: partial sums of the previous launch, the state record and
+  // the instance descriptor, loaded by different threads at the same time
+  constexpr int NS = (int)(sizeof(State) / 4), ND = (int)(sizeof(InstDev) / 4);
+  static_assert(NS <= 64 && ND <= PFC_WG - 64, "state / descriptor too large for the staging threads");
+  Red3 pre = red3(0.0, 0.0, 0.0);
+  for (int k = tid; k < te.size; k += PFC_WG) { pre.a += part_in[4 * k]; pre.b += part_in[4 * k + 1]; pre.c += part_in[4 * k + 2]; }
+  if (tid < NS) ((int*)&S)[tid] = ((const int*)st_in)[tid];
+  else if (tid >= 64 && tid < 64 + ND) ((int*)&sI)[tid - 64] = ((const int*)gI)[tid - 64];
+  pre.a = wave_sum(pre.a);
+  pre.b = wave_sum(pre.b);
+  pre.c = wave_sum(pre.c);
+  if ((tid & 63) == 0) lds4[tid >> 6] = pre;
   __syncthreads();
+  const InstDev& I = sI;
   const bool writer = (te.rank == 0);
   if (S.phase == PH_DONE) {
-    if (writer) {
-      int* dst = (int*)(I.st + (1 - parity));
-      const int* src = (const int*)&S;
-      for (int k = tid; k < (int)(sizeof(State) / 4); k += PFC_WG) dst[k] = src[k];
-    }
+    if (writer && tid < NS) ((int*)st_out)[tid] = ((const int*)&S)[tid];
     return;
   }
-  Red3 red = red3(0.0, 0.0, 0.0);
-  if (phase_partials(S.phase)) {
-    const double* part = I.part + (long long)parity * I.team_size * 4;
-    Red3 a = red3(0.0, 0.0, 0.0);
-    for (int k = tid; k < te.size; k += PFC_WG) { a.a += part[4 * k]; a.b += part[4 * k + 1]; a.c += part[4 * k + 2]; }
-    red = wg_sum3(a, lds4);
+  if (tid == 0) {
+    Red3 red = red3(0.0, 0.0, 0.0);
+    if (phase_partials(S.phase)) {
+#pragma unroll
+      for (int w = 0; w < PFC_WAVES; ++w) { red.a += lds4[w].a; red.b += lds4[w].b; red.c += lds4[w].c; }
+    }
+    transition(S, I, writer, red, ybuf, gcol);
   }
-  if (tid == 0) transition(S, I, writer, red, ybuf, gcol);
   __syncthreads();
+  PFC_STAMP(t_trans);
+  // the new state is final: workgroup 0 stores it while the phase runs
+  if (writer && tid < NS) ((int*)st_out)[tid] = ((const int*)&S)[tid];
   Team tm{te.rank, te.size, tid >> 6, tid & 63};
   Red3 acc = red3(0.0, 0.0, 0.0);
   switch (S.phase) {
@@ -350,19 +389,50 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     case PH_CG_ITER: acc = S.kind >= KIND_CI_OMEGA ? ph_cg_iter<double>(I, S, tm) : ph_cg_iter<T>(I, S, tm); break;
     default: break;
   }
+  PFC_STAMP(t_work);
   if (phase_partials(S.phase)) {
-    const Red3 s = wg_sum3(acc, lds4);
+    acc.a = wave_sum(acc.a);
+    acc.b = wave_sum(acc.b);
+    acc.c = wave_sum(acc.c);
+    if ((tid & 63) == 0) lds4[tid >> 6] = acc;
+    __syncthreads();
     if (tid == 0) {
-      double* dst = I.part + ((long long)(1 - parity) * I.team_size + te.rank) * 4;
-      dst[0] = s.a; dst[1] = s.b; dst[2] = s.c;
+      Red3 r = red3(0.0, 0.0, 0.0);
+#pragma unroll
+      for (int w = 0; w < PFC_WAVES; ++w) { r.a += lds4[w].a; r.b += lds4[w].b; r.c += lds4[w].c; }
+      double* dst = part_out + (long long)te.rank * 4;
+      dst[0] = r.a; dst[1] = r.b; dst[2] = r.c;
     }
   }
-  if (writer) {
-    int* dst = (int*)(I.st + (1 - parity));
-    const int* src = (const int*)&S;
-    for (int k = tid; k < (int)(sizeof(State) / 4); k += PFC_WG) dst[k] = src[k];
+#ifdef PFC_TICK_TIMING
+  __syncthreads();
+  PFC_STAMP(t_exit);
+  const unsigned long long t_loaded = t_trans;
+  if (tid == 0 && (te.rank == 0 || te.rank == te.size - 1) && g_trace) {
+    const unsigned long long k = atomicAdd(&g_trace_n, 1ULL);
+    if (k < g_trace_cap) {
+      unsigned long long* r = g_trace + 8 * k;
+      r[0] = (unsigned long long)S.phase | ((unsigned long long)te.rank << 8) | ((unsigned long long)S.kind << 40);
+      r[1] = t_entry; r[2] = t_loaded; r[3] = t_trans; r[4] = t_work; r[5] = t_exit; r[6] = blockIdx.x; r[7] = 0;
+    }
   }
+#endif
 }
+
+#ifdef PFC_TICK_TIMING
+extern "C" int pfc_debug_trace(unsigned long long* dev_buf, unsigned long long cap) {
+  unsigned long long z = 0;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(g_trace), &dev_buf, sizeof(dev_buf)) != hipSuccess) return -3;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(g_trace_cap), &cap, sizeof(cap)) != hipSuccess) return -3;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(g_trace_n), &z, sizeof(z)) != hipSuccess) return -3;
+  return 0;
+}
+extern "C" unsigned long long pfc_debug_trace_count(void) {
+  unsigned long long n = 0;
+  (void)hipMemcpyFromSymbol(&n, HIP_SYMBOL(g_trace_n), sizeof(n));
+  return n;
+}
+#endif
 
 __global__ void k_report(const InstDev* __restrict__ insts, int count, int* __restrict__ flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -420,6 +490,28 @@ __global__ void k_apply_AR(InstDev I, const double* __restrict__ y, double* __re
   if (i < n) { out[i] = w0; out[n + i] = w1; out[2 * n + i] = w2; }
 }
 
+// Embedded error of the step just taken (psi block): per slice the sum of
+// ((psi_{k+1} - psi_hat) / (atol + rtol max(|psi_k|, |psi_{k+1}|)))^2 with
+// psi_hat = psi_k + sum_j mhat_j y_j^psi (Table rosenbrock_scheme).
+__global__ void k_embedded_err(InstDev I, const double* __restrict__ xold, const double* __restrict__ xnew, double rtol,
+                               double atol) {
+  const int sl = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int n = I.n;
+  const long long n3 = 3LL * n;
+  const int i = sl * 64 + lane;
+  double e2 = 0.0;
+  if (i < n) {
+    const double po = xold[n + i], pn = xnew[n + i];
+    const double ph = po + ROS_MH1 * I.ys[n + i] + ROS_MH2 * I.ys[n3 + n + i] + ROS_MH3 * I.ys[2 * n3 + n + i];
+    const double sc = atol + rtol * fmax(fabs(po), fabs(pn));
+    const double e = (pn - ph) / sc;
+    e2 = e * e;
+  }
+  e2 = wave_sum(e2);
+  if (lane == 0) I.errpart[sl] = e2;
+}
+
 __global__ void k_stage_rhs(InstDev I, int stage, double* __restrict__ b) {
   const int sl = blockIdx.x * PFC_WAVES + (threadIdx.x >> 6);
   if (sl >= I.m.n_slices) return;
@@ -459,6 +551,8 @@ size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int t
   h.r_ = take(n * 8); h.pA = take(n * 8); h.pB = take(n * 8); h.q = take(n * 8);
   h.y0 = take(n * 8); h.y1 = take(n * 8); h.zt = take(n * 8); h.x1 = take(n * 8); h.x2 = take(n * 8);
   h.rB = take(n * 8); h.wB = take(n * 8); h.sA = take(n * 8); h.sB = take(n * 8);
+  h.xbak = (double*)take(n3 * 8);
+  h.errpart = (double*)take((size_t)m->n_slices * 8);
   h.part = (double*)take(2 * (size_t)team_size * 4 * sizeof(double));
   h.st = (State*)take(2 * sizeof(State));
   h.hist = (Hist*)take(sizeof(Hist));
@@ -470,7 +564,7 @@ size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int t
 
 int team_size_for(int n_slices, int rows_per_thread) {
   int rpt = rows_per_thread;
-  if (rpt <= 0) rpt = n_slices >= 2048 ? 2 : 1;
+  if (rpt <= 0) rpt = 1;
   return (n_slices + PFC_WAVES * rpt - 1) / (PFC_WAVES * rpt);
 }
 
@@ -498,14 +592,43 @@ static void fill_info(pfc_solve_info* dst, const InfoDev& s) {
   dst->true_rel_res = s.true_rel_res;
 }
 
+// The descriptors (h_descs) must be filled before build(): a one-instance
+// group bakes that instance's state and partial-sum buffers into the launches.
 int Group::build(hipStream_t capture, int precision, int ticks) {
   graph_ticks = ticks;
+  for (int i = 0; i < count; ++i)
+    if (!h_descs[i].st || !h_descs[i].part || h_descs[i].team_size <= 0) {
+      set_error("internal: launch group built before its descriptors were set");
+      return PFC_ERR_STATE;
+    }
+  if (count == 1 && h_descs[0].team_size != n_wg) {
+    set_error("internal: team size mismatch");
+    return PFC_ERR_STATE;
+  }
   PFC_HIP(hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal));
   for (int t = 0; t < ticks; ++t) {
-    if (precision == PFC_MIXED)
-      hipLaunchKernelGGL(k_tick<float>, dim3(n_wg), dim3(PFC_WG), 0, capture, d_teams, d_descs, t & 1);
-    else
-      hipLaunchKernelGGL(k_tick<double>, dim3(n_wg), dim3(PFC_WG), 0, capture, d_teams, d_descs, t & 1);
+    const int par = t & 1;
+    State* sin = nullptr;
+    State* sout = nullptr;
+    double* pin = nullptr;
+    double* pout = nullptr;
+    if (count == 1) {
+      sin = h_descs[0].st + par;
+      sout = h_descs[0].st + (1 - par);
+      pin = h_descs[0].part + (size_t)par * n_wg * 4;
+      pout = h_descs[0].part + (size_t)(1 - par) * n_wg * 4;
+    }
+    if (precision == PFC_MIXED) {
+      if (count == 1)
+        hipLaunchKernelGGL((k_tick<float, true>), dim3(n_wg), dim3(PFC_WG), 0, capture, d_teams, d_descs, sin, sout, pin, pout, par);
+      else
+        hipLaunchKernelGGL((k_tick<float, false>), dim3(n_wg), dim3(PFC_WG), 0, capture, d_teams, d_descs, sin, sout, pin, pout, par);
+    } else {
+      if (count == 1)
+        hipLaunchKernelGGL((k_tick<double, true>), dim3(n_wg), dim3(PFC_WG), 0, capture, d_teams, d_descs, sin, sout, pin, pout, par);
+      else
+        hipLaunchKernelGGL((k_tick<double, false>), dim3(n_wg), dim3(PFC_WG), 0, capture, d_teams, d_descs, sin, sout, pin, pout, par);
+    }
   }
   hipLaunchKernelGGL(k_report, dim3((count + 255) / 256), dim3(256), 0, capture, d_descs, count, d_flags);
   hipGraph_t g = nullptr;
@@ -585,6 +708,7 @@ static int ensure_group(pfc_instance* I) {
   if (I->grp.exec) return PFC_OK;
   int rc = I->grp.alloc(std::vector<int>{I->team_size});
   if (rc) return rc;
+  I->grp.h_descs[0] = I->h;
   return I->grp.build(I->capture, I->opts.precision, I->ticks);
 }
 
@@ -714,6 +838,7 @@ void pfc_opts_default(pfc_opts* o) {
   o->rows_per_thread = 0;
   o->max_run_steps = 256;
   o->ticks_per_graph = 0;
+  o->single_reduction = 1;
 }
 
 double pfc_tau_critical(double r, double psibar) {
@@ -874,6 +999,74 @@ int pfc_rosenbrock_run(pfc_instance* I, double* state, double r, double psibar, 
   return worst;
 }
 
+int pfc_rosenbrock_adaptive(pfc_instance* I, double* state, double r, double psibar, double tau0, double t_end,
+                            double rtol, double atol, int max_attempts, int init, double* taus, int* n_accepted,
+                            int* n_rejected, void* stream) {
+  if (!I || !state || !taus || !n_accepted || !n_rejected || !std::isfinite(r) || !std::isfinite(psibar) ||
+      !(tau0 > 0.0) || !(t_end > 0.0) || !std::isfinite(t_end) || !(rtol > 0.0) || !(atol > 0.0) || max_attempts < 1 ||
+      (init != PFC_INIT_GIVEN && init != PFC_INIT_CONSISTENT)) {
+    set_error("pfc_rosenbrock_adaptive: invalid arguments");
+    return PFC_ERR_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  InstDev& h = I->h;
+  const int n = I->mesh->n;
+  const int ns = I->mesh->n_slices;
+  double* own_xk = h.xk;
+  h.xk = state;
+  h.replay = 0;
+  *n_accepted = 0;
+  *n_rejected = 0;
+  int rc = PFC_OK, worst = PFC_OK;
+  std::vector<double> part(ns);
+  if (init == PFC_INIT_CONSISTENT) {
+    set_params(h, r, tau0, 1.0 / ROS_GAMMA);
+    h.n_steps = 0;
+    h.init_mode = PFC_INIT_CONSISTENT;
+    rc = prep_ops(I, s);
+    if (!rc) rc = run_single(I, s, JOB_RB);
+  }
+  double t = 0.0, tau = tau0;
+  for (int a = 0; !rc && a < max_attempts && t < t_end * (1.0 - 1e-14); ++a) {
+    const double step = std::min(tau, t_end - t);
+    if (hipMemcpyAsync(h.xbak, state, sizeof(double) * 3 * (size_t)n, hipMemcpyDeviceToDevice, s) != hipSuccess) { rc = PFC_ERR_HIP; break; }
+    set_params(h, r, step, 1.0 / ROS_GAMMA);
+    h.n_steps = 1;
+    h.init_mode = PFC_INIT_GIVEN;
+    rc = prep_ops(I, s);
+    if (!rc) rc = run_single(I, s, JOB_RB);
+    if (rc) break;
+    State fin;
+    if (hipMemcpy(&fin, h.st, sizeof(State), hipMemcpyDeviceToHost) != hipSuccess) { rc = PFC_ERR_HIP; break; }
+    if (fin.status < 0) { worst = fin.status; break; }
+    if (fin.status > worst) worst = fin.status;
+    hipLaunchKernelGGL(k_embedded_err, dim3(ns), dim3(64), 0, s, h, h.xbak, state, rtol, atol);
+    if (hipGetLastError() != hipSuccess || hipMemcpyAsync(part.data(), h.errpart, sizeof(double) * ns, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) { rc = PFC_ERR_HIP; break; }
+    double sum = 0.0;
+    for (int k = 0; k < ns; ++k) sum += part[k];
+    const double err = std::sqrt(sum / n);
+    if (!std::isfinite(err)) { worst = PFC_ERR_BREAKDOWN; break; }
+    if (err <= 1.0) {
+      t += step;
+      taus[*n_accepted] = step;
+      *n_accepted += 1;
+      if (*n_accepted >= max_attempts) break;
+    } else {
+      *n_rejected += 1;
+      if (hipMemcpyAsync(state, h.xbak, sizeof(double) * 3 * (size_t)n, hipMemcpyDeviceToDevice, s) != hipSuccess) { rc = PFC_ERR_HIP; break; }
+    }
+    const double fac = err == 0.0 ? 5.0 : std::min(5.0, std::max(0.2, 0.9 * std::pow(err, -1.0 / 3.0)));
+    tau = step * fac;
+  }
+  if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = PFC_ERR_HIP;
+  h.xk = own_xk;
+  if (rc) return rc;
+  if (worst < 0) return worst;
+  if (t < t_end * (1.0 - 1e-14)) return PFC_NOT_CONVERGED;
+  return worst;
+}
+
 int pfc_apply_AR(pfc_instance* I, const double* psi_k, double r, double tau, double m11, const double* y, double* out,
                  void* stream) {
   if (!I || !psi_k || !y || !out || !std::isfinite(r) || !std::isfinite(tau) || !std::isfinite(m11)) {
@@ -970,7 +1163,6 @@ int pfc_batch_run(pfc_instance* const* insts, int count, double* const* states, 
   auto one_pass = [&](int precision, int steps, int initm) -> int {
     Group g;
     int e = g.alloc(ts);
-    if (!e) e = g.build(insts[0]->capture, precision, ticks);
     if (!e) {
       for (int i = 0; i < count; ++i) {
         InstDev h = insts[i]->h;
@@ -981,8 +1173,9 @@ int pfc_batch_run(pfc_instance* const* insts, int count, double* const* states, 
         g.h_descs[i] = h;
         g.h_states[i] = initial_state(JOB_RB);
       }
-      e = g.run(s, sts, insts[0]->timeout_s * count);
+      e = g.build(insts[0]->capture, precision, ticks);
     }
+    if (!e) e = g.run(s, sts, insts[0]->timeout_s * count);
     g.release();
     return e;
   };

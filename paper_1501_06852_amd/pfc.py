@@ -108,6 +108,8 @@ _sig("pfc_last_inner_counts", C.c_int, [_vp, _ip, C.c_int, _ip])
 _sig("pfc_instance_launch_stats", C.c_int, [_vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)])
 _sig("pfc_rosenbrock_run", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
                                      C.POINTER(pfc_schedule), C.POINTER(pfc_solve_info), _vp])
+_sig("pfc_rosenbrock_adaptive", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                          C.c_double, C.c_int, C.c_int, _dp, _ip, _ip, _vp])
 _sig("pfc_apply_AR", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, _vp, _vp, _vp])
 _sig("pfc_apply_pch", C.c_int, [_vp, C.c_double, _vp, _vp, _ip, _ip, _vp])
 _sig("pfc_stage_rhs", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.c_double, _vp, _vp])
@@ -126,7 +128,7 @@ DECLARED = [
     "pfc_status_str", "pfc_last_error", "pfc_opts_default", "pfc_tau_critical", "pfc_mesh_create_p1",
     "pfc_mesh_create_csr", "pfc_mesh_query", "pfc_mesh_export_csr", "pfc_mesh_destroy", "pfc_spmv",
     "pfc_assemble_N", "pfc_load_psi3", "pfc_instance_footprint", "pfc_instance_create", "pfc_instance_destroy",
-    "pfc_solve", "pfc_last_inner_counts", "pfc_instance_launch_stats", "pfc_rosenbrock_run", "pfc_apply_AR", "pfc_apply_pch", "pfc_stage_rhs",
+    "pfc_solve", "pfc_last_inner_counts", "pfc_instance_launch_stats", "pfc_rosenbrock_run", "pfc_rosenbrock_adaptive", "pfc_apply_AR", "pfc_apply_pch", "pfc_stage_rhs",
     "pfc_batch_run", "pfc_server_create", "pfc_server_submit", "pfc_server_poll", "pfc_result_free",
     "pfc_server_drain", "pfc_server_clock", "pfc_server_destroy",
 ]
@@ -324,6 +326,18 @@ def pfc_rosenbrock_run(inst, n, state, r, psibar, tau, n_steps, init=PFC_INIT_CO
                                  _stream(stream))
     _check(st, "pfc_rosenbrock_run")
     return st, [infos[k].as_dict() for k in range(3 * n_steps)]
+
+
+def pfc_rosenbrock_adaptive(inst, n, state, r, psibar, tau0, t_end, rtol, atol, max_attempts=1000,
+                            init=PFC_INIT_CONSISTENT, stream=None):
+    """Returns (status, accepted taus, n_rejected)."""
+    taus = np.zeros(max_attempts)
+    na, nr = C.c_int(), C.c_int()
+    st = _lib.pfc_rosenbrock_adaptive(inst, _dev(state, 3 * n, "state"), r, psibar, tau0, t_end, rtol, atol,
+                                      max_attempts, init, taus.ctypes.data_as(_dp), C.byref(na), C.byref(nr),
+                                      _stream(stream))
+    _check(st, "pfc_rosenbrock_adaptive")
+    return st, taus[:na.value].copy(), nr.value
 
 
 def pfc_apply_AR(inst, n, psi_k, r, tau, m11, y, out, stream=None):

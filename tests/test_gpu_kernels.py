@@ -113,3 +113,40 @@ def test_pch_apply_fixed_counts(pfc, dim, N, jit, tau_s):
         if inst is not None:
             pfc.pfc_instance_destroy(inst)
         P.close()
+
+
+def test_mesh_from_csr_equals_p1_assembly(pfc):
+    """The CSR entry point (caller-supplied M, K, element volumes) gives the same solver as GPU assembly."""
+    from oracle import pfc as opfc
+    P = Problem(2, 12, 0.2, seed=21)
+    h2 = None
+    i1 = i2 = None
+    try:
+        m1 = P.gpu_mesh()
+        vol = assembly.element_volumes(P.mesh)
+        # the oracle's CSR (same pattern) fed through the CSR entry point
+        h2 = pfc.pfc_mesh_create_csr(2, P.n, P.M.indptr, P.M.indices, P.M.data, P.K.data, P.mesh.elem_nodes, vol)
+        rp, ci, mv, kv = pfc.pfc_mesh_export_csr(h2)
+        assert np.array_equal(mv, P.M.data) and np.array_equal(kv, P.K.data)
+        n = P.n
+        r, tau, m11 = -0.35, 0.5, 1.0 / opfc.ROS3PW_GAMMA
+        b = np.random.default_rng(5).normal(size=3 * n)
+        i1 = pfc.pfc_instance_create(m1, pfc.pfc_opts_default(outer_tol=1e-12))
+        i2 = pfc.pfc_instance_create(h2, pfc.pfc_opts_default(outer_tol=1e-12))
+        x1 = dev(np.zeros(3 * n))
+        x2 = dev(np.zeros(3 * n))
+        pfc.pfc_solve(i1, n, dev(P.psi), r, -0.3, tau, m11, dev(b), x1)
+        pfc.pfc_solve(i2, n, dev(P.psi), r, -0.3, tau, m11, dev(b), x2)
+        assert rel(host(x1), host(x2)) <= 1e-10
+        # invalid CSR: a node pair of an element missing from the pattern
+        rp_bad = P.M.indptr.copy()
+        with pytest.raises(pfc.PFCError):
+            pfc.pfc_mesh_create_csr(2, n, rp_bad, P.M.indices, P.M.data, P.K.data,
+                                    np.array([[0, 1, 2 * 12 + 5]]), np.ones(1))
+    finally:
+        for i in (i1, i2):
+            if i is not None:
+                pfc.pfc_instance_destroy(i)
+        if h2 is not None:
+            pfc.pfc_mesh_destroy(h2)
+        P.close()

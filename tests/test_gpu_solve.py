@@ -181,3 +181,33 @@ def test_rosenbrock_run_replay_parity(pfc, dim, N, jit, tau):
         if inst is not None:
             pfc.pfc_instance_destroy(inst)
         P.close()
+
+
+def test_adaptive_rosenbrock_matches_oracle(pfc):
+    """Embedded error estimate and step-size control: same accepted steps and end state as the oracle."""
+    from oracle import adaptive
+    from oracle.reference import dense_solve
+    P = Problem(2, 8, 0.15, amp=0.3, psibar=-0.2, seed=31, h=2.0)
+    inst = None
+    try:
+        r, T, rtol = -0.35, 3.0, 1e-4
+        n = P.n
+        x0 = opfc.consistent_init(P.mesh, P.M, P.K, r, P.psi)
+        prob = opfc.PFCProblem(P.mesh, P.M, P.K, r)
+
+        def lin(N_, tau_, bR, i):
+            return dense_solve(opfc.AR_sparse(P.M, P.K, N_, r, tau_, M11), bR)
+
+        xr, taus_r, rej_r = adaptive.rosenbrock_adaptive(prob, x0, 0.5, T, rtol, rtol, lin)
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(outer_tol=1e-12))
+        state = dev(np.concatenate([np.zeros(n), P.psi, np.zeros(n)]))
+        st, taus, rej = pfc.pfc_rosenbrock_adaptive(inst, n, state, r, -0.2, 0.5, T, rtol, rtol)
+        assert st >= 0
+        assert len(taus) == len(taus_r) and rej == rej_r
+        assert np.abs(np.array(taus) - np.array(taus_r)).max() <= 1e-8 * max(taus_r)
+        assert abs(sum(taus) - T) <= 1e-12
+        assert rel(host(state), xr) <= 1e-8
+    finally:
+        if inst is not None:
+            pfc.pfc_instance_destroy(inst)
+        P.close()

@@ -91,3 +91,33 @@ def test_fgmres_against_fft_exact_mid_size():
     assert np.linalg.norm(y - yf) <= 1e-10 * np.linalg.norm(yf)
     # iteration counts of the same order as the paper's tables (context, not a pin of the paper's numbers)
     assert 5 <= info["steps"] <= 80
+
+
+def test_arnoldi_relation_and_orthonormal_basis():
+    """Flexible Arnoldi: A Z_k = V_{k+1} H_k and V orthonormal (modified Gram-Schmidt)."""
+    mesh, M, K, psi = _prob(2, 8)
+    r, tau = -0.35, 0.5
+    Nm = assembly.N_matrix(mesh, psi)
+    A = pfc.AR_sparse(M, K, Nm, r, tau, 1.0)
+    inner = precond.InnerSolvers(M, K, tau, mode="pcg", tol=1e-3)
+    b = np.random.default_rng(3).normal(size=3 * mesh.n)
+    rec = []
+    krylov.fgmres(lambda v: A @ v, lambda v: precond.pch_apply(inner, v), b, tol=1e-12, restart=12, record=rec)
+    V, Z, H = rec[0]
+    k = H.shape[1]
+    Vm = np.stack(V[:k + 1], axis=1)
+    Zm = np.stack(Z[:k], axis=1)
+    assert np.abs(A @ Zm - Vm @ H).max() <= 1e-12 * np.abs(A @ Zm).max()
+    # MGS keeps orthogonality to O(eps * cond); a wrong projection would be O(1)
+    assert np.abs(Vm.T @ Vm - np.eye(k + 1)).max() <= 1e-8
+
+
+@pytest.mark.parametrize("dim,N,jit", [(2, 8, 0.0), (2, 8, 0.2), (3, 4, 0.0), (3, 4, 0.2)])
+def test_jacobi_mass_spectrum_element_bounds(dim, N, jit):
+    """eig(D^{-1} M) of a P1 mass matrix lies in [1/2, (m+2)/2] (element mass matrices are |T|(I + J)/((m+1)(m+2)))."""
+    mesh = wl.make_mesh(dim, N, jitter=jit, seed=4)
+    M, _ = assembly.mass_stiffness(mesh)
+    Md = M.toarray()
+    d = np.diag(Md)
+    ev = np.linalg.eigvalsh(Md / np.sqrt(np.outer(d, d)))
+    assert ev.min() >= 0.5 - 1e-12 and ev.max() <= (dim + 2) / 2 + 1e-12
