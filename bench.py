@@ -29,6 +29,36 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per solver launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs,
+# each scaled by what the counter reads for a plain device copy of known size
+# (fetch x2.0, write x1.0), averaged over every launch of a profiled
+# `--steps 1 --warmup 0` run.  A figure holds only for the kernel sources it
+# was taken on: when their digest differs, `traffic` is reported as null.
+TRAFFIC = {
+    # workload: (sha256 of the kernel sources, bytes per launch, algorithmic bytes per launch of the same run)
+    "pfc2d_512_fp64": ("0ecf4fdb166a674ec74466fa5312c6183129b1844f1d48348d16bb0a91ee6a29", 40483035.0, 37986008.0),
+}
+
+
+def kernel_source_digest():
+    import hashlib
+
+    d = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1501_06852_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            d.update(name.encode())
+            with open(os.path.join(csrc, name), "rb") as f:
+                d.update(f.read())
+    return d.hexdigest()
+
+
+def traffic_for(workload):
+    rec = TRAFFIC.get(workload)
+    if rec is None or rec[0] != kernel_source_digest():
+        return None, None
+    return rec[1], rec[2]
+
 WORKLOADS = {
     # name: (dim, N, jitter, r, psibar, tau, precision, default steps)
     "pfc2d_512_fp64": (2, 512, 0.2, -0.35, -0.3, 1.0, 0, 20),
@@ -91,8 +121,12 @@ def bench_batched(args, torch, wl, pfc):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         resid = max(i["true_rel_res"] for row in infos for i in row)
+        from paper_1501_06852_amd import roofline
+        w = 4 if prec == 1 else 8
+        alg = sum(roofline.solve_bytes(n, 7, w, i) for row in infos for i in row)
         res[label] = dict(solves_per_s=3 * steps * count / dt, seconds=dt, status=pfc.pfc_status_str(code),
-                          max_true_rel_res=resid)
+                          max_true_rel_res=resid, algorithmic_GBps=alg / dt / 1e9,
+                          hbm_frac=alg / dt / 1e9 / HBM_PEAK_GBS)
         for i in insts:
             pfc.pfc_instance_destroy(i)
     # plain float64 solver, one instance at a time, on a sample of the same instances
@@ -267,6 +301,7 @@ def main():
     period_s = gpu_ms * 1e-3 / max(1, launches)
     achieved = alg / max(1, launches) / period_s / 1e9
     res = [i["true_rel_res"] for i in infos]
+    traffic, traffic_alg = traffic_for(args.workload)
     out = {
         "metric": "PFC block solves/s @1e-8 rel residual",
         "value": solves / wall,
@@ -288,10 +323,23 @@ def main():
         "outer_iters_mean": float(np.mean([i["outer_iters"] for i in infos])),
         "inner_pcg_per_apply_mean": float(np.mean([i["inner_total"] / max(1, i["inner_applies"]) for i in infos])),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_over_algorithmic": None if traffic is None else traffic / traffic_alg,
                      "kernel": "k_tick (solver phase launch)", "launches": launches,
-                     "algorithmic_bytes": alg, "avg_launch_period_us": period_s * 1e6},
+                     "algorithmic_bytes": alg, "algorithmic_bytes_per_launch": alg / max(1, launches),
+                     "avg_launch_period_us": period_s * 1e6, "kernel_sources_sha256": kernel_source_digest()},
     }
+    if prec == 1:
+        # error of the mixed-precision path against float64, one step from the same state (not timed)
+        inst64 = pfc.pfc_instance_create(h, pfc.pfc_opts_default(precision=0))
+        s32 = state.clone()
+        s64 = state.clone()
+        pfc.pfc_rosenbrock_run(inst, n, s32, r, psibar, tau, 1, pfc.PFC_INIT_GIVEN)
+        pfc.pfc_rosenbrock_run(inst64, n, s64, r, psibar, tau, 1, pfc.PFC_INIT_GIVEN)
+        torch.cuda.synchronize()
+        out["mixed_vs_fp64_rel_err_1step"] = float(torch.linalg.norm(s32 - s64) / torch.linalg.norm(s64))
+        pfc.pfc_instance_destroy(inst64)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = run_cpu_baseline(dim, N, jitter, r, psibar, tau, args.seed)
     pfc.pfc_instance_destroy(inst)

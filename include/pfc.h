@@ -82,7 +82,11 @@ typedef struct pfc_server pfc_server;
  *   single_reduction 0: inner PCG in the standard form (two reductions, two
  *                 launches per iteration); 1: the Chronopoulos-Gear form of the
  *                 same iteration (one reduction, one launch per iteration;
- *                 identical iterates in exact arithmetic) */
+ *                 identical iterates in exact arithmetic)
+ *   schur_variant 0: Schur complement approximated by S_CH (steps 3.1 and 3.2);
+ *                 1: by S_D = M - 2 delta K + delta K M_D^{-1} K, M_D = diag(M)
+ *                 (Section 4.1), one PCG solve on the second-ring pattern
+ *   sd_iters      iteration count of the S_D solve (20, Table inner_solvers) */
 typedef struct pfc_opts {
     int struct_size;
     int precision;
@@ -96,6 +100,8 @@ typedef struct pfc_opts {
     int max_run_steps;
     int ticks_per_graph;
     int single_reduction;
+    int schur_variant;
+    int sd_iters;
 } pfc_opts;
 
 /* Result record of one stage solve.

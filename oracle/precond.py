@@ -42,6 +42,13 @@ from .krylov import pcg
 STEP_NAMES = ("1:M", "2:M+dK", "3.1:M+sqrt(d)K", "3.2:M+sqrt(d)K", "5:M")
 
 
+def schur_D_sparse(M, K, tau):
+    """S_D = M - 2 delta K + delta K M_D^{-1} K with M_D = diag(M) (Section 4.1)."""
+    import scipy.sparse as sp
+    d = math.sqrt(tau)
+    return (M - 2.0 * d * K + d * (K @ sp.diags(1.0 / M.diagonal()) @ K)).tocsr()
+
+
 class InnerSolvers:
     """Inner solves of the five preconditioner steps.
 
@@ -51,12 +58,16 @@ class InnerSolvers:
                   (list of 5-lists) runs exactly those counts.
     """
 
-    def __init__(self, M, K, tau, mode="pcg", tol=1e-3, maxit=500, replay_counts=None):
+    def __init__(self, M, K, tau, mode="pcg", tol=1e-3, maxit=500, replay_counts=None, schur="CH", sd_iters=20):
         self.M, self.K = M, K
         self.tau = tau
         self.delta = math.sqrt(tau)
         self.sdelta = math.sqrt(self.delta)
+        self.schur = schur
+        self.sd_iters = sd_iters
         self.mats = [M, (M + self.delta * K).tocsr(), (M + self.sdelta * K).tocsr()]
+        if schur == "D":
+            self.mats.append(schur_D_sparse(M, K, tau))
         self.mode = mode
         self.tol, self.maxit = tol, maxit
         self.replay = replay_counts
@@ -79,6 +90,8 @@ class InnerSolvers:
             return self.lu[which_mat].solve(rhs)
         A = self.mats[which_mat]
         fixed = None
+        if which_mat == 3:
+            fixed = self.sd_iters  # Table inner_solvers: S_D is solved with a fixed iteration count
         if self.replay is not None:
             fixed = self.replay[len(self.counts)][step]
         x, it = pcg(lambda v: A @ v, rhs, self.dinv[which_mat], self.tol, self.maxit, fixed)
@@ -95,8 +108,12 @@ def pch_apply(inner: InnerSolvers, v):
     inner.begin()
     y0 = inner.solve(0, 0, b0)                          # (1)
     y1 = inner.solve(1, 1, b1 - tau * (K @ y0))         # (2)
-    z = inner.solve(2, 2, M @ y1)                       # (3.1)
-    x1 = inner.solve(2, 3, M @ z)                       # (3.2)
+    if inner.schur == "D":                              # (3) with S_D
+        x1 = inner.solve(3, 2, M @ y1)
+        inner._cur.append(0)
+    else:
+        z = inner.solve(2, 2, M @ y1)                   # (3.1)
+        x1 = inner.solve(2, 3, M @ z)                   # (3.2)
     x0 = y0 + (y1 - x1) / delta                         # (4)
     x2 = inner.solve(0, 4, b2 - K @ x1)                 # (5)
     inner.end()
@@ -137,11 +154,17 @@ def L_U_of_S(Md, Kd, tau, S):
     return L, U
 
 
-def P3_dense(M, K, tau):
-    """3x3 block preconditioner [[P(S_CH), 0], [[0, K], M]] as a dense matrix."""
+def schur_D_dense(Md, Kd, tau):
+    d = math.sqrt(tau)
+    return Md - 2.0 * d * Kd + d * Kd @ np.diag(1.0 / np.diag(Md)) @ Kd
+
+
+def P3_dense(M, K, tau, schur="CH"):
+    """3x3 block preconditioner [[P(S), 0], [[0, K], M]] (S = S_CH or S_D) as a dense matrix."""
     Md, Kd, B = dense_blocks(M, K)
     n = Md.shape[0]
-    P2 = P_of_S(Md, Kd, tau, schur_ch(Md, Kd, B, tau))
+    S = schur_ch(Md, Kd, B, tau) if schur == "CH" else schur_D_dense(Md, Kd, tau)
+    P2 = P_of_S(Md, Kd, tau, S)
     P3 = np.zeros((3 * n, 3 * n))
     P3[:2 * n, :2 * n] = P2
     P3[2 * n:, n:2 * n] = Kd

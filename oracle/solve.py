@@ -23,7 +23,7 @@ from .precond import InnerSolvers, pch_apply
 
 
 def solve_stage(M, K, N, r, tau, m11, b, tol=1e-8, restart=30, max_steps=1000,
-                inner_mode="pcg", inner_tol=1e-3, inner_maxit=500, replay: Schedule | None = None):
+                inner_mode="pcg", inner_tol=1e-3, inner_maxit=500, replay: Schedule | None = None, schur="CH"):
     n = M.shape[0]
     tau_s = tau / m11
     b_s = b.copy()
@@ -31,7 +31,7 @@ def solve_stage(M, K, N, r, tau, m11, b, tol=1e-8, restart=30, max_steps=1000,
     nb = float(np.linalg.norm(b))
     nbs = float(np.linalg.norm(b_s))
     inner = InnerSolvers(M, K, tau_s, mode=inner_mode, tol=inner_tol, maxit=inner_maxit,
-                         replay_counts=None if replay is None else replay.inner)
+                         replay_counts=None if replay is None else replay.inner, schur=schur)
 
     def apply_As(y):
         return apply_AR(M, K, N, r, tau_s, 1.0, y)

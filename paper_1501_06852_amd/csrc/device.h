@@ -70,6 +70,47 @@ __device__ __forceinline__ void for_width(int w, F f) {
   }
 }
 
+// Stores of phase outputs.  PFC_STORE_POLICY selects the cache policy:
+// 0 plain (write-back L2), 1 agent-coherent write-through (sc1), 2 streaming (nt).
+// Write-through is the default: every phase output is read by other XCDs in
+// the next launch, and writing it through during the kernel shortens the
+// cache write-back at the kernel boundary.
+#ifndef PFC_STORE_POLICY
+#define PFC_STORE_POLICY 1
+#endif
+
+template <typename T>
+__device__ __forceinline__ void vst(T* p, T v) {
+#if PFC_STORE_POLICY == 1
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#elif PFC_STORE_POLICY == 2
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+
+// Workgroup placement.  The dispatcher deals the workgroups of a launch to the
+// 8 XCDs in turn (workgroup b lands on XCD b mod 8), and each XCD has its own
+// L2.  Rows a workgroup gathers from its neighbours' blocks are only reused
+// from L2 when those neighbours sit on the same XCD, so the rank (row block)
+// of a workgroup is renumbered to give every XCD one contiguous run of ranks:
+// XCD x owns ranks [x*q + min(x, r), ...) with q = g / 8, r = g mod 8.  The
+// map is a bijection of [0, g) for every g.
+#ifndef PFC_XCD_MAP
+#define PFC_XCD_MAP 1
+#endif
+#define PFC_XCDS 8
+__device__ __forceinline__ int xcd_rank(int b, int g) {
+#if PFC_XCD_MAP
+  const int q = g / PFC_XCDS, r = g % PFC_XCDS, x = b % PFC_XCDS;
+  return x * q + (x < r ? x : r) + b / PFC_XCDS;
+#else
+  (void)g;
+  return b;
+#endif
+}
+
 // ---- typed views ----------------------------------------------------------
 template <typename T> struct TV;
 template <> struct TV<double> {
@@ -210,13 +251,13 @@ __device__ Red3 ph_solve_init(const InstDev& I, const State& S, const Team& tm) 
     if (rb) stage_rhs_row(I, sl, tm.lane, S.stage, b0, b1, b2);
     if (i < n) {
       if (rb) {
-        I.b[i] = b0; I.b[n + i] = b1; I.b[2 * n + i] = b2;
+        vst(I.b + i, b0); vst(I.b + n + i, b1); vst(I.b + 2 * n + i, b2);
       } else {
         b0 = I.b_user[i]; b1 = I.b_user[n + i]; b2 = I.b_user[2 * n + i];
       }
       const double bs1 = b1 * im;
-      I.W[i] = b0; I.W[n + i] = bs1; I.W[2 * n + i] = b2;
-      X[i] = 0.0; X[n + i] = 0.0; X[2 * n + i] = 0.0;
+      vst(I.W + i, b0); vst(I.W + n + i, bs1); vst(I.W + 2 * n + i, b2);
+      vst(X + i, 0.0); vst(X + n + i, 0.0); vst(X + 2 * n + i, 0.0);
       a0 += b0 * b0 + b1 * b1 + b2 * b2;
       a1 += b0 * b0 + bs1 * bs1 + b2 * b2;
     }
@@ -248,7 +289,11 @@ struct PcgOps {
   T cK;
   const T* dinv;
   T* x;
+  const int* sp;   // slice offsets and columns of the operator's pattern
+  const int* colp;
 };
+
+__device__ __forceinline__ bool is_ci(int kind) { return kind == KIND_CI_OMEGA || kind == KIND_CI_MU; }
 
 template <typename T>
 __device__ __forceinline__ PcgOps<T> pcg_ops(const InstDev& I, int kind) {
@@ -259,6 +304,8 @@ __device__ __forceinline__ PcgOps<T> pcg_ops(const InstDev& I, int kind) {
   o.C = o.Mv;
   o.dinv = TV<T>::dM(I);
   o.x = nullptr;
+  o.sp = I.m.slice_ptr;
+  o.colp = I.m.col;
   const int n = I.n;
   switch (kind) {
     case KIND_Y0: o.x = (T*)I.y0; break;
@@ -274,6 +321,13 @@ __device__ __forceinline__ PcgOps<T> pcg_ops(const InstDev& I, int kind) {
       if (I.shared_ops) { o.C = nullptr; o.cK = T(I.sdelta); } else o.C = (const T*)I.Csd;
       break;
     case KIND_X2: o.x = (T*)I.x2; break;
+    case KIND_SD:
+      o.x = (T*)I.x1;
+      o.C = (const T*)I.SDv;
+      o.dinv = (const T*)I.dinvSD;
+      o.sp = I.m.w_slice_ptr;
+      o.colp = I.m.w_col;
+      break;
     case KIND_CI_OMEGA: o.x = (T*)(I.xk + 2LL * n); break;
     case KIND_CI_MU: o.x = (T*)(I.xk); break;
   }
@@ -319,7 +373,7 @@ __device__ Red3 ph_pcg_setup(const InstDev& I, const State& S, const Team& tm) {
         if (i < n) {
           const double vs = S.vscale;
           const double v0 = I.W[i] * vs, v1 = I.W[n + i] * vs, v2 = I.W[2 * n + i] * vs;
-          Vj[i] = v0; Vj[n + i] = v1; Vj[2 * n + i] = v2;
+          vst(Vj + i, v0); vst(Vj + n + i, v1); vst(Vj + 2 * n + i, v2);
           rhs = v0;
         }
       } break;
@@ -328,6 +382,7 @@ __device__ Red3 ph_pcg_setup(const InstDev& I, const State& S, const Team& tm) {
         const T ky = row_dot<T>(I, sl, lane, Kv, [&](int j) { return y0[j]; });
         if (i < n) rhs = Vj[n + i] - I.tau_s * (double)ky;
       } break;
+      case KIND_SD:   // (3) with S_D: M y1
       case KIND_Z: {  // (3.1): M y1
         const T* y1 = (const T*)I.y1;
         const T my = row_dot<T>(I, sl, lane, Mv, [&](int j) { return y1[j]; });
@@ -345,8 +400,8 @@ __device__ Red3 ph_pcg_setup(const InstDev& I, const State& S, const Team& tm) {
           rhs = Vj[2 * n + i] - (double)kx;
           const double y0i = (double)((const T*)I.y0)[i], y1i = (double)((const T*)I.y1)[i];
           const double x1i = (double)x1[i];
-          Zj[i] = y0i + (y1i - x1i) / I.delta;
-          Zj[n + i] = x1i;
+          vst(Zj + i, y0i + (y1i - x1i) / I.delta);
+          vst(Zj + n + i, x1i);
         }
       } break;
       case KIND_CI_OMEGA: {  // M omega_0 = -K psi_0
@@ -372,8 +427,8 @@ __device__ Red3 ph_pcg_setup(const InstDev& I, const State& S, const Team& tm) {
     }
     if (i < n) {
       const T rT = T(rhs);
-      r[i] = rT;
-      o.x[i] = T(0);
+      vst(r + i, rT);
+      vst(o.x + i, T(0));
       const double rd = (double)rT;
       a0 += rd * ((double)o.dinv[i] * rd);
       a1 += rd * rd;
@@ -402,18 +457,18 @@ __device__ Red3 ph_pcg_a(const InstDev& I, const State& S, const Team& tm) {
   double a0 = 0.0;
   PFC_SLICES(I, tm) {
     const int i = sl * 64 + tm.lane;
-    const int base = I.m.slice_ptr[sl];
-    const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
+    const int base = o.sp[sl];
+    const int w = (o.sp[sl + 1] - base) >> 6;
     T acc = T(0);
     for_width(w, [&](int k) {
       const long long e = (long long)base + k * 64 + tm.lane;
-      const int j = I.m.col[e];
+      const int j = o.colp[e];
       acc += opval(o, e) * pval(o.dinv, r, pold, beta, first, j);
     });
     if (i < n) {
       const T pi = pval(o.dinv, r, pold, beta, first, i);
-      pnew[i] = pi;
-      q[i] = acc;
+      vst(pnew + i, pi);
+      vst(q + i, acc);
       a0 += (double)pi * (double)acc;
     }
   }
@@ -434,8 +489,8 @@ __device__ Red3 ph_pcg_b(const InstDev& I, const State& S, const Team& tm) {
     if (i < n) {
       const T xi = o.x[i] + alpha * p[i];
       const T ri = r[i] - alpha * q[i];
-      o.x[i] = xi;
-      r[i] = ri;
+      vst(o.x + i, xi);
+      vst(r + i, ri);
       const double rd = (double)ri;
       a0 += rd * rd;
       a1 += rd * ((double)o.dinv[i] * rd);
@@ -483,8 +538,8 @@ __device__ Red3 ph_aspmv(const InstDev& I, const State& S, const Team& tm) {
               [&](int j, double& mu, double& ps, double& om) { mu = Zj[j]; ps = Zj[n + j]; om = (double)x2[j]; },
               w0, w1, w2);
     if (i < n) {
-      I.W[i] = w0; I.W[n + i] = w1; I.W[2 * n + i] = w2;
-      Zj[2 * n + i] = (double)x2[i];
+      vst(I.W + i, w0); vst(I.W + n + i, w1); vst(I.W + 2 * n + i, w2);
+      vst(Zj + 2 * n + i, (double)x2[i]);
       a0 += w0 * V0[i] + w1 * V0[n + i] + w2 * V0[2 * n + i];
       a1 += w0 * w0 + w1 * w1 + w2 * w2;
     }
@@ -506,7 +561,7 @@ __device__ Red3 ph_mgs(const InstDev& I, const State& S, const Team& tm, bool la
       for (int blk = 0; blk < 3; ++blk) {
         const long long o = (long long)blk * n + i;
         const double w = I.W[o] - h * vp[o];
-        I.W[o] = w;
+        vst(I.W + o, w);
         a0 += last ? w * w : w * vi[o];
       }
     }
@@ -526,7 +581,7 @@ __device__ Red3 ph_update_x(const InstDev& I, const State& S, const Team& tm, co
         const long long o = (long long)blk * n + i;
         double x = X[o];
         for (int l = 0; l < kc; ++l) x += y[l] * I.Z[(long long)l * n3 + o];
-        X[o] = x;
+        vst(X + o, x);
       }
     }
   }
@@ -550,7 +605,7 @@ __device__ Red3 ph_true_res(const InstDev& I, const State& S, const Team& tm) {
     if (i < n) {
       const double r0 = bsrc[i] - w0, r1 = bsrc[n + i] - w1, r2 = bsrc[2 * n + i] - w2;
       const double rs1 = r1 * im;
-      I.W[i] = r0; I.W[n + i] = rs1; I.W[2 * n + i] = r2;
+      vst(I.W + i, r0); vst(I.W + n + i, rs1); vst(I.W + 2 * n + i, r2);
       a0 += r0 * r0 + r1 * r1 + r2 * r2;
       a1 += r0 * r0 + rs1 * rs1 + r2 * r2;
     }
@@ -601,16 +656,16 @@ __device__ Red3 ph_cg_init(const InstDev& I, const State& S, const Team& tm) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   PFC_SLICES(I, tm) {
     const int i = sl * 64 + tm.lane;
-    const int base = I.m.slice_ptr[sl];
-    const int wd = (I.m.slice_ptr[sl + 1] - base) >> 6;
+    const int base = o.sp[sl];
+    const int wd = (o.sp[sl + 1] - base) >> 6;
     T acc = T(0);
     for_width(wd, [&](int k) {
       const long long e = (long long)base + k * 64 + tm.lane;
-      const int j = I.m.col[e];
+      const int j = o.colp[e];
       acc += opval(o, e) * (o.dinv[j] * r[j]);
     });
     if (i < n) {
-      w[i] = acc;
+      vst(w + i, acc);
       const T u = o.dinv[i] * r[i];
       a0 += (double)r[i] * (double)u;
       a1 += (double)acc * (double)u;
@@ -637,25 +692,25 @@ __device__ Red3 ph_cg_iter(const InstDev& I, const State& S, const Team& tm) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   PFC_SLICES(I, tm) {
     const int i = sl * 64 + tm.lane;
-    const int base = I.m.slice_ptr[sl];
-    const int wd = (I.m.slice_ptr[sl + 1] - base) >> 6;
+    const int base = o.sp[sl];
+    const int wd = (o.sp[sl + 1] - base) >> 6;
     T acc = T(0);
     for_width(wd, [&](int k) {
       const long long e = (long long)base + k * 64 + tm.lane;
-      const int j = I.m.col[e];
+      const int j = o.colp[e];
       acc += opval(o, e) * cg_unew(o.dinv, rc, wc, so, alpha, beta, first, j);
     });
     if (i < n) {
       const T si = cg_s(wc, so, beta, first, i);
       const T uo = o.dinv[i] * rc[i];
       const T pi = first ? uo : (uo + beta * p[i]);
-      o.x[i] = o.x[i] + alpha * pi;
+      vst(o.x + i, o.x[i] + alpha * pi);
       const T ri = rc[i] - alpha * si;
       const T ui = cg_unew(o.dinv, rc, wc, so, alpha, beta, first, i);
-      sn[i] = si;
-      p[i] = pi;
-      rn[i] = ri;
-      wn[i] = acc;
+      vst(sn + i, si);
+      vst(p + i, pi);
+      vst(rn + i, ri);
+      vst(wn + i, acc);
       a0 += (double)ri * (double)ui;
       a1 += (double)acc * (double)ui;
       a2 += (double)ri * (double)ri;

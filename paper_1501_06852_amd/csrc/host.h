@@ -42,8 +42,18 @@ struct pfc_mesh {
   int* d_elem_nodes = nullptr;
   double* d_vol = nullptr;
   long long* d_csr2sell = nullptr;
+  // second-ring pattern for the S_D preconditioner (built on first use)
+  int* d_w_slice_ptr = nullptr;
+  int* d_w_col = nullptr;
+  long long* d_w_p1pos = nullptr;
+  int* d_w_tri_ptr = nullptr;
+  int* d_w_tri = nullptr;
   MeshDev dev{};
 };
+
+namespace pfc {
+int build_second_ring(pfc_mesh* m);
+}
 
 namespace pfc {
 // grid of standalone kernels over the slices of a mesh (one wave per slice)

@@ -159,7 +159,8 @@ static int upload(T** dst, const T* src, size_t count) {
 static void mesh_free(pfc_mesh* m) {
   if (!m) return;
   void* ptrs[] = {m->d_slice_ptr, m->d_col, m->d_M, m->d_K, m->d_Mf, m->d_Kf, m->d_dinvM, m->d_dinvMf,
-                  m->d_sl_el_ptr, m->d_sl_el, m->d_nd_el_ptr, m->d_nd_el, m->d_elem_nodes, m->d_vol, m->d_csr2sell};
+                  m->d_sl_el_ptr, m->d_sl_el, m->d_nd_el_ptr, m->d_nd_el, m->d_elem_nodes, m->d_vol, m->d_csr2sell,
+                  m->d_w_slice_ptr, m->d_w_col, m->d_w_p1pos, m->d_w_tri_ptr, m->d_w_tri};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -304,6 +305,97 @@ static int derive(pfc_mesh* m) {
       set_error("mass matrix has a non-positive diagonal entry at row " + std::to_string(i));
       return PFC_ERR_ARG;
     }
+  return PFC_OK;
+}
+
+// Pattern of K M_D^{-1} K (nodes at graph distance <= 2) in SELL-64 layout,
+// with, for each stored entry (i, j), the P1 positions of (i, j) and of the
+// pairs (i, k), (k, j) over the common neighbours k.  Symbolic only; the
+// values of S_D are formed on the GPU per time step size.
+int build_second_ring(pfc_mesh* m) {
+  if (m->d_w_slice_ptr) return PFC_OK;
+  const int n = m->n;
+  // the triples below hold P1 positions as int
+  if (m->nnz_sell > 2000000000LL) { set_error("second-ring pattern too large"); return PFC_ERR_ARG; }
+  std::vector<int> wrp(n + 1, 0), wcol;
+  std::vector<int> buf;
+  for (int i = 0; i < n; ++i) {
+    buf.clear();
+    for (int t = m->row_ptr[i]; t < m->row_ptr[i + 1]; ++t) {
+      const int k = m->col_idx[t];
+      buf.insert(buf.end(), m->col_idx.begin() + m->row_ptr[k], m->col_idx.begin() + m->row_ptr[k + 1]);
+    }
+    std::sort(buf.begin(), buf.end());
+    buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+    wcol.insert(wcol.end(), buf.begin(), buf.end());
+    if (wcol.size() > 2000000000ULL) { set_error("second-ring pattern too large"); return PFC_ERR_ARG; }
+    wrp[i + 1] = (int)wcol.size();
+  }
+  const int ns = m->n_slices;
+  std::vector<int> sptr(ns + 1, 0);
+  for (int sl = 0; sl < ns; ++sl) {
+    int w = 0;
+    for (int l = 0; l < 64; ++l) {
+      const int i = sl * 64 + l;
+      if (i < n) w = std::max(w, wrp[i + 1] - wrp[i]);
+    }
+    const long long nx = (long long)sptr[sl] + 64LL * w;
+    if (nx > 2000000000LL) { set_error("second-ring pattern too large"); return PFC_ERR_ARG; }
+    sptr[sl + 1] = (int)nx;
+  }
+  const long long nw = sptr[ns];
+  std::vector<int> scol((size_t)nw);
+  std::vector<long long> p1pos((size_t)nw, -1);
+  std::vector<int> tptr((size_t)nw + 1, 0);
+  std::vector<int> tri;
+  // first pass: layout; second: triples in entry order
+  for (int sl = 0; sl < ns; ++sl) {
+    const int w = (sptr[sl + 1] - sptr[sl]) / 64;
+    for (int l = 0; l < 64; ++l) {
+      const int i = sl * 64 + l;
+      const int len = i < n ? wrp[i + 1] - wrp[i] : 0;
+      for (int kk = 0; kk < w; ++kk) {
+        const long long pos = (long long)sptr[sl] + kk * 64LL + l;
+        scol[pos] = kk < len ? wcol[wrp[i] + kk] : (i < n ? i : 0);
+      }
+    }
+  }
+  for (int sl = 0; sl < ns; ++sl) {
+    const int w = (sptr[sl + 1] - sptr[sl]) / 64;
+    for (int kk = 0; kk < w; ++kk)
+      for (int l = 0; l < 64; ++l) {
+        const long long pos = (long long)sptr[sl] + kk * 64LL + l;
+        const int i = sl * 64 + l;
+        const int len = i < n ? wrp[i + 1] - wrp[i] : 0;
+        if (kk < len) {
+          const int j = scol[pos];
+          const int sij = slot_of(m, i, j);
+          if (sij >= 0) p1pos[pos] = m->csr2sell[sij];
+          for (int t = m->row_ptr[i]; t < m->row_ptr[i + 1]; ++t) {
+            const int k = m->col_idx[t];
+            const int skj = slot_of(m, k, j);
+            if (skj < 0) continue;
+            tri.push_back((int)m->csr2sell[t]);
+            tri.push_back((int)m->csr2sell[skj]);
+          }
+        }
+        if (tri.size() / 2 > 2000000000ULL) { set_error("second-ring pattern too large"); return PFC_ERR_ARG; }
+        tptr[pos + 1] = (int)(tri.size() / 2);
+      }
+  }
+  // positions were visited in increasing order, so tptr is a prefix sum over them
+  int rc;
+  if ((rc = upload(&m->d_w_slice_ptr, sptr.data(), sptr.size()))) return rc;
+  if ((rc = upload(&m->d_w_col, scol.data(), scol.size()))) return rc;
+  if ((rc = upload(&m->d_w_p1pos, p1pos.data(), p1pos.size()))) return rc;
+  if ((rc = upload(&m->d_w_tri_ptr, tptr.data(), tptr.size()))) return rc;
+  if ((rc = upload(&m->d_w_tri, tri.data(), tri.size()))) return rc;
+  m->dev.w_nnz_sell = nw;
+  m->dev.w_slice_ptr = m->d_w_slice_ptr;
+  m->dev.w_col = m->d_w_col;
+  m->dev.w_p1pos = m->d_w_p1pos;
+  m->dev.w_tri_ptr = m->d_w_tri_ptr;
+  m->dev.w_tri = m->d_w_tri;
   return PFC_OK;
 }
 

@@ -45,7 +45,8 @@ enum { JOB_NONE = 0, JOB_SOLVE = 1, JOB_RB = 2, JOB_PCH = 3 };
 
 // inner solve kinds: steps (1), (2), (3.1), (3.2), (5) of the P_CH apply,
 // then the two mass solves of the consistent initial values
-enum { KIND_Y0 = 0, KIND_Y1 = 1, KIND_Z = 2, KIND_X1 = 3, KIND_X2 = 4, KIND_CI_OMEGA = 5, KIND_CI_MU = 6 };
+enum { KIND_Y0 = 0, KIND_Y1 = 1, KIND_Z = 2, KIND_X1 = 3, KIND_X2 = 4, KIND_CI_OMEGA = 5, KIND_CI_MU = 6, KIND_SD = 7 };
+// step (3) with the diagonal-mass Schur approximation S_D replaces (3.1), (3.2)
 
 struct MeshDev {
   int n, dim, n_slices, n_elem;
@@ -64,6 +65,13 @@ struct MeshDev {
   const int* nd_el;       // packed (elem << 2) | local index
   const int* elem_nodes;  // [n_elem*(dim+1)]
   const double* elem_vol; // [n_elem]
+  // second-ring pattern of K M_D^{-1} K (built only for the S_D preconditioner)
+  long long w_nnz_sell;
+  const int* w_slice_ptr; // [n_slices+1]
+  const int* w_col;       // [w_nnz_sell]
+  const long long* w_p1pos; // [w_nnz_sell] position of the same entry in the P1 layout, or -1
+  const int* w_tri_ptr;   // [w_nnz_sell+1]
+  const int* w_tri;       // pairs (e1, e2): P1 positions of (i,k) and (k,j)
 };
 
 // Double-buffered scalar state of one instance (written by workgroup 0 of its
@@ -105,13 +113,15 @@ struct InstDev {
   MeshDev m;
   int n, precision, restart, max_steps;
   int inner_maxit, shared_ops, team_size, replay;
-  int single_reduction, pad_i;
+  int single_reduction, schur_d;
+  int sd_iters, pad_j;
   double outer_tol, inner_tol, ci_tol;
   // job parameters
   double r, tau, m11, tau_s, delta, sdelta;
   int job, n_steps, init_mode, max_infos;
   // typed operator arrays (float or double by precision)
   void* Cd; void* Csd; void* dinvCd; void* dinvCsd;
+  void* SDv; void* dinvSD;      // S_D values (second-ring layout) and Jacobi diagonal
   double* N;                    // [nnz_sell]
   // float64 vectors
   const double* b_user;         // solve job rhs

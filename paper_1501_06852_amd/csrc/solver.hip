@@ -36,16 +36,20 @@ __device__ __forceinline__ bool phase_partials(int ph) {
 
 __device__ __forceinline__ int solve_index(const State& S) { return S.job == JOB_RB ? S.step * 3 + S.stage - 1 : 0; }
 
+// count slot of an inner solve kind in the per-application record (5 slots)
+__device__ __forceinline__ int count_slot(int kind) { return kind == KIND_SD ? KIND_Z : kind; }
+
 __device__ __forceinline__ int inner_limit(const InstDev& I, const State& S, bool& fixed, double& tol) {
-  if (S.kind >= KIND_CI_OMEGA) { fixed = false; tol = I.ci_tol; return 2000; }
+  if (is_ci(S.kind)) { fixed = false; tol = I.ci_tol; return 2000; }
   tol = I.inner_tol;
   if (I.replay) {
     fixed = true;
     const int idx = solve_index(S);
     const int* meta = I.sched_meta + 4 * idx;
     if (S.apply >= meta[3]) return 0;
-    return I.sched_inner[(long long)(meta[2] + S.apply) * 5 + S.kind];
+    return I.sched_inner[(long long)(meta[2] + S.apply) * 5 + count_slot(S.kind)];
   }
+  if (S.kind == KIND_SD) { fixed = true; return I.sd_iters; }  // Table inner_solvers: fixed count for S_D
   fixed = false;
   return I.inner_maxit;
 }
@@ -95,13 +99,25 @@ __device__ void begin_solve(State& S, const InstDev& I, bool wr, Red3 red) {
 }
 
 __device__ void pcg_done(State& S, const InstDev& I, bool wr) {
-  if (S.kind <= KIND_X2 && wr) {
-    if (S.apply < I.max_steps) I.rec_inner[S.apply * 5 + S.kind] = S.it;
+  if (!is_ci(S.kind) && wr) {
+    const int slot = count_slot(S.kind);
+    if (S.apply < I.max_steps) {
+      I.rec_inner[S.apply * 5 + slot] = S.it;
+      if (S.kind == KIND_SD) I.rec_inner[S.apply * 5 + KIND_X1] = 0;
+    }
     I.hist->inner_total += S.it;
-    if (S.it > I.hist->inner_max[S.kind]) I.hist->inner_max[S.kind] = S.it;
+    if (S.it > I.hist->inner_max[slot]) I.hist->inner_max[slot] = S.it;
   }
   switch (S.kind) {
-    case KIND_Y0: case KIND_Y1: case KIND_Z: case KIND_X1:
+    case KIND_Y1:
+      S.kind = I.schur_d ? KIND_SD : KIND_Z;
+      S.phase = PH_PCG_SETUP;
+      break;
+    case KIND_SD:
+      S.kind = KIND_X2;
+      S.phase = PH_PCG_SETUP;
+      break;
+    case KIND_Y0: case KIND_Z: case KIND_X1:
       S.kind += 1;
       S.phase = PH_PCG_SETUP;
       break;
@@ -327,11 +343,11 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   const double* part_in;
   double* part_out;
   if (SINGLE) {
-    te.inst = 0; te.rank = blockIdx.x; te.size = gridDim.x; te.pad = 0;
+    te.inst = 0; te.rank = xcd_rank(blockIdx.x, gridDim.x); te.size = gridDim.x; te.pad = 0;
     gI = insts;
     st_in = st_in_arg; st_out = st_out_arg; part_in = part_in_arg; part_out = part_out_arg;
   } else {
-    te = teams[blockIdx.x];
+    te = teams[xcd_rank(blockIdx.x, gridDim.x)];
     gI = insts + te.inst;
     st_in = gI->st + parity; st_out = gI->st + (1 - parity);
     part_in = gI->part + (long long)parity * te.size * 4;
@@ -376,17 +392,17 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     case PH_RB_BEGIN: acc = ph_rb_begin(I, tm); break;
     case PH_RB_UPDATE: acc = ph_rb_update(I, tm); break;
     // the mass solves of the consistent initial values run in float64 in every precision
-    case PH_PCG_SETUP: acc = S.kind >= KIND_CI_OMEGA ? ph_pcg_setup<double>(I, S, tm) : ph_pcg_setup<T>(I, S, tm); break;
-    case PH_PCG_A: acc = S.kind >= KIND_CI_OMEGA ? ph_pcg_a<double>(I, S, tm) : ph_pcg_a<T>(I, S, tm); break;
-    case PH_PCG_B: acc = S.kind >= KIND_CI_OMEGA ? ph_pcg_b<double>(I, S, tm) : ph_pcg_b<T>(I, S, tm); break;
+    case PH_PCG_SETUP: acc = is_ci(S.kind) ? ph_pcg_setup<double>(I, S, tm) : ph_pcg_setup<T>(I, S, tm); break;
+    case PH_PCG_A: acc = is_ci(S.kind) ? ph_pcg_a<double>(I, S, tm) : ph_pcg_a<T>(I, S, tm); break;
+    case PH_PCG_B: acc = is_ci(S.kind) ? ph_pcg_b<double>(I, S, tm) : ph_pcg_b<T>(I, S, tm); break;
     case PH_ASPMV: acc = ph_aspmv<T>(I, S, tm); break;
     case PH_MGS: acc = ph_mgs(I, S, tm, false); break;
     case PH_MGS_LAST: acc = ph_mgs(I, S, tm, true); break;
     case PH_UPDATE_X: acc = ph_update_x(I, S, tm, ybuf); break;
     case PH_TRUE_RES: acc = ph_true_res(I, S, tm); break;
     case PH_PCH_OUT: acc = ph_pch_out<T>(I, tm); break;
-    case PH_CG_INIT: acc = S.kind >= KIND_CI_OMEGA ? ph_cg_init<double>(I, S, tm) : ph_cg_init<T>(I, S, tm); break;
-    case PH_CG_ITER: acc = S.kind >= KIND_CI_OMEGA ? ph_cg_iter<double>(I, S, tm) : ph_cg_iter<T>(I, S, tm); break;
+    case PH_CG_INIT: acc = is_ci(S.kind) ? ph_cg_init<double>(I, S, tm) : ph_cg_init<T>(I, S, tm); break;
+    case PH_CG_ITER: acc = is_ci(S.kind) ? ph_cg_iter<double>(I, S, tm) : ph_cg_iter<T>(I, S, tm); break;
     default: break;
   }
   PFC_STAMP(t_work);
@@ -466,6 +482,33 @@ __global__ void k_prep_ops(InstDev I) {
   }
 }
 
+// S_D = M - 2 delta K + delta K M_D^{-1} K on the second-ring pattern (Section 4.1)
+// and its Jacobi diagonal, in the inner precision.
+template <typename T>
+__global__ void k_prep_sd(InstDev I) {
+  const int sl = blockIdx.x * PFC_WAVES + (threadIdx.x >> 6);
+  if (sl >= I.m.n_slices) return;
+  const int lane = threadIdx.x & 63;
+  const int i = sl * 64 + lane;
+  const int base = I.m.w_slice_ptr[sl];
+  const int w = (I.m.w_slice_ptr[sl + 1] - base) >> 6;
+  double dg = 0.0;
+  for (int k = 0; k < w; ++k) {
+    const long long e = (long long)base + k * 64 + lane;
+    const long long p = I.m.w_p1pos[e];
+    double v = p >= 0 ? I.m.M[p] - 2.0 * I.delta * I.m.K[p] : 0.0;
+    double acc = 0.0;
+    for (int t = I.m.w_tri_ptr[e]; t < I.m.w_tri_ptr[e + 1]; ++t) {
+      const int e1 = I.m.w_tri[2 * t], e2 = I.m.w_tri[2 * t + 1];
+      acc += I.m.K[e1] * I.m.dinvM[I.m.col[e1]] * I.m.K[e2];
+    }
+    v += I.delta * acc;
+    ((T*)I.SDv)[e] = T(v);
+    if (I.m.w_col[e] == i) dg += v;
+  }
+  if (i < I.n) ((T*)I.dinvSD)[i] = T(1.0 / dg);
+}
+
 __global__ void k_assemble_N_sell(InstDev I, const double* __restrict__ psi) {
   const int sl = blockIdx.x * PFC_WAVES + (threadIdx.x >> 6);
   if (sl >= I.m.n_slices) return;
@@ -537,6 +580,13 @@ size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int t
   const size_t n = (size_t)m->n, n3 = 3 * n, ns = (size_t)m->nnz_sell;
   const size_t w = o.precision == PFC_MIXED ? 4 : 8;
   const int mr = o.restart;
+  if (o.schur_variant == 1) {
+    h.SDv = take((size_t)m->dev.w_nnz_sell * w);
+    h.dinvSD = take(n * w);
+  } else {
+    h.SDv = nullptr;
+    h.dinvSD = nullptr;
+  }
   h.Cd = o.shared_ops ? nullptr : (void*)take(ns * w);
   h.Csd = o.shared_ops ? nullptr : (void*)take(ns * w);
   h.dinvCd = take(n * w);
@@ -577,6 +627,8 @@ static int validate_opts(const pfc_opts* o) {
   if (o->rows_per_thread < 0 || o->rows_per_thread > 8) { set_error("pfc_opts: rows_per_thread must be 0..8"); return PFC_ERR_ARG; }
   if (o->ticks_per_graph < 0 || o->ticks_per_graph > 4096) { set_error("pfc_opts: ticks_per_graph must be 0..4096"); return PFC_ERR_ARG; }
   if (o->single_reduction != 0 && o->single_reduction != 1) { set_error("pfc_opts: single_reduction must be 0 or 1"); return PFC_ERR_ARG; }
+  if (o->schur_variant != 0 && o->schur_variant != 1) { set_error("pfc_opts: schur_variant must be 0 (S_CH) or 1 (S_D)"); return PFC_ERR_ARG; }
+  if (o->sd_iters < 1 || o->sd_iters > 10000) { set_error("pfc_opts: sd_iters must be in 1..10000"); return PFC_ERR_ARG; }
   return PFC_OK;
 }
 
@@ -720,6 +772,12 @@ static int prep_ops(pfc_instance* I, hipStream_t s) {
     hipLaunchKernelGGL(k_prep_ops<float>, dim3(nb), dim3(PFC_WG), 0, s, h);
   else
     hipLaunchKernelGGL(k_prep_ops<double>, dim3(nb), dim3(PFC_WG), 0, s, h);
+  if (h.schur_d) {
+    if (I->opts.precision == PFC_MIXED)
+      hipLaunchKernelGGL(k_prep_sd<float>, dim3(nb), dim3(PFC_WG), 0, s, h);
+    else
+      hipLaunchKernelGGL(k_prep_sd<double>, dim3(nb), dim3(PFC_WG), 0, s, h);
+  }
   PFC_HIP(hipGetLastError());
   I->ops_tau_s = h.tau_s;
   return PFC_OK;
@@ -839,6 +897,8 @@ void pfc_opts_default(pfc_opts* o) {
   o->max_run_steps = 256;
   o->ticks_per_graph = 0;
   o->single_reduction = 1;
+  o->schur_variant = 0;
+  o->sd_iters = 20;
 }
 
 double pfc_tau_critical(double r, double psibar) {
@@ -850,6 +910,8 @@ double pfc_tau_critical(double r, double psibar) {
 
 size_t pfc_instance_footprint(const pfc_mesh* m, const pfc_opts* o) {
   if (!m || validate_opts(o)) return 0;
+  // the S_D layout is part of the mesh; build it (once) to know its size
+  if (o->schur_variant == 1 && build_second_ring(const_cast<pfc_mesh*>(m))) return 0;
   InstDev h{};
   const int ts = team_size_for(m->n_slices, o->rows_per_thread);
   return carve(h, nullptr, m, *o, ts);
@@ -860,6 +922,7 @@ int pfc_instance_create(pfc_mesh* m, const pfc_opts* o, pfc_instance** out) {
   int rc = validate_opts(o);
   if (rc) return rc;
   *out = nullptr;
+  if (o->schur_variant == 1 && (rc = build_second_ring(m))) return rc;
   pfc_instance* I = new pfc_instance();
   I->mesh = m;
   I->opts = *o;
@@ -878,7 +941,7 @@ int pfc_instance_create(pfc_mesh* m, const pfc_opts* o, pfc_instance** out) {
   }
   I->bytes = bytes;
   carve(h, I->arena, m, *o, I->team_size);
-  h.m = m->dev;
+  h.m = m->dev;  // includes the second-ring layout when it was built
   h.n = m->n;
   h.precision = o->precision;
   h.restart = o->restart;
@@ -886,6 +949,8 @@ int pfc_instance_create(pfc_mesh* m, const pfc_opts* o, pfc_instance** out) {
   h.inner_maxit = o->inner_maxit;
   h.shared_ops = o->shared_ops;
   h.single_reduction = o->single_reduction;
+  h.schur_d = o->schur_variant;
+  h.sd_iters = o->sd_iters;
   h.team_size = I->team_size;
   h.outer_tol = o->outer_tol;
   h.inner_tol = o->inner_tol;

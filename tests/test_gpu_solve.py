@@ -211,3 +211,76 @@ def test_adaptive_rosenbrock_matches_oracle(pfc):
         if inst is not None:
             pfc.pfc_instance_destroy(inst)
         P.close()
+
+
+def test_extreme_parameters_and_status_codes(pfc):
+    """tau beyond tau* (warning status), tiny tau, short restart, and the Arnoldi-step cap."""
+    P = Problem(2, 16, 0.2, seed=41)
+    insts = []
+    try:
+        n = P.n
+        r, psibar = -0.35, -0.3
+        b = np.random.default_rng(8).normal(size=3 * n)
+        Nm = assembly.N_matrix(P.mesh, P.psi)
+        x = dev(np.zeros(3 * n))
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default())
+        insts.append(inst)
+        # the paper accepts steps up to 18 with this preconditioner (Section 6); tau* = 12.26 here
+        tau = 18.0
+        assert tau >= pfc.pfc_tau_critical(r, psibar)
+        st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
+        res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, tau, M11, host(x))) / np.linalg.norm(b)
+        assert st == pfc.PFC_WARN_TAU_CRITICAL and res <= 1e-8
+        st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, 1e-5, M11, dev(b), x)
+        res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, 1e-5, M11, host(x))) / np.linalg.norm(b)
+        assert st == pfc.PFC_OK and res <= 1e-8
+        # restart 3: more cycles, same accuracy
+        i3 = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(restart=3))
+        insts.append(i3)
+        st, gi = pfc.pfc_solve(i3, n, dev(P.psi), r, psibar, 1.0, M11, dev(b), x)
+        res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, 1.0, M11, host(x))) / np.linalg.norm(b)
+        assert st == pfc.PFC_OK and res <= 1e-8 and gi["cycles"] > 1
+        # cap of 4 Arnoldi steps: not converged, info still valid
+        i4 = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(max_steps=4))
+        insts.append(i4)
+        st, gi = pfc.pfc_solve(i4, n, dev(P.psi), r, psibar, 1.0, M11, dev(b), x)
+        res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, 1.0, M11, host(x))) / np.linalg.norm(b)
+        assert st == pfc.PFC_NOT_CONVERGED and gi["outer_iters"] == 4 and abs(gi["true_rel_res"] - res) <= 1e-6 * res
+        # a non-finite right-hand side is a breakdown
+        bad = b.copy()
+        bad[3] = np.nan
+        with pytest.raises(pfc.PFCError) as e:
+            pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, 1.0, M11, dev(bad), x)
+        assert e.value.code == pfc.PFC_ERR_BREAKDOWN
+    finally:
+        for i in insts:
+            pfc.pfc_instance_destroy(i)
+        P.close()
+
+
+@pytest.mark.parametrize("dim,N,jit,tau,prec", [(2, 16, 0.2, 0.1, 0), (3, 5, 0.1, 0.5, 0), (2, 16, 0.2, 0.5, 1)])
+def test_schur_D_variant_parity(pfc, dim, N, jit, tau, prec):
+    """P(S_D) with the fixed 20-iteration inner PCG (Table inner_solvers, last row)."""
+    P = Problem(dim, N, jit, seed=51)
+    inst = None
+    try:
+        r, psibar = -0.35, -0.3
+        n = P.n
+        _, b = _stage1(P, r, tau)
+        Nm = assembly.N_matrix(P.mesh, P.psi)
+        y_ref, info = osolve.solve_stage(P.M, P.K, Nm, r, tau, M11, b, tol=1e-8, schur="D")
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(schur_variant=1, precision=prec))
+        x = dev(np.zeros(3 * n))
+        if prec == 0:
+            s = info["schedule"]
+            st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
+            assert rel(host(x), y_ref) <= 1e-10
+        st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
+        res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, tau, M11, host(x))) / np.linalg.norm(b)
+        assert st == pfc.PFC_OK and res <= 1e-8
+        got = pfc.pfc_last_inner_counts(inst)
+        assert (got[:, 2] == 20).all() and (got[:, 3] == 0).all()
+    finally:
+        if inst is not None:
+            pfc.pfc_instance_destroy(inst)
+        P.close()

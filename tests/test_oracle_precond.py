@@ -102,3 +102,38 @@ def test_printed_PCH_block_does_not_reproduce_printed_spectrum():
     c = 3 * psibar ** 2 + 1 + r
     lam = (1 + tau * (c * mu - 2 * mu ** 2 + mu ** 3)) / ((1 + d * mu) * (1 + math.sqrt(d) * mu) ** 2)
     assert abs(np.trace(A @ np.linalg.inv(P3)) - (2 * n + lam.sum())) > 1e-3
+
+
+@pytest.mark.parametrize("dim,N,tau", [(2, 4, 0.1), (3, 3, 0.5)])
+def test_SD_five_steps_equal_dense_inverse(dim, N, tau):
+    mesh, M, K = _mk(dim, N)
+    inner = precond.InnerSolvers(M, K, tau, mode="exact", schur="D")
+    P3 = precond.P3_dense(M, K, tau, schur="D")
+    v = np.random.default_rng(2).normal(size=3 * mesh.n)
+    z = precond.pch_apply(inner, v)
+    assert np.linalg.norm(z - np.linalg.solve(P3, v)) <= 1e-11 * np.linalg.norm(z)
+
+
+@pytest.mark.parametrize("tau", [0.01, 0.1, 0.3])
+def test_lemma1_interval_3d(tau):
+    """Lemma 1 with the printed tetrahedral bound: eig(S_D^{-1} S) in [0.3924, 2.5]."""
+    mesh, M, K = _mk(3, 4, h=0.7, jitter=0.0)
+    Md, Kd, B = precond.dense_blocks(M, K)
+    S = precond.schur_exact(Md, Kd, B, tau)
+    SD = precond.schur_D_dense(Md, Kd, tau)
+    ev = sla.eigh(S, SD, eigvals_only=True)
+    assert ev.min() >= 0.3924 - 1e-12 and ev.max() <= 2.5 + 1e-12
+
+
+def test_SD_preconditioned_fgmres_converges():
+    from oracle import assembly, solve
+    import workloads as wl
+    mesh = wl.make_mesh(2, 12, jitter=0.1, seed=3)
+    M, K = assembly.mass_stiffness(mesh)
+    psi = wl.psi0(mesh.n, -0.3, 0.05, seed=3)
+    Nm = assembly.N_matrix(mesh, psi)
+    b = np.random.default_rng(1).normal(size=3 * mesh.n)
+    y, info = solve.solve_stage(M, K, Nm, -0.35, 0.1, 1.0, b, tol=1e-8, schur="D")
+    A = pfc.AR_sparse(M, K, Nm, -0.35, 0.1, 1.0)
+    assert info["converged"] and np.linalg.norm(b - A @ y) <= 1e-8 * np.linalg.norm(b)
+    assert all(c[2] == 20 and c[3] == 0 for c in info["schedule"].inner)
