@@ -92,6 +92,7 @@ def bench_batched(args, torch, wl, pfc):
     the plain float64 solver run instance by instance (same instances, same steps)."""
     count = args.batch
     N = 128
+    rpt = 4 if args.rows_per_thread is None else args.rows_per_thread
     mesh = wl.make_mesh(2, N)
     n = mesh.n
     h = pfc.pfc_mesh_create_p1(2, n, mesh.elem_nodes, mesh.elem_coords)
@@ -109,7 +110,8 @@ def bench_batched(args, torch, wl, pfc):
 
     res = {}
     for label, prec, shared in (("batched_mixed", 1, 1), ("batched_fp64", 0, 1)):
-        insts = [pfc.pfc_instance_create(h, pfc.pfc_opts_default(precision=prec, shared_ops=shared))
+        insts = [pfc.pfc_instance_create(h, pfc.pfc_opts_default(precision=prec, shared_ops=shared,
+                                                                 rows_per_thread=rpt))
                  for _ in range(count)]
         st = states()
         pfc.pfc_batch_run(insts, [n] * count, st, [p.r for p in prm], [p.psibar for p in prm],
@@ -149,7 +151,8 @@ def bench_batched(args, torch, wl, pfc):
     out = {"metric": "PFC block solves/s @1e-8 rel residual", "value": res["batched_mixed"]["solves_per_s"],
            "unit": "stage solves/s", "n_gpus": 1, "steps": steps, "warmup": 0, "higher_is_better": True,
            "dtype": "f64 outer / f32 inner", "data": "synthetic",
-           "config": {"workload": f"pfc2d_128_batched{count}_mixed", "instances": count, "grid": N, "nodes": n},
+           "config": {"workload": f"pfc2d_128_batched{count}_mixed", "instances": count, "grid": N, "nodes": n,
+                      "rows_per_thread": rpt},
            "speedup_vs_plain_fp64": res["batched_mixed"]["solves_per_s"] / res["plain_fp64_sequential"]["solves_per_s"],
            "detail": res}
     print(json.dumps(out), flush=True)
@@ -166,12 +169,13 @@ def bench_served(args, torch, wl, pfc):
         meshes.append((m, pfc.pfc_mesh_create_p1(dim, m.n, m.elem_nodes, m.elem_coords)))
     nreq = args.requests
     steps = args.req_steps
+    rpt = 1 if args.rows_per_thread is None else args.rows_per_thread
 
     def stream(rate):
         return wl.served_stream(nreq, rate, 4242)
 
-    def serve(prec, slots, rate):
-        so = pfc.pfc_server_opts(C.sizeof(pfc.pfc_server_opts), prec, 96 << 30, slots, 0)
+    def serve(prec, slots, rate, rpt):
+        so = pfc.pfc_server_opts(C.sizeof(pfc.pfc_server_opts), prec, 96 << 30, slots, 0, rpt)
         srv = C.c_void_p()
         assert pfc._lib.pfc_server_create(C.byref(so), C.byref(srv)) == 0
         reqs = stream(rate)
@@ -206,18 +210,19 @@ def bench_served(args, torch, wl, pfc):
                     max_true_rel_res=worst)
 
     # capacity of the plain server (backlogged), then both at 0.8 of that rate
-    base_bl = serve(0, 1, 0.0)
+    base_bl = serve(0, 1, 0.0, 0)
     rate = 0.8 * nreq / base_bl["wall_s"]
-    ours_bl = serve(1, args.slots, 0.0)
-    base = serve(0, 1, rate)
-    ours = serve(1, args.slots, rate)
+    ours_bl = serve(1, args.slots, 0.0, rpt)
+    base = serve(0, 1, rate, 0)
+    ours = serve(1, args.slots, rate, rpt)
     for _, hm in meshes:
         pfc.pfc_mesh_destroy(hm)
     out = {"metric": "PFC block solves/s @1e-8 rel residual; p50/p99 served latency", "value": ours_bl["solves_per_s"],
            "unit": "stage solves/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64 outer / f32 inner",
            "data": "synthetic",
            "config": {"workload": "served_stream", "requests": nreq, "rosenbrock_steps": steps,
-                      "classes": [f"{d}D {N}" for d, N in classes], "arrival_rate_hz": rate, "slots": args.slots},
+                      "classes": [f"{d}D {N}" for d, N in classes], "arrival_rate_hz": rate, "slots": args.slots,
+                      "rows_per_thread": rpt},
            "speedup_vs_plain_fp64_fifo": ours_bl["solves_per_s"] / base_bl["solves_per_s"],
            "backlogged": {"mixed_continuous": ours_bl, "fp64_fifo": base_bl},
            "poisson": {"mixed_continuous": ours, "fp64_fifo": base}}
@@ -251,6 +256,8 @@ def main():
     ap.add_argument("--requests", type=int, default=48)
     ap.add_argument("--req-steps", type=int, default=5)
     ap.add_argument("--slots", type=int, default=32)
+    ap.add_argument("--rows-per-thread", type=int, default=None,
+                    help="rows per thread of the batched (default 4) and served mixed (default 1) instances")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1"}))

@@ -302,6 +302,10 @@ int pfc_batch_run(pfc_instance* const* insts, int count, double* const* states,
  *   hbm_budget  bytes of device memory the server may hold for instances
  *   max_slots   maximum number of concurrently active requests
  *   precision   PFC_FP64 or PFC_MIXED
+ *   ticks_per_graph  as in pfc_opts (0: default)
+ *   rows_per_thread  rows per thread of the request instances (0: one); more
+ *               rows per thread give each request fewer, longer workgroups,
+ *               which raises throughput when many requests share the GPU
  *   n_steps ... Rosenbrock steps per request (set per request) */
 typedef struct pfc_server_opts {
     int struct_size;
@@ -309,6 +313,7 @@ typedef struct pfc_server_opts {
     size_t hbm_budget;
     int max_slots;
     int ticks_per_graph;
+    int rows_per_thread;
 } pfc_server_opts;
 
 typedef struct pfc_result {

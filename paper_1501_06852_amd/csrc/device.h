@@ -16,7 +16,44 @@ namespace pfc {
 struct Team {
   int rank, size;   // workgroup rank within the team, team size
   int wave, lane;   // wave within the workgroup, lane
+  int lo;           // SELL position of the first staged column (pfc_lcol[0])
 };
+
+// Column indices of the P1 pattern for the workgroup's own slices, staged in
+// LDS by the launch prologue when every slice of the mesh has the same width
+// (at most PFC_LCOL_W) and a workgroup owns at most PFC_WAVES slices.  They are
+// loaded in the same memory round trip as the solver state, which takes the
+// index load off the critical path of every SpMV in the launch.
+#define PFC_LCOL_W 16
+#define PFC_LCOL (PFC_WAVES * 64 * PFC_LCOL_W)
+__shared__ int pfc_lcol[PFC_LCOL];
+
+// Slice geometry and columns of a SELL pattern.  L: the P1 pattern with its
+// columns staged in pfc_lcol (uniform width uw).
+template <bool L>
+struct PatView {
+  const int* sp;    // slice offsets [n_slices + 1]
+  const int* col;   // columns [nnz_sell]
+  int uw;           // uniform slice width, or 0
+  int lo;           // SELL position of pfc_lcol[0] (L only)
+  __device__ __forceinline__ int base(int sl) const {
+    if constexpr (L) return sl * 64 * uw;
+    else return uw ? sl * 64 * uw : sp[sl];
+  }
+  __device__ __forceinline__ int width(int sl) const {
+    if constexpr (L) return uw;
+    else return uw ? uw : ((sp[sl + 1] - sp[sl]) >> 6);
+  }
+  __device__ __forceinline__ int at(long long e) const {
+    if constexpr (L) return pfc_lcol[(int)(e - lo)];
+    else return col[e];
+  }
+};
+
+template <bool L>
+__device__ __forceinline__ PatView<L> p1_pat(const InstDev& I, const Team& tm) {
+  return PatView<L>{I.m.slice_ptr, I.m.col, I.m.uw, tm.lo};
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -180,13 +217,15 @@ __device__ double node_psi3(const MeshDev& m, int i, PsiF psi) {
 // Every phase returns this thread's contribution to the two partial sums.
 
 // N(psi_k) = -3 Mpsi2 reassembled in place (one value per stored entry).
+template <bool L>
 __device__ Red3 ph_rb_begin(const InstDev& I, const Team& tm) {
   const int n = I.n;
   const double* xk = I.xk;
   auto psi = [&](int j) { return xk[n + j]; };
+  const PatView<L> pv = p1_pat<L>(I, tm);
   PFC_SLICES(I, tm) {
-    const int base = I.m.slice_ptr[sl];
-    const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
+    const int base = pv.base(sl);
+    const int w = pv.width(sl);
     const int lane = tm.lane;
     for (int k = 0; k < w; ++k) {
       const long long e = (long long)base + k * 64 + lane;
@@ -208,17 +247,18 @@ __device__ __forceinline__ double stage_comb(const InstDev& I, int stage, int bl
 // Stage right-hand side at the row of (slice, lane) (Section 3.1): F(x_i) with
 // block 1 multiplied by tau, plus sum_j c_ij M y_j^psi on block 1, with the
 // stage state x_i = x_k + sum_j a_ij y_j formed on the fly.
-__device__ __forceinline__ void stage_rhs_row(const InstDev& I, int sl, int lane, int stage, double& b0, double& b1,
-                                              double& b2) {
+template <bool L>
+__device__ __forceinline__ void stage_rhs_row(const InstDev& I, const PatView<L>& pv, int sl, int lane, int stage,
+                                              double& b0, double& b1, double& b2) {
   const int n = I.n;
   const int i = sl * 64 + lane;
-  const int base = I.m.slice_ptr[sl];
-  const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
+  const int base = pv.base(sl);
+  const int w = pv.width(sl);
   double sMmu = 0, sMps = 0, sMom = 0, sKmu = 0, sKps = 0, sKom = 0, sMy1 = 0, sMy2 = 0;
   const long long n3 = 3LL * n;
   for (int k = 0; k < w; ++k) {
     const long long e = (long long)base + k * 64 + lane;
-    const int j = I.m.col[e];
+    const int j = pv.at(e);
     const double Mv = I.m.M[e], Kv = I.m.K[e];
     const double mu = stage_comb(I, stage, 0, j);
     const double ps = stage_comb(I, stage, 1, j);
@@ -239,16 +279,18 @@ __device__ __forceinline__ void stage_rhs_row(const InstDev& I, int sl, int lane
 
 // Right-hand side of the solve: stage rhs b_i^R for job RB, the caller's rhs
 // for job SOLVE.  Writes W = b with block 1 divided by m11, X = 0.
+template <bool L>
 __device__ Red3 ph_solve_init(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   const bool rb = (S.job == JOB_RB);
+  const PatView<L> pv = p1_pat<L>(I, tm);
   double* X = rb ? (I.ys + (long long)(S.stage - 1) * 3 * n) : I.x_user;
   const double im = 1.0 / I.m11;
   double a0 = 0.0, a1 = 0.0;
   PFC_SLICES(I, tm) {
     const int i = sl * 64 + tm.lane;
     double b0 = 0.0, b1 = 0.0, b2 = 0.0;
-    if (rb) stage_rhs_row(I, sl, tm.lane, S.stage, b0, b1, b2);
+    if (rb) stage_rhs_row<L>(I, pv, sl, tm.lane, S.stage, b0, b1, b2);
     if (i < n) {
       if (rb) {
         vst(I.b + i, b0); vst(I.b + n + i, b1); vst(I.b + 2 * n + i, b2);
@@ -334,29 +376,37 @@ __device__ __forceinline__ PcgOps<T> pcg_ops(const InstDev& I, int kind) {
   return o;
 }
 
+// Pattern of the operator of a PCG solve: the P1 pattern (staged columns when
+// L) or, for S_D, the second-ring pattern (never staged).
+template <bool L, typename T>
+__device__ __forceinline__ PatView<L> op_pat(const InstDev& I, const PcgOps<T>& o, const Team& tm) {
+  return PatView<L>{o.sp, o.colp, o.sp == I.m.slice_ptr ? I.m.uw : 0, tm.lo};
+}
+
 template <typename T>
 __device__ __forceinline__ T opval(const PcgOps<T>& o, long long e) {
   return o.C ? o.C[e] : (o.Mv[e] + o.cK * o.Kv[e]);
 }
 
 // y_i = (A v)_i for a stored operator A (typed) over the row of thread lane
-template <typename T, typename VF>
-__device__ __forceinline__ T row_dot(const InstDev& I, int sl, int lane, const T* A, VF v) {
-  const int base = I.m.slice_ptr[sl];
-  const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
+template <typename T, bool L, typename VF>
+__device__ __forceinline__ T row_dot(const PatView<L>& pv, int sl, int lane, const T* A, VF v) {
+  const int base = pv.base(sl);
+  const int w = pv.width(sl);
   T acc = T(0);
   for_width(w, [&](int k) {
     const long long e = (long long)base + k * 64 + lane;
-    acc += A[e] * v(I.m.col[e]);
+    acc += A[e] * v(pv.at(e));
   });
   return acc;
 }
 
-template <typename T>
+template <typename T, bool L>
 __device__ Red3 ph_pcg_setup(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   const int kind = S.kind;
   PcgOps<T> o = pcg_ops<T>(I, kind);
+  const PatView<L> pv = p1_pat<L>(I, tm);   // every right-hand side is a P1 product
   T* r = (T*)I.r_;
   const long long n3 = 3LL * n;
   double* Vj = I.V + (long long)S.j * n3;
@@ -379,23 +429,23 @@ __device__ Red3 ph_pcg_setup(const InstDev& I, const State& S, const Team& tm) {
       } break;
       case KIND_Y1: {  // (2): b1 - tau K y0
         const T* y0 = (const T*)I.y0;
-        const T ky = row_dot<T>(I, sl, lane, Kv, [&](int j) { return y0[j]; });
+        const T ky = row_dot<T>(pv, sl, lane, Kv, [&](int j) { return y0[j]; });
         if (i < n) rhs = Vj[n + i] - I.tau_s * (double)ky;
       } break;
       case KIND_SD:   // (3) with S_D: M y1
       case KIND_Z: {  // (3.1): M y1
         const T* y1 = (const T*)I.y1;
-        const T my = row_dot<T>(I, sl, lane, Mv, [&](int j) { return y1[j]; });
+        const T my = row_dot<T>(pv, sl, lane, Mv, [&](int j) { return y1[j]; });
         rhs = (double)my;
       } break;
       case KIND_X1: {  // (3.2): M z
         const T* zt = (const T*)I.zt;
-        const T mz = row_dot<T>(I, sl, lane, Mv, [&](int j) { return zt[j]; });
+        const T mz = row_dot<T>(pv, sl, lane, Mv, [&](int j) { return zt[j]; });
         rhs = (double)mz;
       } break;
       case KIND_X2: {  // (5): b2 - K x1, and (4): x0 = y0 + (y1 - x1)/delta
         const T* x1 = (const T*)I.x1;
-        const T kx = row_dot<T>(I, sl, lane, Kv, [&](int j) { return x1[j]; });
+        const T kx = row_dot<T>(pv, sl, lane, Kv, [&](int j) { return x1[j]; });
         if (i < n) {
           rhs = Vj[2 * n + i] - (double)kx;
           const double y0i = (double)((const T*)I.y0)[i], y1i = (double)((const T*)I.y1)[i];
@@ -405,16 +455,16 @@ __device__ Red3 ph_pcg_setup(const InstDev& I, const State& S, const Team& tm) {
         }
       } break;
       case KIND_CI_OMEGA: {  // M omega_0 = -K psi_0
-        const double kp = row_dot<double>(I, sl, lane, I.m.K, [&](int j) { return I.xk[n + j]; });
+        const double kp = row_dot<double>(pv, sl, lane, I.m.K, [&](int j) { return I.xk[n + j]; });
         rhs = -kp;
       } break;
       case KIND_CI_MU: {  // M mu_0 = (1+r) M psi_0 - 2 K psi_0 - K omega_0 + g(psi_0)
-        const int base = I.m.slice_ptr[sl];
-        const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
+        const int base = pv.base(sl);
+        const int w = pv.width(sl);
         double sMp = 0, sKp = 0, sKo = 0;
         for (int k = 0; k < w; ++k) {
           const long long e = (long long)base + k * 64 + lane;
-          const int j = I.m.col[e];
+          const int j = pv.at(e);
           sMp += I.m.M[e] * I.xk[n + j];
           sKp += I.m.K[e] * I.xk[n + j];
           sKo += I.m.K[e] * I.xk[2 * n + j];
@@ -444,10 +494,11 @@ __device__ __forceinline__ T pval(const T* dinv, const T* r, const T* pold, T be
   return first ? z : (z + beta * pold[j]);
 }
 
-template <typename T>
+template <typename T, bool L>
 __device__ Red3 ph_pcg_a(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   PcgOps<T> o = pcg_ops<T>(I, S.kind);
+  const PatView<L> pv = op_pat<L>(I, o, tm);
   const T* r = (const T*)I.r_;
   const T* pold = (const T*)(S.pcur ? I.pB : I.pA);
   T* pnew = (T*)(S.pcur ? I.pA : I.pB);
@@ -457,12 +508,12 @@ __device__ Red3 ph_pcg_a(const InstDev& I, const State& S, const Team& tm) {
   double a0 = 0.0;
   PFC_SLICES(I, tm) {
     const int i = sl * 64 + tm.lane;
-    const int base = o.sp[sl];
-    const int w = (o.sp[sl + 1] - base) >> 6;
+    const int base = pv.base(sl);
+    const int w = pv.width(sl);
     T acc = T(0);
     for_width(w, [&](int k) {
       const long long e = (long long)base + k * 64 + tm.lane;
-      const int j = o.colp[e];
+      const int j = pv.at(e);
       acc += opval(o, e) * pval(o.dinv, r, pold, beta, first, j);
     });
     if (i < n) {
@@ -504,16 +555,16 @@ __device__ Red3 ph_pcg_b(const InstDev& I, const State& S, const Team& tm) {
 //   w0 = M mu + (-(1+r) M + 2K + N) psi + K omega
 //   w1 = t K mu + s M psi
 //   w2 = K psi + M omega
-template <typename YF>
-__device__ __forceinline__ void block_row(const InstDev& I, int sl, int lane, double t, double s, YF y,
-                                          double& w0, double& w1, double& w2) {
-  const int base = I.m.slice_ptr[sl];
-  const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
+template <bool L, typename YF>
+__device__ __forceinline__ void block_row(const InstDev& I, const PatView<L>& pv, int sl, int lane, double t, double s,
+                                          YF y, double& w0, double& w1, double& w2) {
+  const int base = pv.base(sl);
+  const int w = pv.width(sl);
   const double c1 = -(1.0 + I.r);
   w0 = w1 = w2 = 0.0;
   for_width(w, [&](int k) {
     const long long e = (long long)base + k * 64 + lane;
-    const int j = I.m.col[e];
+    const int j = pv.at(e);
     const double Mv = I.m.M[e], Kv = I.m.K[e], Nv = I.N[e];
     double mu, ps, om;
     y(j, mu, ps, om);
@@ -523,9 +574,10 @@ __device__ __forceinline__ void block_row(const InstDev& I, int sl, int lane, do
   });
 }
 
-template <typename T>
+template <typename T, bool L>
 __device__ Red3 ph_aspmv(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
+  const PatView<L> pv = p1_pat<L>(I, tm);
   const long long n3 = 3LL * n;
   double* Zj = I.Z + (long long)S.j * n3;
   const T* x2 = (const T*)I.x2;
@@ -534,7 +586,7 @@ __device__ Red3 ph_aspmv(const InstDev& I, const State& S, const Team& tm) {
   PFC_SLICES(I, tm) {
     const int i = sl * 64 + tm.lane;
     double w0, w1, w2;
-    block_row(I, sl, tm.lane, I.tau_s, 1.0,
+    block_row<L>(I, pv, sl, tm.lane, I.tau_s, 1.0,
               [&](int j, double& mu, double& ps, double& om) { mu = Zj[j]; ps = Zj[n + j]; om = (double)x2[j]; },
               w0, w1, w2);
     if (i < n) {
@@ -588,8 +640,10 @@ __device__ Red3 ph_update_x(const InstDev& I, const State& S, const Team& tm, co
   return red3(0.0, 0.0);
 }
 
+template <bool L>
 __device__ Red3 ph_true_res(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
+  const PatView<L> pv = p1_pat<L>(I, tm);
   const long long n3 = 3LL * n;
   const bool rb = (S.job == JOB_RB);
   const double* X = rb ? (I.ys + (long long)(S.stage - 1) * n3) : I.x_user;
@@ -599,7 +653,7 @@ __device__ Red3 ph_true_res(const InstDev& I, const State& S, const Team& tm) {
   PFC_SLICES(I, tm) {
     const int i = sl * 64 + tm.lane;
     double w0, w1, w2;
-    block_row(I, sl, tm.lane, I.tau, I.m11,
+    block_row<L>(I, pv, sl, tm.lane, I.tau, I.m11,
               [&](int j, double& mu, double& ps, double& om) { mu = X[j]; ps = X[n + j]; om = X[2 * n + j]; },
               w0, w1, w2);
     if (i < n) {
@@ -647,21 +701,22 @@ __device__ __forceinline__ T cg_unew(const T* dinv, const T* rc, const T* wc, co
   return dinv[j] * (rc[j] - alpha * cg_s(wc, so, beta, first, j));
 }
 
-template <typename T>
+template <typename T, bool L>
 __device__ Red3 ph_cg_init(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   PcgOps<T> o = pcg_ops<T>(I, S.kind);
+  const PatView<L> pv = op_pat<L>(I, o, tm);
   const T* r = (const T*)I.r_;
   T* w = (T*)I.q;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   PFC_SLICES(I, tm) {
     const int i = sl * 64 + tm.lane;
-    const int base = o.sp[sl];
-    const int wd = (o.sp[sl + 1] - base) >> 6;
+    const int base = pv.base(sl);
+    const int wd = pv.width(sl);
     T acc = T(0);
     for_width(wd, [&](int k) {
       const long long e = (long long)base + k * 64 + tm.lane;
-      const int j = o.colp[e];
+      const int j = pv.at(e);
       acc += opval(o, e) * (o.dinv[j] * r[j]);
     });
     if (i < n) {
@@ -675,10 +730,11 @@ __device__ Red3 ph_cg_init(const InstDev& I, const State& S, const Team& tm) {
   return red3(a0, a1, a2);
 }
 
-template <typename T>
+template <typename T, bool L>
 __device__ Red3 ph_cg_iter(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   PcgOps<T> o = pcg_ops<T>(I, S.kind);
+  const PatView<L> pv = op_pat<L>(I, o, tm);
   const int c = S.cur;
   const T* rc = (const T*)(c ? I.rB : I.r_);
   T* rn = (T*)(c ? I.r_ : I.rB);
@@ -692,12 +748,12 @@ __device__ Red3 ph_cg_iter(const InstDev& I, const State& S, const Team& tm) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   PFC_SLICES(I, tm) {
     const int i = sl * 64 + tm.lane;
-    const int base = o.sp[sl];
-    const int wd = (o.sp[sl + 1] - base) >> 6;
+    const int base = pv.base(sl);
+    const int wd = pv.width(sl);
     T acc = T(0);
     for_width(wd, [&](int k) {
       const long long e = (long long)base + k * 64 + tm.lane;
-      const int j = o.colp[e];
+      const int j = pv.at(e);
       acc += opval(o, e) * cg_unew(o.dinv, rc, wc, so, alpha, beta, first, j);
     });
     if (i < n) {

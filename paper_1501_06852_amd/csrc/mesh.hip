@@ -225,6 +225,15 @@ static int finish_layout(pfc_mesh* m, const int32_t* en, const std::vector<int>&
     sptr[s + 1] = (int)nxt;
   }
   m->nnz_sell = sptr[m->n_slices];
+  // common slice width (structured meshes): lets kernels compute slice offsets
+  // and stage a workgroup's columns in LDS
+  m->uniform_width = 0;
+  if (m->n_slices > 0) {
+    const int w0 = (sptr[1] - sptr[0]) / 64;
+    bool same = w0 >= 1 && w0 <= PFC_LCOL_W;
+    for (int s = 1; same && s < m->n_slices; ++s) same = (sptr[s + 1] - sptr[s]) / 64 == w0;
+    if (same) m->uniform_width = w0;
+  }
   std::vector<int> scol((size_t)m->nnz_sell);
   m->csr2sell.assign(m->nnz, 0);
   for (int s = 0; s < m->n_slices; ++s) {
@@ -285,6 +294,7 @@ static int finish_layout(pfc_mesh* m, const int32_t* en, const std::vector<int>&
   if ((rc = upload<float>(&m->d_dinvMf, nullptr, n))) return rc;
   MeshDev& d = m->dev;
   d.n = n; d.dim = m->dim; d.n_slices = m->n_slices; d.n_elem = m->n_elem; d.nnz_sell = m->nnz_sell;
+  d.uw = m->uniform_width;
   d.slice_ptr = m->d_slice_ptr; d.col = m->d_col; d.M = m->d_M; d.K = m->d_K; d.Mf = m->d_Mf; d.Kf = m->d_Kf;
   d.dinvM = m->d_dinvM; d.dinvMf = m->d_dinvMf; d.sl_el_ptr = m->d_sl_el_ptr; d.sl_el = m->d_sl_el;
   d.nd_el_ptr = m->d_nd_el_ptr; d.nd_el = m->d_nd_el; d.elem_nodes = m->d_elem_nodes; d.elem_vol = m->d_vol;

@@ -51,6 +51,7 @@ enum { KIND_Y0 = 0, KIND_Y1 = 1, KIND_Z = 2, KIND_X1 = 3, KIND_X2 = 4, KIND_CI_O
 struct MeshDev {
   int n, dim, n_slices, n_elem;
   long long nnz_sell;
+  int uw, pad_uw;         // common width of all slices (structured meshes), 0 if they differ
   const int* slice_ptr;   // [n_slices+1] entry offset of each slice (multiple of 64)
   const int* col;         // [nnz_sell]
   const double* M;        // [nnz_sell]
@@ -149,7 +150,13 @@ struct InstDev {
   InfoDev* info;                // [max_infos]
 };
 
-struct TeamEntry { int inst, rank, size, pad; };
+// One workgroup of a launch: its instance, its rank in the instance's team,
+// and the P1 pattern of the instance's mesh for the column staging.
+struct TeamEntry {
+  int inst, rank, size, uw;
+  const int* col;
+  int n_slices, pad;
+};
 
 // Rosenbrock coefficients of Table rosenbrock_scheme (Ros3Pw, modified form).
 #define ROS_GAMMA 0.78867513459481287

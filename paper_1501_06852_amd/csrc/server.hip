@@ -69,6 +69,7 @@ pfc_opts server_instance_opts(const pfc_server* S) {
   pfc_opts_default(&o);
   o.precision = S->o.precision;
   o.ticks_per_graph = S->o.ticks_per_graph;
+  o.rows_per_thread = S->o.rows_per_thread;
   return o;
 }
 
@@ -247,7 +248,8 @@ extern "C" {
 
 int pfc_server_create(const pfc_server_opts* o, pfc_server** out) {
   if (!o || !out || o->struct_size != (int)sizeof(pfc_server_opts) || o->max_slots < 1 || o->hbm_budget == 0 ||
-      (o->precision != PFC_FP64 && o->precision != PFC_MIXED) || o->ticks_per_graph < 0 || o->ticks_per_graph > 4096) {
+      (o->precision != PFC_FP64 && o->precision != PFC_MIXED) || o->ticks_per_graph < 0 || o->ticks_per_graph > 4096 ||
+      o->rows_per_thread < 0 || o->rows_per_thread > 8) {
     set_error("pfc_server_create: invalid options");
     return PFC_ERR_ARG;
   }

@@ -12,6 +12,8 @@ namespace pfc {
 struct Group {
   int count = 0, n_wg = 0, graph_ticks = 0;
   TeamEntry* d_teams = nullptr;
+  std::vector<TeamEntry> h_teams;
+  bool lds = false;             // launches stage the P1 columns in LDS
   InstDev* d_descs = nullptr;
   InstDev* h_descs = nullptr;   // pinned staging of the descriptors
   State* h_states = nullptr;    // pinned staging of the initial states

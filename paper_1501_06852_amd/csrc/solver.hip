@@ -197,6 +197,25 @@ __device__ void givens(State& S, const InstDev& I, bool wr, double hn2, double* 
   S.phase = PH_UPDATE_X;
 }
 
+// The most frequent transition, a single-reduction PCG iteration that is not
+// the last of its solve, kept inline next to the launch prologue (the general
+// transition below is out of line and its code is fetched only when needed).
+// Same decisions and arithmetic as the PH_CG_ITER case of transition().
+__device__ __forceinline__ bool cg_iter_continues(State& S, const InstDev& I, Red3 red) {
+  if (S.phase != PH_CG_ITER || I.replay || S.kind == KIND_SD || is_ci(S.kind)) return false;
+  const int it = S.it + 1;
+  const double g = red.a, dl = red.b, rr = red.c;
+  const double tol = I.inner_tol;
+  if (it >= I.inner_maxit || rr <= tol * tol * S.bb || g == 0.0 || !isfinite(rr)) return false;
+  S.it = it;
+  S.cur ^= 1;
+  const double beta = g / S.rho;
+  S.alpha = g / (dl - beta * g / S.alpha);
+  S.beta_cg = beta;
+  S.rho = g;
+  return true;
+}
+
 __device__ void transition(State& S, const InstDev& I, bool wr, Red3 red, double* ybuf, double* col) {
   switch (S.phase) {
     case PH_START:
@@ -322,13 +341,17 @@ __device__ unsigned long long g_trace_cap = 0;
 #endif
 
 // One solver launch.  SINGLE: the launch serves one instance and receives its
-// state and partial-sum buffers as kernel arguments (preloaded into scalar
-// registers), so the first memory round trip already fetches the state.
-// Otherwise each workgroup looks up its team and instance descriptor.
-template <typename T, bool SINGLE>
+// state and partial-sum buffers and its mesh pattern as kernel arguments
+// (preloaded into scalar registers), so the first memory round trip already
+// fetches the state.  Otherwise each workgroup looks up its team entry and
+// instance descriptor.  LDS: the workgroup's P1 columns are staged in LDS in
+// the same round trip (uniform slice width, at most PFC_WAVES slices per
+// workgroup; the host launches this variant only then).
+template <typename T, bool SINGLE, bool LDS>
 __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ teams, const InstDev* __restrict__ insts,
                                                  const State* st_in_arg, State* st_out_arg, const double* part_in_arg,
-                                                 double* part_out_arg, int parity) {
+                                                 double* part_out_arg, int parity, const int* __restrict__ col_arg,
+                                                 int uw_arg, int nsl_arg) {
   __shared__ State S;
   __shared__ InstDev sI;
   __shared__ Red3 lds4[PFC_WAVES];
@@ -343,7 +366,8 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   const double* part_in;
   double* part_out;
   if (SINGLE) {
-    te.inst = 0; te.rank = xcd_rank(blockIdx.x, gridDim.x); te.size = gridDim.x; te.pad = 0;
+    te.inst = 0; te.rank = xcd_rank(blockIdx.x, gridDim.x); te.size = gridDim.x;
+    te.uw = uw_arg; te.col = col_arg; te.n_slices = nsl_arg; te.pad = 0;
     gI = insts;
     st_in = st_in_arg; st_out = st_out_arg; part_in = part_in_arg; part_out = part_out_arg;
   } else {
@@ -357,15 +381,42 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   // the instance descriptor, loaded by different threads at the same time
   constexpr int NS = (int)(sizeof(State) / 4), ND = (int)(sizeof(InstDev) / 4);
   static_assert(NS <= 64 && ND <= PFC_WG - 64, "state / descriptor too large for the staging threads");
+  // columns of this workgroup's slices: positions [lo, lo + len) of the SELL
+  // pattern, issued first and written to LDS once everything has arrived
+  int lo = 0, len = 0;
+  int cv[PFC_LCOL_W];
+  if (LDS) {
+    const int spw = (te.n_slices + te.size - 1) / te.size;
+    const int sbeg = te.rank * spw;
+    const int send = min(sbeg + spw, te.n_slices);
+    lo = sbeg * 64 * te.uw;
+    len = max(send - sbeg, 0) * 64 * te.uw;
+#pragma unroll
+    for (int q = 0; q < PFC_LCOL_W; ++q) {
+      const int idx = tid + q * PFC_WG;
+      if (idx < len) cv[q] = te.col[lo + idx];
+    }
+  }
   Red3 pre = red3(0.0, 0.0, 0.0);
   for (int k = tid; k < te.size; k += PFC_WG) { pre.a += part_in[4 * k]; pre.b += part_in[4 * k + 1]; pre.c += part_in[4 * k + 2]; }
   if (tid < NS) ((int*)&S)[tid] = ((const int*)st_in)[tid];
   else if (tid >= 64 && tid < 64 + ND) ((int*)&sI)[tid - 64] = ((const int*)gI)[tid - 64];
+  if (LDS) {
+#pragma unroll
+    for (int q = 0; q < PFC_LCOL_W; ++q) {
+      const int idx = tid + q * PFC_WG;
+      if (idx < len) pfc_lcol[idx] = cv[q];
+    }
+  }
   pre.a = wave_sum(pre.a);
   pre.b = wave_sum(pre.b);
   pre.c = wave_sum(pre.c);
   if ((tid & 63) == 0) lds4[tid >> 6] = pre;
   __syncthreads();
+#ifdef PFC_TICK_TIMING
+  const unsigned long long t_ld = wall_clock64();
+  unsigned long long t_red = 0;
+#endif
   const InstDev& I = sI;
   const bool writer = (te.rank == 0);
   if (S.phase == PH_DONE) {
@@ -378,31 +429,38 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
 #pragma unroll
       for (int w = 0; w < PFC_WAVES; ++w) { red.a += lds4[w].a; red.b += lds4[w].b; red.c += lds4[w].c; }
     }
-    transition(S, I, writer, red, ybuf, gcol);
+    if (!cg_iter_continues(S, I, red)) transition(S, I, writer, red, ybuf, gcol);
   }
   __syncthreads();
   PFC_STAMP(t_trans);
   // the new state is final: workgroup 0 stores it while the phase runs
   if (writer && tid < NS) ((int*)st_out)[tid] = ((const int*)&S)[tid];
-  Team tm{te.rank, te.size, tid >> 6, tid & 63};
+  Team tm{te.rank, te.size, tid >> 6, tid & 63, lo};
+  const bool sd = (S.kind == KIND_SD);  // second-ring pattern, never staged
   Red3 acc = red3(0.0, 0.0, 0.0);
   switch (S.phase) {
     case PH_SOLVE_INIT:
-    case PH_RB_RHS: acc = ph_solve_init(I, S, tm); break;
-    case PH_RB_BEGIN: acc = ph_rb_begin(I, tm); break;
+    case PH_RB_RHS: acc = ph_solve_init<LDS>(I, S, tm); break;
+    case PH_RB_BEGIN: acc = ph_rb_begin<LDS>(I, tm); break;
     case PH_RB_UPDATE: acc = ph_rb_update(I, tm); break;
     // the mass solves of the consistent initial values run in float64 in every precision
-    case PH_PCG_SETUP: acc = is_ci(S.kind) ? ph_pcg_setup<double>(I, S, tm) : ph_pcg_setup<T>(I, S, tm); break;
-    case PH_PCG_A: acc = is_ci(S.kind) ? ph_pcg_a<double>(I, S, tm) : ph_pcg_a<T>(I, S, tm); break;
+    case PH_PCG_SETUP: acc = is_ci(S.kind) ? ph_pcg_setup<double, LDS>(I, S, tm) : ph_pcg_setup<T, LDS>(I, S, tm); break;
+    case PH_PCG_A:
+      acc = is_ci(S.kind) ? ph_pcg_a<double, LDS>(I, S, tm) : sd ? ph_pcg_a<T, false>(I, S, tm) : ph_pcg_a<T, LDS>(I, S, tm);
+      break;
     case PH_PCG_B: acc = is_ci(S.kind) ? ph_pcg_b<double>(I, S, tm) : ph_pcg_b<T>(I, S, tm); break;
-    case PH_ASPMV: acc = ph_aspmv<T>(I, S, tm); break;
+    case PH_ASPMV: acc = ph_aspmv<T, LDS>(I, S, tm); break;
     case PH_MGS: acc = ph_mgs(I, S, tm, false); break;
     case PH_MGS_LAST: acc = ph_mgs(I, S, tm, true); break;
     case PH_UPDATE_X: acc = ph_update_x(I, S, tm, ybuf); break;
-    case PH_TRUE_RES: acc = ph_true_res(I, S, tm); break;
+    case PH_TRUE_RES: acc = ph_true_res<LDS>(I, S, tm); break;
     case PH_PCH_OUT: acc = ph_pch_out<T>(I, tm); break;
-    case PH_CG_INIT: acc = is_ci(S.kind) ? ph_cg_init<double>(I, S, tm) : ph_cg_init<T>(I, S, tm); break;
-    case PH_CG_ITER: acc = is_ci(S.kind) ? ph_cg_iter<double>(I, S, tm) : ph_cg_iter<T>(I, S, tm); break;
+    case PH_CG_INIT:
+      acc = is_ci(S.kind) ? ph_cg_init<double, LDS>(I, S, tm) : sd ? ph_cg_init<T, false>(I, S, tm) : ph_cg_init<T, LDS>(I, S, tm);
+      break;
+    case PH_CG_ITER:
+      acc = is_ci(S.kind) ? ph_cg_iter<double, LDS>(I, S, tm) : sd ? ph_cg_iter<T, false>(I, S, tm) : ph_cg_iter<T, LDS>(I, S, tm);
+      break;
     default: break;
   }
   PFC_STAMP(t_work);
@@ -412,6 +470,9 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     acc.c = wave_sum(acc.c);
     if ((tid & 63) == 0) lds4[tid >> 6] = acc;
     __syncthreads();
+#ifdef PFC_TICK_TIMING
+    t_red = wall_clock64();
+#endif
     if (tid == 0) {
       Red3 r = red3(0.0, 0.0, 0.0);
 #pragma unroll
@@ -423,13 +484,13 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
 #ifdef PFC_TICK_TIMING
   __syncthreads();
   PFC_STAMP(t_exit);
-  const unsigned long long t_loaded = t_trans;
   if (tid == 0 && (te.rank == 0 || te.rank == te.size - 1) && g_trace) {
     const unsigned long long k = atomicAdd(&g_trace_n, 1ULL);
     if (k < g_trace_cap) {
       unsigned long long* r = g_trace + 8 * k;
-      r[0] = (unsigned long long)S.phase | ((unsigned long long)te.rank << 8) | ((unsigned long long)S.kind << 40);
-      r[1] = t_entry; r[2] = t_loaded; r[3] = t_trans; r[4] = t_work; r[5] = t_exit; r[6] = blockIdx.x; r[7] = 0;
+      r[0] = (unsigned long long)S.phase | ((unsigned long long)te.rank << 8) | ((unsigned long long)S.kind << 40) |
+             ((unsigned long long)(S.it & 0xffff) << 48);
+      r[1] = t_entry; r[2] = t_ld; r[3] = t_trans; r[4] = t_work; r[5] = t_exit; r[6] = blockIdx.x; r[7] = t_red;
     }
   }
 #endif
@@ -528,7 +589,8 @@ __global__ void k_apply_AR(InstDev I, const double* __restrict__ y, double* __re
   const int i = sl * 64 + lane;
   const int n = I.n;
   double w0, w1, w2;
-  block_row(I, sl, lane, I.tau, I.m11,
+  const PatView<false> pv{I.m.slice_ptr, I.m.col, I.m.uw, 0};
+  block_row<false>(I, pv, sl, lane, I.tau, I.m11,
             [&](int j, double& mu, double& ps, double& om) { mu = y[j]; ps = y[n + j]; om = y[2 * n + j]; }, w0, w1, w2);
   if (i < n) { out[i] = w0; out[n + i] = w1; out[2 * n + i] = w2; }
 }
@@ -561,7 +623,8 @@ __global__ void k_stage_rhs(InstDev I, int stage, double* __restrict__ b) {
   const int lane = threadIdx.x & 63;
   const int i = sl * 64 + lane;
   double b0, b1, b2;
-  stage_rhs_row(I, sl, lane, stage, b0, b1, b2);
+  const PatView<false> pv{I.m.slice_ptr, I.m.col, I.m.uw, 0};
+  stage_rhs_row<false>(I, pv, sl, lane, stage, b0, b1, b2);
   if (i < I.n) { b[i] = b0; b[I.n + i] = b1; b[2 * I.n + i] = b2; }
 }
 
@@ -657,6 +720,30 @@ int Group::build(hipStream_t capture, int precision, int ticks) {
     set_error("internal: team size mismatch");
     return PFC_ERR_STATE;
   }
+  // the mesh pattern of every team entry, and whether the launches stage the
+  // columns.  They can when every mesh has a uniform slice width <= PFC_LCOL_W
+  // and a workgroup owns at most PFC_WAVES slices (the staging buffer holds
+  // exactly that).  Staging moves the column stream into the prologue's round
+  // trip; it pays where that stream is a large share of a launch's bytes
+  // (measured: 3D 64^3 mixed +5.7%, the mixed 2D/3D served mix +6%, 2D 512^2
+  // float64 -2%, where the 7 columns are 16% of an iteration's bytes), so
+  // float64 runs stage only from 8 columns per row on (3D: 22%).
+  lds = true;
+  for (TeamEntry& t : h_teams) {
+    const MeshDev& m = h_descs[t.inst].m;
+    t.uw = m.uw;
+    t.col = m.col;
+    t.n_slices = m.n_slices;
+    if (!(m.uw >= 1 && m.uw <= PFC_LCOL_W && (m.n_slices + t.size - 1) / t.size <= PFC_WAVES)) lds = false;
+    if (precision == PFC_FP64 && m.uw < 8) lds = false;
+  }
+#ifdef PFC_NO_COLUMN_STAGING
+  lds = false;
+#endif
+  PFC_HIP(hipMemcpy(d_teams, h_teams.data(), sizeof(TeamEntry) * h_teams.size(), hipMemcpyHostToDevice));
+  const int* pcol = count == 1 ? h_descs[0].m.col : nullptr;
+  const int puw = count == 1 ? h_descs[0].m.uw : 0;
+  const int pnsl = count == 1 ? h_descs[0].m.n_slices : 0;
   PFC_HIP(hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal));
   for (int t = 0; t < ticks; ++t) {
     const int par = t & 1;
@@ -670,17 +757,18 @@ int Group::build(hipStream_t capture, int precision, int ticks) {
       pin = h_descs[0].part + (size_t)par * n_wg * 4;
       pout = h_descs[0].part + (size_t)(1 - par) * n_wg * 4;
     }
+#define PFC_TICK(TT, SG, LD)                                                                                    \
+  hipLaunchKernelGGL((k_tick<TT, SG, LD>), dim3(n_wg), dim3(PFC_WG), 0, capture, d_teams, d_descs, sin, sout, pin, pout, \
+                     par, pcol, puw, pnsl)
+    const bool sg = (count == 1);
     if (precision == PFC_MIXED) {
-      if (count == 1)
-        hipLaunchKernelGGL((k_tick<float, true>), dim3(n_wg), dim3(PFC_WG), 0, capture, d_teams, d_descs, sin, sout, pin, pout, par);
-      else
-        hipLaunchKernelGGL((k_tick<float, false>), dim3(n_wg), dim3(PFC_WG), 0, capture, d_teams, d_descs, sin, sout, pin, pout, par);
+      if (sg) { if (lds) PFC_TICK(float, true, true); else PFC_TICK(float, true, false); }
+      else { if (lds) PFC_TICK(float, false, true); else PFC_TICK(float, false, false); }
     } else {
-      if (count == 1)
-        hipLaunchKernelGGL((k_tick<double, true>), dim3(n_wg), dim3(PFC_WG), 0, capture, d_teams, d_descs, sin, sout, pin, pout, par);
-      else
-        hipLaunchKernelGGL((k_tick<double, false>), dim3(n_wg), dim3(PFC_WG), 0, capture, d_teams, d_descs, sin, sout, pin, pout, par);
+      if (sg) { if (lds) PFC_TICK(double, true, true); else PFC_TICK(double, true, false); }
+      else { if (lds) PFC_TICK(double, false, true); else PFC_TICK(double, false, false); }
     }
+#undef PFC_TICK
   }
   hipLaunchKernelGGL(k_report, dim3((count + 255) / 256), dim3(256), 0, capture, d_descs, count, d_flags);
   hipGraph_t g = nullptr;
@@ -694,12 +782,11 @@ int Group::build(hipStream_t capture, int precision, int ticks) {
 
 int Group::alloc(const std::vector<int>& team_sizes) {
   count = (int)team_sizes.size();
-  std::vector<TeamEntry> tes;
+  h_teams.clear();
   for (int i = 0; i < count; ++i)
-    for (int r = 0; r < team_sizes[i]; ++r) tes.push_back(TeamEntry{i, r, team_sizes[i], 0});
-  n_wg = (int)tes.size();
-  PFC_HIP(hipMalloc((void**)&d_teams, sizeof(TeamEntry) * tes.size()));
-  PFC_HIP(hipMemcpy(d_teams, tes.data(), sizeof(TeamEntry) * tes.size(), hipMemcpyHostToDevice));
+    for (int r = 0; r < team_sizes[i]; ++r) h_teams.push_back(TeamEntry{i, r, team_sizes[i], 0, nullptr, 0, 0});
+  n_wg = (int)h_teams.size();
+  PFC_HIP(hipMalloc((void**)&d_teams, sizeof(TeamEntry) * h_teams.size()));
   PFC_HIP(hipMalloc((void**)&d_descs, sizeof(InstDev) * count));
   PFC_HIP(hipHostMalloc((void**)&h_descs, sizeof(InstDev) * count, hipHostMallocDefault));
   PFC_HIP(hipHostMalloc((void**)&h_states, sizeof(State) * count, hipHostMallocDefault));

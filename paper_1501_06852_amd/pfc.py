@@ -65,7 +65,7 @@ class pfc_schedule(C.Structure):
 
 class pfc_server_opts(C.Structure):
     _fields_ = [("struct_size", C.c_int), ("precision", C.c_int), ("hbm_budget", C.c_size_t),
-                ("max_slots", C.c_int), ("ticks_per_graph", C.c_int)]
+                ("max_slots", C.c_int), ("ticks_per_graph", C.c_int), ("rows_per_thread", C.c_int)]
 
 
 class pfc_result(C.Structure):

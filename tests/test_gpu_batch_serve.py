@@ -70,7 +70,7 @@ def test_batch_alone_equals_mix(pfc, prec):
 
 def _serve(pfc, meshes, reqs, prec, slots, budget):
     import ctypes as C
-    so = pfc.pfc_server_opts(C.sizeof(pfc.pfc_server_opts), prec, budget, slots, 0)
+    so = pfc.pfc_server_opts(C.sizeof(pfc.pfc_server_opts), prec, budget, slots, 0, 0)
     srv = C.c_void_p()
     assert pfc._lib.pfc_server_create(C.byref(so), C.byref(srv)) == 0
     try:
@@ -127,7 +127,7 @@ def test_server_alone_equals_mix_and_admission(pfc, prec):
                 assert np.array_equal(state, alone[k]), (slots, budget, k)
         # a request that can never fit is refused at submission
         import ctypes as C
-        so = pfc.pfc_server_opts(C.sizeof(pfc.pfc_server_opts), prec, 1024, 1, 0)
+        so = pfc.pfc_server_opts(C.sizeof(pfc.pfc_server_opts), prec, 1024, 1, 0, 0)
         srv = C.c_void_p()
         assert pfc._lib.pfc_server_create(C.byref(so), C.byref(srv)) == 0
         a = np.zeros(probs[0].n)

@@ -24,8 +24,10 @@ def _stage1(P, r, tau):
     return x0, b
 
 
+# the last two cases span several workgroups with a ragged last one: 3D float64
+# runs stage the columns in LDS, 2D float64 runs read them from memory
 @pytest.mark.parametrize("dim,N,jit,tau,prec", [(2, 16, 0.2, 0.1, 0), (2, 10, 0.0, 1.0, 0), (3, 5, 0.2, 0.5, 0),
-                                                (2, 24, 0.2, 1.0, 0)])
+                                                (2, 24, 0.2, 1.0, 0), (3, 24, 0.1, 0.5, 0), (2, 72, 0.2, 1.0, 0)])
 def test_solve_replay_parity(pfc, dim, N, jit, tau, prec):
     P = Problem(dim, N, jit, seed=7)
     inst = None
@@ -79,7 +81,7 @@ def test_single_reduction_pcg_replay_parity(pfc, dim, N, jit, tau):
 
 
 @pytest.mark.parametrize("dim,N,jit,tau,prec", [(2, 16, 0.2, 0.1, 0), (2, 16, 0.2, 1.0, 1), (3, 5, 0.2, 0.5, 0),
-                                                (3, 6, 0.0, 0.5, 1)])
+                                                (3, 6, 0.0, 0.5, 1), (2, 72, 0.2, 1.0, 1)])
 def test_solve_tolerance_mode(pfc, dim, N, jit, tau, prec):
     """True residual <= 1e-8 checked with the oracle's operator; error against a tight oracle solve stated."""
     P = Problem(dim, N, jit, seed=8)
