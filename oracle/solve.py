@@ -10,6 +10,11 @@ judged on the true relative residual of the system as given,
 ||b - A^R y||_2 / ||b||_2; the Givens estimate of the scaled system is
 compared with tol*||b||/max(1, m11), which bounds the unscaled residual.
 
+PFC1 (Kp, Fm given, oracle.mobility): the operator is the PFC1 stage matrix
+and P_CH is built for the time step m0 * tau_s (constant-mobility
+approximation K_+ ~ M0 K of Section 4); with Kp = K, Fm = 0, m0 = 1 this is
+the PFC2 solve.
+
 Pinned through its parts (precond, krylov, reference) and by agreement with
 dense LU and the FFT-exact solve in tests/test_oracle_solvers.py.
 """
@@ -23,21 +28,30 @@ from .precond import InnerSolvers, pch_apply
 
 
 def solve_stage(M, K, N, r, tau, m11, b, tol=1e-8, restart=30, max_steps=1000,
-                inner_mode="pcg", inner_tol=1e-3, inner_maxit=500, replay: Schedule | None = None, schur="CH"):
+                inner_mode="pcg", inner_tol=1e-3, inner_maxit=500, replay: Schedule | None = None, schur="CH",
+                Kp=None, Fm=None, m0=1.0):
     n = M.shape[0]
     tau_s = tau / m11
     b_s = b.copy()
     b_s[n:2 * n] /= m11
     nb = float(np.linalg.norm(b))
     nbs = float(np.linalg.norm(b_s))
-    inner = InnerSolvers(M, K, tau_s, mode=inner_mode, tol=inner_tol, maxit=inner_maxit,
+    inner = InnerSolvers(M, K, m0 * tau_s, mode=inner_mode, tol=inner_tol, maxit=inner_maxit,
                          replay_counts=None if replay is None else replay.inner, schur=schur)
+    if Kp is None:
+        def op(t, s, y):
+            return apply_AR(M, K, N, r, t, s, y)
+    else:
+        from .mobility import apply_AR1
+
+        def op(t, s, y):
+            return apply_AR1(M, K, N, Kp, Fm, r, t, s, y)
 
     def apply_As(y):
-        return apply_AR(M, K, N, r, tau_s, 1.0, y)
+        return op(tau_s, 1.0, y)
 
     def true_res(y):
-        return float(np.linalg.norm(b - apply_AR(M, K, N, r, tau, m11, y))) / nb
+        return float(np.linalg.norm(b - op(tau, m11, y))) / nb
 
     est_scale = (nb / nbs) / max(1.0, m11) if nbs > 0 else 1.0
     y, info = fgmres(apply_As, lambda v: pch_apply(inner, v), b_s, tol=tol, restart=restart,
