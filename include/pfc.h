@@ -61,6 +61,7 @@ extern "C" {
 enum { PFC_FP64 = 0, PFC_MIXED = 1 };
 enum { PFC_INIT_GIVEN = 0, PFC_INIT_CONSISTENT = 1 };
 enum { PFC_OP_M = 0, PFC_OP_K = 1 };
+enum { PFC_MODEL_PFC2 = 0, PFC_MODEL_PFC1 = 1 };
 
 typedef struct pfc_mesh pfc_mesh;
 typedef struct pfc_instance pfc_instance;
@@ -86,7 +87,20 @@ typedef struct pfc_server pfc_server;
  *   schur_variant 0: Schur complement approximated by S_CH (steps 3.1 and 3.2);
  *                 1: by S_D = M - 2 delta K + delta K M_D^{-1} K, M_D = diag(M)
  *                 (Section 4.1), one PCG solve on the second-ring pattern
- *   sd_iters      iteration count of the S_D solve (20, Table inner_solvers) */
+ *   sd_iters      iteration count of the S_D solve (20, Table inner_solvers)
+ *   model         PFC_MODEL_PFC2 (H^{-1} flow: K_+ = K, F = 0; the default) or
+ *                 PFC_MODEL_PFC1 (Wasserstein flow with mobility psi^+ =
+ *                 psi - psi_min, Section 2): block (1,0) of A^R becomes
+ *                 tau K_+(psi_k), block (1,1) m11 M + tau F(mu_k), with
+ *                 K_+(psi)_ij = (psi^+ grad phi_j, grad phi_i) and
+ *                 F(mu)_ij = (phi_j grad mu, grad phi_i) (eq. rosenbrock_matrix);
+ *                 the stage right-hand side carries -tau K_+(psi_i) mu_i; P_CH is
+ *                 built for the time step M0 tau_s with M0 the mean of psi^+
+ *                 (constant-mobility approximation, Section 4).  M0 is taken
+ *                 from psi_k for a single solve and once from the initial state
+ *                 for a Rosenbrock run (the scheme conserves the integral of psi).
+ *                 PFC1 needs the element geometry: meshes from pfc_mesh_create_p1.
+ *   psi_min       lower bound of the order parameter in the mobility (-1.5) */
 typedef struct pfc_opts {
     int struct_size;
     int precision;
@@ -102,6 +116,8 @@ typedef struct pfc_opts {
     int single_reduction;
     int schur_variant;
     int sd_iters;
+    int model;
+    double psi_min;
 } pfc_opts;
 
 /* Result record of one stage solve.
@@ -220,6 +236,13 @@ void pfc_instance_destroy(pfc_instance* inst);
 int pfc_solve(pfc_instance* inst, const double* psi_k, double r, double psibar, double tau,
               double m11, const double* rhs, double* x, const pfc_schedule* replay,
               pfc_solve_info* info, void* stream);
+/* The same stage solve taking the full step state x_k (device float64 [3n],
+ * [mu_k | psi_k | omega_k]): required for PFC_MODEL_PFC1 instances, whose
+ * stage matrix also holds K_+(psi_k) and F(mu_k) (eq. rosenbrock_matrix) and
+ * whose P_CH uses the mobility mean M0 of psi_k; pfc_solve returns
+ * PFC_ERR_ARG for them.  For PFC2 it equals pfc_solve with psi_k = x_k + n. */
+int pfc_solve_x(pfc_instance* inst, const double* x_k, double r, double psibar, double tau, double m11,
+                const double* rhs, double* x, const pfc_schedule* replay, pfc_solve_info* info, void* stream);
 
 /* After a pfc_solve without replay: copy the recorded inner counts of its
  * preconditioner applications (5 per application, in order) into the host
@@ -268,8 +291,12 @@ int pfc_rosenbrock_adaptive(pfc_instance* inst, double* state, double r, double 
 /* out = A^R y with N(psi_k) reassembled from psi_k; y, out [3n]. */
 int pfc_apply_AR(pfc_instance* inst, const double* psi_k, double r, double tau, double m11,
                  const double* y, double* out, void* stream);
-/* z = P_CH^{-1} v with parameter tau_s (the tau of block row 1 after division
- * by m11): the five steps (1), (2), (3.1), (3.2), (4), (5) of Section 4.2 with
+/* out = A^R y at the full state x_k [3n] (N(psi_k), and for PFC1 K_+(psi_k)
+ * and F(mu_k), reassembled); the form PFC_MODEL_PFC1 instances require. */
+int pfc_apply_AR_x(pfc_instance* inst, const double* x_k, double r, double tau, double m11,
+                   const double* y, double* out, void* stream);
+/* z = P_CH^{-1} v with parameter tau_s (the time step the preconditioner is
+ * built for: tau/m11 for PFC2, M0 tau/m11 for PFC1; used as given): the five steps (1), (2), (3.1), (3.2), (4), (5) of Section 4.2 with
  * Jacobi-PCG inner solves.  fixed_counts: NULL (tolerance inner_tol) or host
  * int[5] exact iteration counts; counts_out: host int[5] or NULL. */
 int pfc_apply_pch(pfc_instance* inst, double tau_s, const double* v, double* z,
@@ -277,7 +304,8 @@ int pfc_apply_pch(pfc_instance* inst, double tau_s, const double* v, double* z,
 /* Stage right-hand side b_i^R of stage `stage` (1..3) at step state x_k and
  * earlier stage solutions ys = [y_1 | y_2 | y_3] (device, 3 x 3n; only
  * y_1..y_{stage-1} read): b0 = F0(x_i), b1 = tau F1(x_i) + sum c_ij M y_j^psi,
- * b2 = F2(x_i), x_i = x_k + sum a_ij y_j.  b device [3n]. */
+ * b2 = F2(x_i), x_i = x_k + sum a_ij y_j, with F1(x) = -K mu (PFC2) or
+ * -K_+(psi) mu (PFC1, formed element by element at the stage state).  b device [3n]. */
 int pfc_stage_rhs(pfc_instance* inst, const double* x_k, const double* ys, int stage,
                   double r, double tau, double* b, void* stream);
 

@@ -213,6 +213,71 @@ __device__ double node_psi3(const MeshDev& m, int i, PsiF psi) {
   return acc;
 }
 
+// ---- mobility matrices of the PFC1 model (Section 3) ---------------------------
+// P1: grad lambda is constant on a simplex and int_T lambda_c = |T| / (m+1), so
+//   K_+(psi)^T_ab = (sum_c psi^+_c / (m+1)) |T| grad l_a . grad l_b
+//   F(mu)^T_ab    = (1 / (m+1)) sum_c mu_c |T| grad l_c . grad l_a   (a: test, b: trial)
+// with |T| grad l_a . grad l_b read from the element stiffness (upper triangle).
+__device__ __forceinline__ double elem_k(const MeshDev& m, int el, int a, int b) {
+  const int k = m.dim + 1;
+  if (a > b) { const int t = a; a = b; b = t; }
+  return m.elem_K[(long long)el * (k * (k + 1) / 2) + a * k - a * (a - 1) / 2 + (b - a)];
+}
+
+template <typename PsiF>
+__device__ __forceinline__ double entry_Kplus(const MeshDev& m, long long e, PsiF psi, double psi_min) {
+  double acc = 0.0;
+  const int k = m.dim + 1;
+  const double ik = 1.0 / k;
+  for (int t = m.sl_el_ptr[e]; t < m.sl_el_ptr[e + 1]; ++t) {
+    const int pk = m.sl_el[t];
+    const int el = pk >> 4, a = (pk >> 2) & 3, b = pk & 3;
+    const int* en = m.elem_nodes + (long long)el * k;
+    double s = 0.0;
+    for (int c = 0; c < k; ++c) s += psi(en[c]) - psi_min;
+    acc += s * ik * elem_k(m, el, a, b);
+  }
+  return acc;
+}
+
+template <typename MuF>
+__device__ __forceinline__ double entry_F(const MeshDev& m, long long e, MuF mu) {
+  double acc = 0.0;
+  const int k = m.dim + 1;
+  const double ik = 1.0 / k;
+  for (int t = m.sl_el_ptr[e]; t < m.sl_el_ptr[e + 1]; ++t) {
+    const int pk = m.sl_el[t];
+    const int el = pk >> 4, a = (pk >> 2) & 3;
+    const int* en = m.elem_nodes + (long long)el * k;
+    double s = 0.0;
+    for (int c = 0; c < k; ++c) s += mu(en[c]) * elem_k(m, el, c, a);
+    acc += s * ik;
+  }
+  return acc;
+}
+
+// (K_+(psi) mu)_i at node i, element by element (the stage right-hand side
+// needs it at the stage state, where no assembled K_+ exists)
+template <typename PsiF, typename MuF>
+__device__ __forceinline__ double node_Kplus_mu(const MeshDev& m, int i, PsiF psi, MuF mu, double psi_min) {
+  double acc = 0.0;
+  const int k = m.dim + 1;
+  const double ik = 1.0 / k;
+  for (int t = m.nd_el_ptr[i]; t < m.nd_el_ptr[i + 1]; ++t) {
+    const int pk = m.nd_el[t];
+    const int el = pk >> 2, a = pk & 3;
+    const int* en = m.elem_nodes + (long long)el * k;
+    double sp = 0.0, km = 0.0;
+    for (int c = 0; c < k; ++c) {
+      const int j = en[c];
+      sp += psi(j) - psi_min;
+      km += elem_k(m, el, a, c) * mu(j);
+    }
+    acc += sp * ik * km;
+  }
+  return acc;
+}
+
 // ---- phases ---------------------------------------------------------------
 // Every phase returns this thread's contribution to the two partial sums.
 
@@ -230,6 +295,10 @@ __device__ Red3 ph_rb_begin(const InstDev& I, const Team& tm) {
     for (int k = 0; k < w; ++k) {
       const long long e = (long long)base + k * 64 + lane;
       I.N[e] = -3.0 * entry_Mpsi2(I.m, e, psi);
+      if (I.model == PFC_MODEL_PFC1) {
+        I.Kp[e] = entry_Kplus(I.m, e, psi, I.psi_min);
+        I.Fm[e] = entry_F(I.m, e, [&](int j) { return xk[j]; });
+      }
     }
   }
   return red3(0.0, 0.0);
@@ -271,7 +340,15 @@ __device__ __forceinline__ void stage_rhs_row(const InstDev& I, const PatView<L>
   double g = 0.0;
   if (i < n) g = node_psi3(I.m, i, [&](int j) { return stage_comb(I, stage, 1, j); });
   b0 = -sMmu + (1.0 + I.r) * sMps - 2.0 * sKps - sKom + g;
-  b1 = I.tau * (-sKmu);
+  if (I.model == PFC_MODEL_PFC1) {  // -tau K_+(psi_i) mu_i
+    double kpm = 0.0;
+    if (i < n)
+      kpm = node_Kplus_mu(I.m, i, [&](int j) { return stage_comb(I, stage, 1, j); },
+                          [&](int j) { return stage_comb(I, stage, 0, j); }, I.psi_min);
+    b1 = I.tau * (-kpm);
+  } else {
+    b1 = I.tau * (-sKmu);
+  }
   if (stage == 2) b1 += ROS_C21 * sMy1;
   if (stage == 3) b1 += ROS_C31 * sMy1 + ROS_C32 * sMy2;
   b2 = -sMom - sKps;
@@ -430,7 +507,7 @@ __device__ Red3 ph_pcg_setup(const InstDev& I, const State& S, const Team& tm) {
       case KIND_Y1: {  // (2): b1 - tau K y0
         const T* y0 = (const T*)I.y0;
         const T ky = row_dot<T>(pv, sl, lane, Kv, [&](int j) { return y0[j]; });
-        if (i < n) rhs = Vj[n + i] - I.tau_s * (double)ky;
+        if (i < n) rhs = Vj[n + i] - I.tau_p * (double)ky;
       } break;
       case KIND_SD:   // (3) with S_D: M y1
       case KIND_Z: {  // (3.1): M y1
@@ -555,7 +632,8 @@ __device__ Red3 ph_pcg_b(const InstDev& I, const State& S, const Team& tm) {
 //   w0 = M mu + (-(1+r) M + 2K + N) psi + K omega
 //   w1 = t K mu + s M psi
 //   w2 = K psi + M omega
-template <bool L, typename YF>
+//   PFC1 (MOB): w1 = t K_+ mu + s M psi + t F psi
+template <bool L, bool MOB, typename YF>
 __device__ __forceinline__ void block_row(const InstDev& I, const PatView<L>& pv, int sl, int lane, double t, double s,
                                           YF y, double& w0, double& w1, double& w2) {
   const int base = pv.base(sl);
@@ -569,12 +647,13 @@ __device__ __forceinline__ void block_row(const InstDev& I, const PatView<L>& pv
     double mu, ps, om;
     y(j, mu, ps, om);
     w0 += Mv * mu + (c1 * Mv + 2.0 * Kv + Nv) * ps + Kv * om;
-    w1 += t * Kv * mu + s * Mv * ps;
+    if constexpr (MOB) w1 += t * I.Kp[e] * mu + s * Mv * ps + t * I.Fm[e] * ps;
+    else w1 += t * Kv * mu + s * Mv * ps;
     w2 += Kv * ps + Mv * om;
   });
 }
 
-template <typename T, bool L>
+template <typename T, bool L, bool MOB>
 __device__ Red3 ph_aspmv(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   const PatView<L> pv = p1_pat<L>(I, tm);
@@ -586,7 +665,7 @@ __device__ Red3 ph_aspmv(const InstDev& I, const State& S, const Team& tm) {
   PFC_SLICES(I, tm) {
     const int i = sl * 64 + tm.lane;
     double w0, w1, w2;
-    block_row<L>(I, pv, sl, tm.lane, I.tau_s, 1.0,
+    block_row<L, MOB>(I, pv, sl, tm.lane, I.tau_s, 1.0,
               [&](int j, double& mu, double& ps, double& om) { mu = Zj[j]; ps = Zj[n + j]; om = (double)x2[j]; },
               w0, w1, w2);
     if (i < n) {
@@ -640,7 +719,7 @@ __device__ Red3 ph_update_x(const InstDev& I, const State& S, const Team& tm, co
   return red3(0.0, 0.0);
 }
 
-template <bool L>
+template <bool L, bool MOB>
 __device__ Red3 ph_true_res(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   const PatView<L> pv = p1_pat<L>(I, tm);
@@ -653,7 +732,7 @@ __device__ Red3 ph_true_res(const InstDev& I, const State& S, const Team& tm) {
   PFC_SLICES(I, tm) {
     const int i = sl * 64 + tm.lane;
     double w0, w1, w2;
-    block_row<L>(I, pv, sl, tm.lane, I.tau, I.m11,
+    block_row<L, MOB>(I, pv, sl, tm.lane, I.tau, I.m11,
               [&](int j, double& mu, double& ps, double& om) { mu = X[j]; ps = X[n + j]; om = X[2 * n + j]; },
               w0, w1, w2);
     if (i < n) {

@@ -43,6 +43,7 @@ struct pfc_mesh {
   int* d_elem_nodes = nullptr;
   double* d_vol = nullptr;
   long long* d_csr2sell = nullptr;
+  double* d_elemK = nullptr;           // element stiffness (P1 meshes), for the PFC1 mobility
   // second-ring pattern for the S_D preconditioner (built on first use)
   int* d_w_slice_ptr = nullptr;
   int* d_w_col = nullptr;

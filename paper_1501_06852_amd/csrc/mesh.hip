@@ -95,6 +95,22 @@ __global__ void k_assemble_MK(MeshDev m, const double* __restrict__ grad, double
   K[e] = kv;
 }
 
+// Element stiffness |T| grad lambda_a . grad lambda_b, upper triangle a <= b in
+// row order (kept for the mobility matrices of the PFC1 model).
+__global__ void k_elem_stiff(int dim, int n_elem, const double* __restrict__ vol, const double* __restrict__ grad,
+                             double* __restrict__ ek) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_elem) return;
+  const int k = dim + 1, kk = k * (k + 1) / 2;
+  int q = 0;
+  for (int a = 0; a < k; ++a)
+    for (int b = a; b < k; ++b) {
+      double d = 0.0;
+      for (int c = 0; c < dim; ++c) d += grad[((long long)e * k + a) * dim + c] * grad[((long long)e * k + b) * dim + c];
+      ek[(long long)e * kk + q++] = vol[e] * d;
+    }
+}
+
 // float copies of M and K; Jacobi diagonal 1/diag(M) in both precisions
 __global__ void k_mesh_derived(MeshDev m, const double* __restrict__ M, const double* __restrict__ K, float* Mf,
                                float* Kf, double* dinvM, float* dinvMf) {
@@ -160,7 +176,7 @@ static void mesh_free(pfc_mesh* m) {
   if (!m) return;
   void* ptrs[] = {m->d_slice_ptr, m->d_col, m->d_M, m->d_K, m->d_Mf, m->d_Kf, m->d_dinvM, m->d_dinvMf,
                   m->d_sl_el_ptr, m->d_sl_el, m->d_nd_el_ptr, m->d_nd_el, m->d_elem_nodes, m->d_vol, m->d_csr2sell,
-                  m->d_w_slice_ptr, m->d_w_col, m->d_w_p1pos, m->d_w_tri_ptr, m->d_w_tri};
+                  m->d_w_slice_ptr, m->d_w_col, m->d_w_p1pos, m->d_w_tri_ptr, m->d_w_tri, m->d_elemK};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -483,6 +499,10 @@ int pfc_mesh_create_p1(int dim, int n, int n_elem, const int32_t* elem_nodes, co
   hipLaunchKernelGGL(k_elem_geom, dim3((n_elem + 255) / 256), dim3(256), 0, 0, dim, n_elem, d_X, m->d_vol, d_grad, d_bad);
   hipLaunchKernelGGL(k_assemble_MK, dim3((unsigned)((m->nnz_sell + 255) / 256)), dim3(256), 0, 0, m->dev, d_grad,
                      m->d_M, m->d_K);
+  if ((rc = upload<double>(&m->d_elemK, nullptr, (size_t)n_elem * (k * (k + 1) / 2)))) return fail(rc);
+  m->dev.elem_K = m->d_elemK;
+  hipLaunchKernelGGL(k_elem_stiff, dim3((n_elem + 255) / 256), dim3(256), 0, 0, dim, n_elem, m->d_vol, d_grad,
+                     m->d_elemK);
   hipError_t he = hipGetLastError();
   if (he == hipSuccess) he = hipDeviceSynchronize();
   if (he != hipSuccess) return fail(hip_fail(he, "P1 assembly"));

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/pfc.h"
+
 #define PFC_WG 1024
 #define PFC_WAVES 16
 #define PFC_SLICE 64
@@ -66,6 +68,7 @@ struct MeshDev {
   const int* nd_el;       // packed (elem << 2) | local index
   const int* elem_nodes;  // [n_elem*(dim+1)]
   const double* elem_vol; // [n_elem]
+  const double* elem_K;   // [n_elem * k(k+1)/2] |T| grad l_a . grad l_b for a <= b (P1 meshes; else null)
   // second-ring pattern of K M_D^{-1} K (built only for the S_D preconditioner)
   long long w_nnz_sell;
   const int* w_slice_ptr; // [n_slices+1]
@@ -115,15 +118,18 @@ struct InstDev {
   int n, precision, restart, max_steps;
   int inner_maxit, shared_ops, team_size, replay;
   int single_reduction, schur_d;
-  int sd_iters, pad_j;
+  int sd_iters, model;          // model: PFC_MODEL_PFC2 / PFC_MODEL_PFC1
   double outer_tol, inner_tol, ci_tol;
-  // job parameters
+  // job parameters; tau_p = m0 tau_s is the preconditioner's time step
   double r, tau, m11, tau_s, delta, sdelta;
+  double psi_min, m0, tau_p;
   int job, n_steps, init_mode, max_infos;
   // typed operator arrays (float or double by precision)
   void* Cd; void* Csd; void* dinvCd; void* dinvCsd;
   void* SDv; void* dinvSD;      // S_D values (second-ring layout) and Jacobi diagonal
   double* N;                    // [nnz_sell]
+  double* Kp;                   // [nnz_sell] K_+(psi_k) (PFC1)
+  double* Fm;                   // [nnz_sell] F(mu_k) (PFC1)
   // float64 vectors
   const double* b_user;         // solve job rhs
   double* x_user;               // solve job solution
@@ -135,7 +141,7 @@ struct InstDev {
   double* W;                    // [3n]
   double* pch_out;              // preconditioner-only job output
   double* xbak;                 // [3n] state before an adaptive step attempt
-  double* errpart;              // [n_slices] partial sums of the embedded error
+  double* errpart;              // [2 n_slices] per-slice partial sums (embedded error, mobility mean)
   // inner PCG vectors (sized for float64; typed by precision)
   void *r_, *pA, *pB, *q, *y0, *y1, *zt, *x1, *x2;
   void *rB, *wB, *sA, *sB;      // extra buffers of the single-reduction PCG

@@ -109,6 +109,8 @@ int start_request(pfc_server* S, Request* q) {
   std::vector<double> st((size_t)3 * n, 0.0);
   std::copy(q->psi0.begin(), q->psi0.end(), st.begin() + n);
   PFC_HIP(hipMemcpy(h.xk, st.data(), sizeof(double) * st.size(), hipMemcpyHostToDevice));
+  int rcm = set_mobility_mean(I, h.xk + n, S->stream);
+  if (rcm) return rcm;
   set_params(h, q->r, q->tau, 1.0 / ROS_GAMMA);
   h.replay = 0;
   h.job = JOB_RB;

@@ -31,6 +31,7 @@ struct Group {
 size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int team_size);
 int team_size_for(int n_slices, int rows_per_thread);
 void set_params(InstDev& h, double r, double tau, double m11);
+int set_mobility_mean(pfc_instance* I, const double* psi, hipStream_t s);
 int prep_ops_public(pfc_instance* I, hipStream_t s);
 
 }  // namespace pfc

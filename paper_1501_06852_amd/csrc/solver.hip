@@ -16,6 +16,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "device.h"
@@ -340,6 +341,33 @@ __device__ unsigned long long g_trace_cap = 0;
 #define PFC_STAMP(v)
 #endif
 
+// Inner PCG phase PH of the current solve kind, with one call site per
+// distinct instantiation: the float64 solves of the consistent initial values
+// (every precision), the S_D solve on its unstaged second-ring pattern, and the
+// main path.  (Several call sites of one instantiation make the compiler keep
+// it out of line, and the out-of-line call costs a scratch spill of the team
+// record on every launch.)
+template <typename TT, bool L, int PH>
+__device__ __forceinline__ Red3 pcg_phase_one(const InstDev& I, const State& S, const Team& tm) {
+  if constexpr (PH == PH_PCG_SETUP) return ph_pcg_setup<TT, L>(I, S, tm);
+  else if constexpr (PH == PH_PCG_A) return ph_pcg_a<TT, L>(I, S, tm);
+  else if constexpr (PH == PH_PCG_B) return ph_pcg_b<TT>(I, S, tm);
+  else if constexpr (PH == PH_CG_INIT) return ph_cg_init<TT, L>(I, S, tm);
+  else return ph_cg_iter<TT, L>(I, S, tm);
+}
+
+template <typename T, bool LDS, int PH>
+__device__ __forceinline__ Red3 pcg_phase(const InstDev& I, const State& S, const Team& tm, bool sd) {
+  constexpr bool uses_pattern = (PH != PH_PCG_SETUP && PH != PH_PCG_B);  // the operator's own SpMV
+  if constexpr (!std::is_same<T, double>::value) {
+    if (is_ci(S.kind)) return pcg_phase_one<double, LDS, PH>(I, S, tm);
+  }
+  if constexpr (LDS && uses_pattern) {
+    if (sd) return pcg_phase_one<T, false, PH>(I, S, tm);
+  }
+  return pcg_phase_one<T, LDS, PH>(I, S, tm);
+}
+
 // One solver launch.  SINGLE: the launch serves one instance and receives its
 // state and partial-sum buffers and its mesh pattern as kernel arguments
 // (preloaded into scalar registers), so the first memory round trip already
@@ -444,23 +472,21 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     case PH_RB_BEGIN: acc = ph_rb_begin<LDS>(I, tm); break;
     case PH_RB_UPDATE: acc = ph_rb_update(I, tm); break;
     // the mass solves of the consistent initial values run in float64 in every precision
-    case PH_PCG_SETUP: acc = is_ci(S.kind) ? ph_pcg_setup<double, LDS>(I, S, tm) : ph_pcg_setup<T, LDS>(I, S, tm); break;
-    case PH_PCG_A:
-      acc = is_ci(S.kind) ? ph_pcg_a<double, LDS>(I, S, tm) : sd ? ph_pcg_a<T, false>(I, S, tm) : ph_pcg_a<T, LDS>(I, S, tm);
+    case PH_PCG_SETUP: acc = pcg_phase<T, LDS, PH_PCG_SETUP>(I, S, tm, sd); break;
+    case PH_PCG_A: acc = pcg_phase<T, LDS, PH_PCG_A>(I, S, tm, sd); break;
+    case PH_PCG_B: acc = pcg_phase<T, LDS, PH_PCG_B>(I, S, tm, sd); break;
+    case PH_ASPMV:
+      acc = I.model == PFC_MODEL_PFC1 ? ph_aspmv<T, LDS, true>(I, S, tm) : ph_aspmv<T, LDS, false>(I, S, tm);
       break;
-    case PH_PCG_B: acc = is_ci(S.kind) ? ph_pcg_b<double>(I, S, tm) : ph_pcg_b<T>(I, S, tm); break;
-    case PH_ASPMV: acc = ph_aspmv<T, LDS>(I, S, tm); break;
     case PH_MGS: acc = ph_mgs(I, S, tm, false); break;
     case PH_MGS_LAST: acc = ph_mgs(I, S, tm, true); break;
     case PH_UPDATE_X: acc = ph_update_x(I, S, tm, ybuf); break;
-    case PH_TRUE_RES: acc = ph_true_res<LDS>(I, S, tm); break;
+    case PH_TRUE_RES:
+      acc = I.model == PFC_MODEL_PFC1 ? ph_true_res<LDS, true>(I, S, tm) : ph_true_res<LDS, false>(I, S, tm);
+      break;
     case PH_PCH_OUT: acc = ph_pch_out<T>(I, tm); break;
-    case PH_CG_INIT:
-      acc = is_ci(S.kind) ? ph_cg_init<double, LDS>(I, S, tm) : sd ? ph_cg_init<T, false>(I, S, tm) : ph_cg_init<T, LDS>(I, S, tm);
-      break;
-    case PH_CG_ITER:
-      acc = is_ci(S.kind) ? ph_cg_iter<double, LDS>(I, S, tm) : sd ? ph_cg_iter<T, false>(I, S, tm) : ph_cg_iter<T, LDS>(I, S, tm);
-      break;
+    case PH_CG_INIT: acc = pcg_phase<T, LDS, PH_CG_INIT>(I, S, tm, sd); break;
+    case PH_CG_ITER: acc = pcg_phase<T, LDS, PH_CG_ITER>(I, S, tm, sd); break;
     default: break;
   }
   PFC_STAMP(t_work);
@@ -582,6 +608,39 @@ __global__ void k_assemble_N_sell(InstDev I, const double* __restrict__ psi) {
   }
 }
 
+// K_+(psi) and F(mu) of the PFC1 model on the P1 pattern, in place
+__global__ void k_assemble_mob(InstDev I, const double* __restrict__ psi, const double* __restrict__ mu) {
+  const int sl = blockIdx.x * PFC_WAVES + (threadIdx.x >> 6);
+  if (sl >= I.m.n_slices) return;
+  const int lane = threadIdx.x & 63;
+  const int base = I.m.slice_ptr[sl];
+  const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
+  for (int k = 0; k < w; ++k) {
+    const long long e = (long long)base + k * 64 + lane;
+    I.Kp[e] = entry_Kplus(I.m, e, [&](int j) { return psi[j]; }, I.psi_min);
+    I.Fm[e] = entry_F(I.m, e, [&](int j) { return mu[j]; });
+  }
+}
+
+// per slice: sum of (M psi)_i and of (M 1)_i over its rows (the mobility mean
+// M0 = 1^T M psi / 1^T M 1 - psi_min is formed on the host in slice order)
+__global__ void k_mass_moments(InstDev I, const double* __restrict__ psi) {
+  const int sl = blockIdx.x * PFC_WAVES + (threadIdx.x >> 6);
+  if (sl >= I.m.n_slices) return;
+  const int lane = threadIdx.x & 63;
+  const int base = I.m.slice_ptr[sl];
+  const int w = (I.m.slice_ptr[sl + 1] - base) >> 6;
+  double a = 0.0, b = 0.0;
+  for (int k = 0; k < w; ++k) {
+    const long long e = (long long)base + k * 64 + lane;
+    a += I.m.M[e] * psi[I.m.col[e]];
+    b += I.m.M[e];
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (lane == 0) { I.errpart[sl] = a; I.errpart[I.m.n_slices + sl] = b; }
+}
+
 __global__ void k_apply_AR(InstDev I, const double* __restrict__ y, double* __restrict__ out) {
   const int sl = blockIdx.x * PFC_WAVES + (threadIdx.x >> 6);
   if (sl >= I.m.n_slices) return;
@@ -590,8 +649,9 @@ __global__ void k_apply_AR(InstDev I, const double* __restrict__ y, double* __re
   const int n = I.n;
   double w0, w1, w2;
   const PatView<false> pv{I.m.slice_ptr, I.m.col, I.m.uw, 0};
-  block_row<false>(I, pv, sl, lane, I.tau, I.m11,
-            [&](int j, double& mu, double& ps, double& om) { mu = y[j]; ps = y[n + j]; om = y[2 * n + j]; }, w0, w1, w2);
+  auto yv = [&](int j, double& mu, double& ps, double& om) { mu = y[j]; ps = y[n + j]; om = y[2 * n + j]; };
+  if (I.model == PFC_MODEL_PFC1) block_row<false, true>(I, pv, sl, lane, I.tau, I.m11, yv, w0, w1, w2);
+  else block_row<false, false>(I, pv, sl, lane, I.tau, I.m11, yv, w0, w1, w2);
   if (i < n) { out[i] = w0; out[n + i] = w1; out[2 * n + i] = w2; }
 }
 
@@ -655,6 +715,13 @@ size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int t
   h.dinvCd = take(n * w);
   h.dinvCsd = take(n * w);
   h.N = (double*)take(ns * 8);
+  if (o.model == PFC_MODEL_PFC1) {
+    h.Kp = (double*)take(ns * 8);
+    h.Fm = (double*)take(ns * 8);
+  } else {
+    h.Kp = nullptr;
+    h.Fm = nullptr;
+  }
   h.b = (double*)take(n3 * 8);
   h.xk = (double*)take(n3 * 8);
   h.ys = (double*)take(3 * n3 * 8);
@@ -665,7 +732,7 @@ size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int t
   h.y0 = take(n * 8); h.y1 = take(n * 8); h.zt = take(n * 8); h.x1 = take(n * 8); h.x2 = take(n * 8);
   h.rB = take(n * 8); h.wB = take(n * 8); h.sA = take(n * 8); h.sB = take(n * 8);
   h.xbak = (double*)take(n3 * 8);
-  h.errpart = (double*)take((size_t)m->n_slices * 8);
+  h.errpart = (double*)take((size_t)m->n_slices * 2 * 8);
   h.part = (double*)take(2 * (size_t)team_size * 4 * sizeof(double));
   h.st = (State*)take(2 * sizeof(State));
   h.hist = (Hist*)take(sizeof(Hist));
@@ -692,6 +759,8 @@ static int validate_opts(const pfc_opts* o) {
   if (o->single_reduction != 0 && o->single_reduction != 1) { set_error("pfc_opts: single_reduction must be 0 or 1"); return PFC_ERR_ARG; }
   if (o->schur_variant != 0 && o->schur_variant != 1) { set_error("pfc_opts: schur_variant must be 0 (S_CH) or 1 (S_D)"); return PFC_ERR_ARG; }
   if (o->sd_iters < 1 || o->sd_iters > 10000) { set_error("pfc_opts: sd_iters must be in 1..10000"); return PFC_ERR_ARG; }
+  if (o->model != PFC_MODEL_PFC2 && o->model != PFC_MODEL_PFC1) { set_error("pfc_opts: bad model"); return PFC_ERR_ARG; }
+  if (!std::isfinite(o->psi_min)) { set_error("pfc_opts: psi_min must be finite"); return PFC_ERR_ARG; }
   return PFC_OK;
 }
 
@@ -853,7 +922,7 @@ static int ensure_group(pfc_instance* I) {
 
 static int prep_ops(pfc_instance* I, hipStream_t s) {
   const InstDev& h = I->h;
-  if (I->ops_tau_s == h.tau_s) return PFC_OK;
+  if (I->ops_tau_s == h.tau_p) return PFC_OK;
   const int nb = slice_blocks(I->mesh->n_slices);
   if (I->opts.precision == PFC_MIXED)
     hipLaunchKernelGGL(k_prep_ops<float>, dim3(nb), dim3(PFC_WG), 0, s, h);
@@ -866,17 +935,41 @@ static int prep_ops(pfc_instance* I, hipStream_t s) {
       hipLaunchKernelGGL(k_prep_sd<double>, dim3(nb), dim3(PFC_WG), 0, s, h);
   }
   PFC_HIP(hipGetLastError());
-  I->ops_tau_s = h.tau_s;
+  I->ops_tau_s = h.tau_p;
   return PFC_OK;
 }
 
 int prep_ops_public(pfc_instance* I, hipStream_t s) { return prep_ops(I, s); }
 
+// h.m0 (mobility mean, 1 for PFC2) must be current: the preconditioner is
+// built for the time step tau_p = m0 tau / m11
 void set_params(InstDev& h, double r, double tau, double m11) {
   h.r = r; h.tau = tau; h.m11 = m11;
   h.tau_s = tau / m11;
-  h.delta = std::sqrt(h.tau_s);
+  h.tau_p = h.m0 * h.tau_s;
+  h.delta = std::sqrt(h.tau_p);
   h.sdelta = std::sqrt(h.delta);
+}
+
+// Mobility mean M0 = (1^T M psi)/(1^T M 1) - psi_min of a PFC1 instance from
+// psi (device [n]); PFC2 instances keep M0 = 1.
+int set_mobility_mean(pfc_instance* I, const double* psi, hipStream_t s) {
+  InstDev& h = I->h;
+  if (h.model != PFC_MODEL_PFC1) { h.m0 = 1.0; return PFC_OK; }
+  const int ns = I->mesh->n_slices;
+  hipLaunchKernelGGL(k_mass_moments, dim3(slice_blocks(ns)), dim3(PFC_WG), 0, s, h, psi);
+  PFC_HIP(hipGetLastError());
+  std::vector<double> part((size_t)2 * ns);
+  PFC_HIP(hipMemcpyAsync(part.data(), h.errpart, sizeof(double) * part.size(), hipMemcpyDeviceToHost, s));
+  PFC_HIP(hipStreamSynchronize(s));
+  double a = 0.0, b = 0.0;
+  for (int k = 0; k < ns; ++k) { a += part[k]; b += part[ns + k]; }
+  h.m0 = a / b - h.psi_min;
+  if (!(h.m0 > 0.0) || !std::isfinite(h.m0)) {
+    set_error("PFC1: the mean mobility of the state is not positive (psi below psi_min on average)");
+    return PFC_ERR_ARG;
+  }
+  return PFC_OK;
 }
 
 static State initial_state(int job) {
@@ -986,6 +1079,8 @@ void pfc_opts_default(pfc_opts* o) {
   o->single_reduction = 1;
   o->schur_variant = 0;
   o->sd_iters = 20;
+  o->model = PFC_MODEL_PFC2;
+  o->psi_min = -1.5;
 }
 
 double pfc_tau_critical(double r, double psibar) {
@@ -1010,6 +1105,10 @@ int pfc_instance_create(pfc_mesh* m, const pfc_opts* o, pfc_instance** out) {
   if (rc) return rc;
   *out = nullptr;
   if (o->schur_variant == 1 && (rc = build_second_ring(m))) return rc;
+  if (o->model == PFC_MODEL_PFC1 && !m->dev.elem_K) {
+    set_error("pfc_instance_create: the PFC1 model needs the element geometry of a mesh from pfc_mesh_create_p1");
+    return PFC_ERR_ARG;
+  }
   pfc_instance* I = new pfc_instance();
   I->mesh = m;
   I->opts = *o;
@@ -1038,6 +1137,9 @@ int pfc_instance_create(pfc_mesh* m, const pfc_opts* o, pfc_instance** out) {
   h.single_reduction = o->single_reduction;
   h.schur_d = o->schur_variant;
   h.sd_iters = o->sd_iters;
+  h.model = o->model;
+  h.psi_min = o->psi_min;
+  h.m0 = 1.0;
   h.team_size = I->team_size;
   h.outer_tol = o->outer_tol;
   h.inner_tol = o->inner_tol;
@@ -1061,8 +1163,10 @@ void pfc_instance_destroy(pfc_instance* I) {
   delete I;
 }
 
-int pfc_solve(pfc_instance* I, const double* psi_k, double r, double psibar, double tau, double m11,
-              const double* rhs, double* x, const pfc_schedule* replay, pfc_solve_info* info, void* stream) {
+// One stage solve at psi_k (and mu_k for the PFC1 mobility matrices).
+static int solve_impl(pfc_instance* I, const double* psi_k, const double* mu_k, double r, double psibar, double tau,
+                      double m11, const double* rhs, double* x, const pfc_schedule* replay, pfc_solve_info* info,
+                      void* stream) {
   if (!I || !psi_k || !rhs || !x || !std::isfinite(r) || !std::isfinite(psibar) || !(tau > 0.0) ||
       !std::isfinite(tau) || !(m11 > 0.0) || !std::isfinite(m11)) {
     set_error("pfc_solve: invalid arguments");
@@ -1070,6 +1174,8 @@ int pfc_solve(pfc_instance* I, const double* psi_k, double r, double psibar, dou
   }
   hipStream_t s = (hipStream_t)stream;
   InstDev& h = I->h;
+  int rc0 = set_mobility_mean(I, psi_k, s);
+  if (rc0) return rc0;
   set_params(h, r, tau, m11);
   h.b_user = rhs;
   h.x_user = x;
@@ -1083,6 +1189,8 @@ int pfc_solve(pfc_instance* I, const double* psi_k, double r, double psibar, dou
   int rc = prep_ops(I, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_assemble_N_sell, dim3(slice_blocks(I->mesh->n_slices)), dim3(PFC_WG), 0, s, h, psi_k);
+  if (h.model == PFC_MODEL_PFC1)
+    hipLaunchKernelGGL(k_assemble_mob, dim3(slice_blocks(I->mesh->n_slices)), dim3(PFC_WG), 0, s, h, psi_k, mu_k);
   PFC_HIP(hipGetLastError());
   rc = run_single(I, s, JOB_SOLVE);
   h.replay = 0;
@@ -1094,6 +1202,21 @@ int pfc_solve(pfc_instance* I, const double* psi_k, double r, double psibar, dou
   int st = f.status;
   if (st == PFC_OK && tau >= pfc_tau_critical(r, psibar)) st = PFC_WARN_TAU_CRITICAL;
   return st;
+}
+
+int pfc_solve(pfc_instance* I, const double* psi_k, double r, double psibar, double tau, double m11,
+              const double* rhs, double* x, const pfc_schedule* replay, pfc_solve_info* info, void* stream) {
+  if (I && I->h.model == PFC_MODEL_PFC1) {
+    set_error("pfc_solve: a PFC1 instance needs mu_k as well; use pfc_solve_x");
+    return PFC_ERR_ARG;
+  }
+  return solve_impl(I, psi_k, nullptr, r, psibar, tau, m11, rhs, x, replay, info, stream);
+}
+
+int pfc_solve_x(pfc_instance* I, const double* x_k, double r, double psibar, double tau, double m11, const double* rhs,
+                double* x, const pfc_schedule* replay, pfc_solve_info* info, void* stream) {
+  if (!I || !x_k) { set_error("pfc_solve_x: invalid arguments"); return PFC_ERR_ARG; }
+  return solve_impl(I, x_k + I->mesh->n, x_k, r, psibar, tau, m11, rhs, x, replay, info, stream);
 }
 
 int pfc_instance_launch_stats(const pfc_instance* I, long long* launches, long long* graphs) {
@@ -1121,11 +1244,13 @@ int pfc_rosenbrock_run(pfc_instance* I, double* state, double r, double psibar, 
   }
   hipStream_t s = (hipStream_t)stream;
   InstDev& h = I->h;
+  // PFC1: the mobility mean of the initial state (conserved by the scheme)
+  int rc = set_mobility_mean(I, state + I->mesh->n, s);
+  if (rc) return rc;
   set_params(h, r, tau, 1.0 / ROS_GAMMA);
   double* own_xk = h.xk;
   h.xk = state;
   h.replay = 0;
-  int rc = PFC_OK;
   if (replays) rc = upload_schedules(I, replays, 3 * n_steps, s);
   if (!rc) rc = prep_ops(I, s);
   if (!rc) {
@@ -1169,9 +1294,9 @@ int pfc_rosenbrock_adaptive(pfc_instance* I, double* state, double r, double psi
   h.replay = 0;
   *n_accepted = 0;
   *n_rejected = 0;
-  int rc = PFC_OK, worst = PFC_OK;
+  int rc = set_mobility_mean(I, state + n, s), worst = PFC_OK;
   std::vector<double> part(ns);
-  if (init == PFC_INIT_CONSISTENT) {
+  if (!rc && init == PFC_INIT_CONSISTENT) {
     set_params(h, r, tau0, 1.0 / ROS_GAMMA);
     h.n_steps = 0;
     h.init_mode = PFC_INIT_CONSISTENT;
@@ -1219,8 +1344,8 @@ int pfc_rosenbrock_adaptive(pfc_instance* I, double* state, double r, double psi
   return worst;
 }
 
-int pfc_apply_AR(pfc_instance* I, const double* psi_k, double r, double tau, double m11, const double* y, double* out,
-                 void* stream) {
+static int apply_AR_impl(pfc_instance* I, const double* psi_k, const double* mu_k, double r, double tau, double m11,
+                         const double* y, double* out, void* stream) {
   if (!I || !psi_k || !y || !out || !std::isfinite(r) || !std::isfinite(tau) || !std::isfinite(m11)) {
     set_error("pfc_apply_AR: invalid arguments");
     return PFC_ERR_ARG;
@@ -1230,10 +1355,26 @@ int pfc_apply_AR(pfc_instance* I, const double* psi_k, double r, double tau, dou
   h.r = r; h.tau = tau; h.m11 = m11;
   const int nb = slice_blocks(I->mesh->n_slices);
   hipLaunchKernelGGL(k_assemble_N_sell, dim3(nb), dim3(PFC_WG), 0, s, h, psi_k);
+  if (h.model == PFC_MODEL_PFC1) hipLaunchKernelGGL(k_assemble_mob, dim3(nb), dim3(PFC_WG), 0, s, h, psi_k, mu_k);
   hipLaunchKernelGGL(k_apply_AR, dim3(nb), dim3(PFC_WG), 0, s, h, y, out);
   PFC_HIP(hipGetLastError());
   PFC_HIP(hipStreamSynchronize(s));
   return PFC_OK;
+}
+
+int pfc_apply_AR(pfc_instance* I, const double* psi_k, double r, double tau, double m11, const double* y, double* out,
+                 void* stream) {
+  if (I && I->h.model == PFC_MODEL_PFC1) {
+    set_error("pfc_apply_AR: a PFC1 instance needs mu_k as well; use pfc_apply_AR_x");
+    return PFC_ERR_ARG;
+  }
+  return apply_AR_impl(I, psi_k, nullptr, r, tau, m11, y, out, stream);
+}
+
+int pfc_apply_AR_x(pfc_instance* I, const double* x_k, double r, double tau, double m11, const double* y, double* out,
+                   void* stream) {
+  if (!I || !x_k) { set_error("pfc_apply_AR_x: invalid arguments"); return PFC_ERR_ARG; }
+  return apply_AR_impl(I, x_k + I->mesh->n, x_k, r, tau, m11, y, out, stream);
 }
 
 int pfc_apply_pch(pfc_instance* I, double tau_s, const double* v, double* z, const int* fixed_counts, int* counts_out,
@@ -1244,6 +1385,7 @@ int pfc_apply_pch(pfc_instance* I, double tau_s, const double* v, double* z, con
   }
   hipStream_t s = (hipStream_t)stream;
   InstDev& h = I->h;
+  h.m0 = 1.0;  // tau_s is the preconditioner's own time step
   set_params(h, 0.0, tau_s, 1.0);
   h.pch_out = z;
   h.replay = 0;
@@ -1303,6 +1445,8 @@ int pfc_batch_run(pfc_instance* const* insts, int count, double* const* states, 
   std::vector<State*> sts(count);
   for (int i = 0; i < count; ++i) {
     InstDev& h = insts[i]->h;
+    int rcm = set_mobility_mean(insts[i], states[i] + insts[i]->mesh->n, s);
+    if (rcm) return rcm;
     set_params(h, r[i], tau[i], 1.0 / ROS_GAMMA);
     h.replay = 0;
     ts[i] = insts[i]->team_size;

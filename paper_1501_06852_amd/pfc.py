@@ -37,6 +37,8 @@ PFC_INIT_GIVEN = 0
 PFC_INIT_CONSISTENT = 1
 PFC_OP_M = 0
 PFC_OP_K = 1
+PFC_MODEL_PFC2 = 0
+PFC_MODEL_PFC1 = 1
 
 
 class pfc_opts(C.Structure):
@@ -44,7 +46,7 @@ class pfc_opts(C.Structure):
                 ("outer_tol", C.c_double), ("inner_tol", C.c_double), ("inner_maxit", C.c_int),
                 ("shared_ops", C.c_int), ("rows_per_thread", C.c_int), ("max_run_steps", C.c_int),
                 ("ticks_per_graph", C.c_int), ("single_reduction", C.c_int),
-                ("schur_variant", C.c_int), ("sd_iters", C.c_int)]
+                ("schur_variant", C.c_int), ("sd_iters", C.c_int), ("model", C.c_int), ("psi_min", C.c_double)]
 
 
 class pfc_solve_info(C.Structure):
@@ -105,6 +107,8 @@ _sig("pfc_instance_create", C.c_int, [_vp, C.POINTER(pfc_opts), C.POINTER(_vp)])
 _sig("pfc_instance_destroy", None, [_vp])
 _sig("pfc_solve", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, _vp, _vp,
                             C.POINTER(pfc_schedule), C.POINTER(pfc_solve_info), _vp])
+_sig("pfc_solve_x", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, _vp, _vp,
+                              C.POINTER(pfc_schedule), C.POINTER(pfc_solve_info), _vp])
 _sig("pfc_last_inner_counts", C.c_int, [_vp, _ip, C.c_int, _ip])
 _sig("pfc_instance_launch_stats", C.c_int, [_vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)])
 _sig("pfc_rosenbrock_run", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
@@ -112,6 +116,7 @@ _sig("pfc_rosenbrock_run", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_doubl
 _sig("pfc_rosenbrock_adaptive", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                           C.c_double, C.c_int, C.c_int, _dp, _ip, _ip, _vp])
 _sig("pfc_apply_AR", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, _vp, _vp, _vp])
+_sig("pfc_apply_AR_x", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, _vp, _vp, _vp])
 _sig("pfc_apply_pch", C.c_int, [_vp, C.c_double, _vp, _vp, _ip, _ip, _vp])
 _sig("pfc_stage_rhs", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.c_double, _vp, _vp])
 _sig("pfc_batch_run", C.c_int, [C.POINTER(_vp), C.c_int, C.POINTER(_vp), _dp, _dp, _dp, C.c_int, C.c_int,
@@ -129,7 +134,8 @@ DECLARED = [
     "pfc_status_str", "pfc_last_error", "pfc_opts_default", "pfc_tau_critical", "pfc_mesh_create_p1",
     "pfc_mesh_create_csr", "pfc_mesh_query", "pfc_mesh_export_csr", "pfc_mesh_destroy", "pfc_spmv",
     "pfc_assemble_N", "pfc_load_psi3", "pfc_instance_footprint", "pfc_instance_create", "pfc_instance_destroy",
-    "pfc_solve", "pfc_last_inner_counts", "pfc_instance_launch_stats", "pfc_rosenbrock_run", "pfc_rosenbrock_adaptive", "pfc_apply_AR", "pfc_apply_pch", "pfc_stage_rhs",
+    "pfc_solve", "pfc_solve_x", "pfc_last_inner_counts", "pfc_instance_launch_stats", "pfc_rosenbrock_run",
+    "pfc_rosenbrock_adaptive", "pfc_apply_AR", "pfc_apply_AR_x", "pfc_apply_pch", "pfc_stage_rhs",
     "pfc_batch_run", "pfc_server_create", "pfc_server_submit", "pfc_server_poll", "pfc_result_free",
     "pfc_server_drain", "pfc_server_clock", "pfc_server_destroy",
 ]
@@ -296,6 +302,21 @@ def pfc_solve(inst, n, psi_k, r, psibar, tau, m11, rhs, x, replay=None, stream=N
     return st, info.as_dict()
 
 
+def pfc_solve_x(inst, n, x_k, r, psibar, tau, m11, rhs, x, replay=None, stream=None):
+    """pfc_solve at the full state x_k [3n] (required for PFC1 instances).  Returns (status, info dict)."""
+    info = pfc_solve_info()
+    keep = None
+    rp = None
+    if replay is not None:
+        q, keep = _sched(replay)
+        rp = C.byref(q)
+    st = _lib.pfc_solve_x(inst, _dev(x_k, 3 * n, "x_k"), r, psibar, tau, m11, _dev(rhs, 3 * n, "rhs"),
+                          _dev(x, 3 * n, "x"), rp, C.byref(info), _stream(stream))
+    _check(st, "pfc_solve_x")
+    del keep
+    return st, info.as_dict()
+
+
 def pfc_last_inner_counts(inst, cap=1000):
     buf = np.zeros((cap, 5), np.int32)
     na = C.c_int()
@@ -344,6 +365,11 @@ def pfc_rosenbrock_adaptive(inst, n, state, r, psibar, tau0, t_end, rtol, atol, 
 def pfc_apply_AR(inst, n, psi_k, r, tau, m11, y, out, stream=None):
     return _check(_lib.pfc_apply_AR(inst, _dev(psi_k, n, "psi_k"), r, tau, m11, _dev(y, 3 * n, "y"),
                                     _dev(out, 3 * n, "out"), _stream(stream)), "pfc_apply_AR")
+
+
+def pfc_apply_AR_x(inst, n, x_k, r, tau, m11, y, out, stream=None):
+    return _check(_lib.pfc_apply_AR_x(inst, _dev(x_k, 3 * n, "x_k"), r, tau, m11, _dev(y, 3 * n, "y"),
+                                      _dev(out, 3 * n, "out"), _stream(stream)), "pfc_apply_AR_x")
 
 
 def pfc_apply_pch(inst, n, tau_s, v, z, fixed_counts=None, stream=None):

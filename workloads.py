@@ -31,6 +31,7 @@ _TAG_JITTER = 1
 _TAG_PSI = 2
 _TAG_PARAMS = 3
 _TAG_ARRIVALS = 4
+_TAG_SMOOTH = 5
 
 
 @dataclass
@@ -159,6 +160,36 @@ def make_mesh(dim: int, N: int, h: float = H_DEFAULT, jitter: float = 0.0, seed:
 def psi0(n: int, psibar: float, amplitude: float = 0.01, seed: int = 0) -> np.ndarray:
     """Noisy constant initial density: psi_0 = psibar + U[-A, A] per node (not re-centred)."""
     return psibar + _rng(seed, _TAG_PSI).uniform(-amplitude, amplitude, size=n)
+
+
+def node_coords(mesh: Mesh) -> np.ndarray:
+    """Coordinates of every node in [0, L)^dim (from the unwrapped element vertices)."""
+    out = np.zeros((mesh.n, mesh.dim))
+    flat_nodes = mesh.elem_nodes.reshape(-1)
+    flat_xy = mesh.elem_coords.reshape(-1, mesh.dim)
+    first = np.unique(flat_nodes, return_index=True)[1]
+    out[flat_nodes[first]] = flat_xy[first]
+    return np.mod(out, mesh.L)
+
+
+def psi_smooth(mesh: Mesh, psibar: float, amplitude: float = 0.2, kmax: int = 2, seed: int = 0) -> np.ndarray:
+    """psibar plus a band-limited periodic perturbation.
+
+    Random-phase cosines of the integer wave vectors m with max |m_i| <= kmax
+    (wavelengths >= L/kmax), seeded, scaled so that the largest deviation from
+    psibar is `amplitude`.  A smooth state with moderate gradients, for the
+    terms that grow with the gradient of mu (the PFC1 mobility derivative).
+    """
+    x = node_coords(mesh)
+    rng = _rng(seed, _TAG_SMOOTH)
+    f = np.zeros(mesh.n)
+    for m in itertools.product(range(-kmax, kmax + 1), repeat=mesh.dim):
+        if not any(m):
+            continue
+        phase = rng.uniform(0.0, 2.0 * math.pi)
+        weight = rng.uniform(0.5, 1.0)
+        f += weight * np.cos(2.0 * math.pi * (x @ np.asarray(m, dtype=np.float64)) / mesh.L + phase)
+    return psibar + amplitude * f / np.abs(f).max()
 
 
 @dataclass
