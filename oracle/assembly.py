@@ -6,7 +6,7 @@ Definitions (Section 3, after the block system A):
     Mpsi2_ij   = (psi_h^2 phi_j, phi_i)         psi^2-weighted mass matrix
     N(psi)     = ((-3 psi^2 phi_j, phi_i))_ij  = -3 Mpsi2
     g(psi)_i   = (psi_h^3, phi_i)               cubic load of the operator F
-with psi_h = sum_i psi_i phi_i the P1 interpolant.  All element integrals are
+with psi_h = sum_i psi_i phi_i the P1 interpolant (P2 meshes: `oracle.p2`).  All element integrals are
 exact (the integrands are polynomials on each simplex) and are taken through
 the barycentric monomial formula in `oracle.simplex`, looping over local
 index tuples.  Global matrices are summed element by element (COO -> CSR).
@@ -48,7 +48,10 @@ def _assemble_vec(elem_nodes: np.ndarray, elem_vals: np.ndarray, n: int) -> np.n
 
 
 def mass_stiffness(mesh):
-    """Global P1 mass and stiffness matrices (CSR, float64)."""
+    """Global mass and stiffness matrices (CSR, float64); P2 meshes go to `oracle.p2`."""
+    if getattr(mesh, "degree", 1) == 2:
+        from .p2 import mass_stiffness_p2
+        return mass_stiffness_p2(mesh)
     m = mesh.dim
     vol, grad = simplex_geometry(mesh.elem_coords)
     I2 = product_table(m, 2)  # int lambda_i lambda_j / |T|
@@ -63,6 +66,9 @@ def element_volumes(mesh) -> np.ndarray:
 
 def mass_psi2(mesh, psi: np.ndarray) -> sp.csr_matrix:
     """Mpsi2_ij = int psi_h^2 phi_i phi_j, by summing psi_a psi_b int lambda_a lambda_b lambda_i lambda_j."""
+    if getattr(mesh, "degree", 1) == 2:
+        from .p2 import mass_psi2_p2
+        return mass_psi2_p2(mesh, psi)
     m = mesh.dim
     vol = element_volumes(mesh)
     I4 = product_table(m, 4)
@@ -78,6 +84,9 @@ def N_matrix(mesh, psi: np.ndarray) -> sp.csr_matrix:
 
 def load_psi3(mesh, psi: np.ndarray) -> np.ndarray:
     """g(psi)_i = int psi_h^3 phi_i, by summing psi_a psi_b psi_c int lambda_a lambda_b lambda_c lambda_i."""
+    if getattr(mesh, "degree", 1) == 2:
+        from .p2 import load_psi3_p2
+        return load_psi3_p2(mesh, psi)
     m = mesh.dim
     vol = element_volumes(mesh)
     I4 = product_table(m, 4)

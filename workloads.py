@@ -45,6 +45,9 @@ class Mesh:
                  that each simplex is a proper simplex even where it crosses
                  the periodic boundary
     N            cells per direction, h the cell size, L = N*h the period
+    degree       1: P1, elem_nodes holds the dim+1 vertices; 2: P2,
+                 elem_nodes holds the dim+1 vertices and then one node per
+                 edge, edges in the order of P2_EDGES[dim] (local vertex pairs)
     """
 
     dim: int
@@ -53,6 +56,7 @@ class Mesh:
     elem_coords: np.ndarray
     N: int
     h: float
+    degree: int = 1
 
     @property
     def n_elem(self) -> int:
@@ -149,6 +153,31 @@ def periodic_mesh_3d(N: int, h: float = H_DEFAULT, jitter: float = 0.0, seed: in
     return Mesh(3, n, nodes, coords, N, h)
 
 
+# Local edges of a simplex in the node order of a P2 element (pairs of local vertices).
+P2_EDGES = {2: ((0, 1), (1, 2), (0, 2)),
+            3: ((0, 1), (1, 2), (0, 2), (0, 3), (1, 3), (2, 3))}
+
+
+def p2_mesh(mesh: Mesh) -> Mesh:
+    """The P2 version of a periodic P1 mesh: one extra node per edge.
+
+    Vertex nodes keep their indices 0..n-1; edge nodes follow, numbered in the
+    lexicographic order of their (smaller, larger) vertex index pair.  Needs
+    N >= 3, so that distinct edges join distinct vertex pairs.
+    """
+    if mesh.N < 3:
+        raise ValueError("P2 meshes need N >= 3")
+    ev = mesh.elem_nodes.astype(np.int64)
+    pairs = np.stack([np.stack([ev[:, i], ev[:, j]], axis=1) for i, j in P2_EDGES[mesh.dim]], axis=1)  # [E, ne, 2]
+    lo = pairs.min(axis=2)
+    hi = pairs.max(axis=2)
+    key = lo * mesh.n + hi
+    uniq, inv = np.unique(key.reshape(-1), return_inverse=True)
+    edge_nodes = (mesh.n + inv).reshape(key.shape)
+    nodes = np.concatenate([ev, edge_nodes], axis=1).astype(np.int32)
+    return Mesh(mesh.dim, mesh.n + len(uniq), nodes, mesh.elem_coords, mesh.N, mesh.h, degree=2)
+
+
 def make_mesh(dim: int, N: int, h: float = H_DEFAULT, jitter: float = 0.0, seed: int = 0) -> Mesh:
     if dim == 2:
         return periodic_mesh_2d(N, h, jitter, seed)
@@ -165,8 +194,12 @@ def psi0(n: int, psibar: float, amplitude: float = 0.01, seed: int = 0) -> np.nd
 def node_coords(mesh: Mesh) -> np.ndarray:
     """Coordinates of every node in [0, L)^dim (from the unwrapped element vertices)."""
     out = np.zeros((mesh.n, mesh.dim))
+    xy = mesh.elem_coords
+    if mesh.degree == 2:  # edge nodes sit at the edge midpoints
+        mids = [0.5 * (xy[:, i] + xy[:, j]) for i, j in P2_EDGES[mesh.dim]]
+        xy = np.concatenate([xy, np.stack(mids, axis=1)], axis=1)
     flat_nodes = mesh.elem_nodes.reshape(-1)
-    flat_xy = mesh.elem_coords.reshape(-1, mesh.dim)
+    flat_xy = xy.reshape(-1, mesh.dim)
     first = np.unique(flat_nodes, return_index=True)[1]
     out[flat_nodes[first]] = flat_xy[first]
     return np.mod(out, mesh.L)
