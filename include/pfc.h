@@ -179,6 +179,22 @@ double pfc_tau_critical(double r, double psibar);
 int pfc_mesh_create_p1(int dim, int n, int n_elem, const int32_t* elem_nodes,
                        const double* elem_coords, pfc_mesh** out);
 
+/* pfc_mesh_create_p2: quadratic Lagrange elements (Section 3 with p = 2, the
+ * degree of Tables 3-5).  The local basis on a simplex with barycentric
+ * coordinates l_0..l_dim is l_a (2 l_a - 1) at the vertices and 4 l_i l_j at
+ * the edges; M, K, N(psi) and the cubic load are integrated exactly.
+ *   elem_nodes   host int32 [n_elem * q], q = 6 (2D) or 10 (3D): the dim+1
+ *                vertex nodes, then the edge nodes of the local vertex pairs
+ *                (0,1), (1,2), (0,2) in 2D and (0,1), (1,2), (0,2), (0,3),
+ *                (1,3), (2,3) in 3D
+ *   elem_coords  host float64 [n_elem * (dim+1) * dim], vertex coordinates
+ *                (straight-sided simplices)
+ *   n_elem       at most 2^22
+ * Other arguments and errors as pfc_mesh_create_p1.  The PFC1 model needs a P1
+ * mesh. */
+int pfc_mesh_create_p2(int dim, int n, int n_elem, const int32_t* elem_nodes,
+                       const double* elem_coords, pfc_mesh** out);
+
 /* pfc_mesh_create_csr: take M and K from the caller in CSR form (host arrays).
  *   row_ptr [n+1], col_idx [nnz]: sorted column indices per row, diagonal
  *   present, pattern structurally symmetric and containing every node pair

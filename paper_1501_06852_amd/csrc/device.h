@@ -175,8 +175,66 @@ __device__ __forceinline__ void elem_psi(const MeshDev& m, int el, PsiF psi, dou
   for (int a = 0; a < k; ++a) p[a] = psi(en[a]);
 }
 
+// P2 (Section 3, p = 2; integrands of degree 8, exact through the reference
+// table C4[a][b][c][d] = int phi_a phi_b phi_c phi_d / |T|):
+//   Mpsi2^T_ab             = |T| sum_{c,d} psi_c psi_d C4[a][b][c][d]
+//   int_T psi_h^3 phi_a    = |T| sum_b psi_b sum_{c,d} psi_c psi_d C4[a][b][c][d]
+template <int Q, typename PsiF>
+__device__ __forceinline__ double entry_Mpsi2_p2(const MeshDev& m, long long e, PsiF psi) {
+  double acc = 0.0;
+  for (int t = m.sl_el_ptr[e]; t < m.sl_el_ptr[e + 1]; ++t) {
+    const int pk = m.sl_el[t];
+    const int el = pk >> 8, a = (pk >> 4) & 15, b = pk & 15;
+    const int* en = m.elem_nodes + (long long)el * Q;
+    double p[Q];
+#pragma unroll
+    for (int c = 0; c < Q; ++c) p[c] = psi(en[c]);
+    const double* C = m.p2_C4 + (a * Q + b) * Q * Q;
+    double s = 0.0;
+#pragma unroll 1
+    for (int c = 0; c < Q; ++c) {  // one row of the table at a time keeps the register use low
+      double r = 0.0;
+#pragma unroll
+      for (int d = 0; d < Q; ++d) r += C[c * Q + d] * p[d];
+      s += p[c] * r;
+    }
+    acc += m.elem_vol[el] * s;
+  }
+  return acc;
+}
+
+template <int Q, typename PsiF>
+__device__ __forceinline__ double node_psi3_p2(const MeshDev& m, int i, PsiF psi) {
+  double acc = 0.0;
+  for (int t = m.nd_el_ptr[i]; t < m.nd_el_ptr[i + 1]; ++t) {
+    const int pk = m.nd_el[t];
+    const int el = pk >> 4, a = pk & 15;
+    const int* en = m.elem_nodes + (long long)el * Q;
+    double p[Q];
+#pragma unroll
+    for (int c = 0; c < Q; ++c) p[c] = psi(en[c]);
+    double s = 0.0;
+#pragma unroll 1
+    for (int b = 0; b < Q; ++b) {
+      const double* C = m.p2_C4 + (a * Q + b) * Q * Q;
+      double r2 = 0.0;
+#pragma unroll 1
+      for (int c = 0; c < Q; ++c) {
+        double r = 0.0;
+#pragma unroll
+        for (int d = 0; d < Q; ++d) r += C[c * Q + d] * p[d];
+        r2 += p[c] * r;
+      }
+      s += psi(en[b]) * r2;
+    }
+    acc += m.elem_vol[el] * s;
+  }
+  return acc;
+}
+
 template <typename PsiF>
-__device__ double entry_Mpsi2(const MeshDev& m, long long e, PsiF psi) {
+__device__ __forceinline__ double entry_Mpsi2(const MeshDev& m, long long e, PsiF psi) {
+  if (m.degree == 2) return m.dim == 2 ? entry_Mpsi2_p2<6>(m, e, psi) : entry_Mpsi2_p2<10>(m, e, psi);
   double acc = 0.0;
   const double cm = cm_of(m.dim);
   const int t0 = m.sl_el_ptr[e], t1 = m.sl_el_ptr[e + 1];
@@ -195,7 +253,8 @@ __device__ double entry_Mpsi2(const MeshDev& m, long long e, PsiF psi) {
 }
 
 template <typename PsiF>
-__device__ double node_psi3(const MeshDev& m, int i, PsiF psi) {
+__device__ __forceinline__ double node_psi3(const MeshDev& m, int i, PsiF psi) {
+  if (m.degree == 2) return m.dim == 2 ? node_psi3_p2<6>(m, i, psi) : node_psi3_p2<10>(m, i, psi);
   double acc = 0.0;
   const double cm = cm_of(m.dim);
   const int t0 = m.nd_el_ptr[i], t1 = m.nd_el_ptr[i + 1];

@@ -24,6 +24,8 @@ int hip_fail(hipError_t e, const char* what);
 struct pfc_mesh {
   int dim = 0, n = 0, nnz = 0, n_elem = 0, n_slices = 0;
   int uniform_width = 0;               // common slice width (1..16), 0 if slices differ
+  int degree = 1, nloc = 0;            // Lagrange degree and nodes per element
+  double* d_p2tab = nullptr;           // P2 reference tables (M2, D, C4)
   long long nnz_sell = 0;
   std::vector<int> row_ptr, col_idx;   // CSR pattern (host)
   std::vector<long long> csr2sell;     // CSR slot -> SELL position

@@ -2,6 +2,7 @@
 // P1 mass and stiffness matrices, element lists for the in-place reassembly
 // of N(psi) and the cubic load, and the mesh-level operators of the C ABI.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -95,6 +96,33 @@ __global__ void k_assemble_MK(MeshDev m, const double* __restrict__ grad, double
   K[e] = kv;
 }
 
+// P2: M_ij = sum_T |T| M2[a][b],  K_ij = sum_T |T| sum_{s,t} (grad l_s . grad l_t) D[s][t][a][b]
+// with the reference tables of the quadratic basis (Section 3, p = 2).
+__global__ void k_assemble_MK_p2(MeshDev m, const double* __restrict__ grad, double* __restrict__ M,
+                                 double* __restrict__ K) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.nnz_sell) return;
+  const int k = m.dim + 1, q = m.nloc;
+  double mv = 0.0, kv = 0.0;
+  for (int t = m.sl_el_ptr[e]; t < m.sl_el_ptr[e + 1]; ++t) {
+    const int pk = m.sl_el[t];
+    const int el = pk >> 8, a = (pk >> 4) & 15, b = pk & 15;
+    const double v = m.elem_vol[el];
+    mv += v * m.p2_M2[a * q + b];
+    double kk = 0.0;
+    for (int s = 0; s < k; ++s)
+      for (int u = 0; u < k; ++u) {
+        double g = 0.0;
+        for (int c = 0; c < m.dim; ++c)
+          g += grad[((long long)el * k + s) * m.dim + c] * grad[((long long)el * k + u) * m.dim + c];
+        kk += g * m.p2_D[((s * k + u) * q + a) * q + b];
+      }
+    kv += v * kk;
+  }
+  M[e] = mv;
+  K[e] = kv;
+}
+
 // Element stiffness |T| grad lambda_a . grad lambda_b, upper triangle a <= b in
 // row order (kept for the mobility matrices of the PFC1 model).
 __global__ void k_elem_stiff(int dim, int n_elem, const double* __restrict__ vol, const double* __restrict__ grad,
@@ -176,14 +204,13 @@ static void mesh_free(pfc_mesh* m) {
   if (!m) return;
   void* ptrs[] = {m->d_slice_ptr, m->d_col, m->d_M, m->d_K, m->d_Mf, m->d_Kf, m->d_dinvM, m->d_dinvMf,
                   m->d_sl_el_ptr, m->d_sl_el, m->d_nd_el_ptr, m->d_nd_el, m->d_elem_nodes, m->d_vol, m->d_csr2sell,
-                  m->d_w_slice_ptr, m->d_w_col, m->d_w_p1pos, m->d_w_tri_ptr, m->d_w_tri, m->d_elemK};
+                  m->d_w_slice_ptr, m->d_w_col, m->d_w_p1pos, m->d_w_tri_ptr, m->d_w_tri, m->d_elemK, m->d_p2tab};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
 }
 
-static int check_elements(int dim, int n, int n_elem, const int32_t* en) {
-  const int k = dim + 1;
+static int check_elements(int k, int n, int n_elem, const int32_t* en) {
   for (long long e = 0; e < n_elem; ++e) {
     for (int a = 0; a < k; ++a) {
       const int v = en[e * k + a];
@@ -202,15 +229,15 @@ static int check_elements(int dim, int n, int n_elem, const int32_t* en) {
 }
 
 // node -> (element, local index) lists in element order
-static void node_elements(int dim, int n, int n_elem, const int32_t* en, std::vector<int>& ptr, std::vector<int>& lst) {
-  const int k = dim + 1;
+static void node_elements(int k, int n, int n_elem, const int32_t* en, std::vector<int>& ptr, std::vector<int>& lst) {
+  const int bits = k <= 4 ? 2 : 4;
   ptr.assign(n + 1, 0);
   for (long long t = 0; t < (long long)n_elem * k; ++t) ptr[en[t] + 1]++;
   for (int i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
   lst.resize((size_t)n_elem * k);
   std::vector<int> fill(ptr.begin(), ptr.end() - 1);
   for (int e = 0; e < n_elem; ++e)
-    for (int a = 0; a < k; ++a) lst[fill[en[(long long)e * k + a]]++] = (e << 2) | a;
+    for (int a = 0; a < k; ++a) lst[fill[en[(long long)e * k + a]]++] = (e << bits) | a;
 }
 
 static int slot_of(const pfc_mesh* m, int row, int col) {
@@ -224,7 +251,8 @@ static int slot_of(const pfc_mesh* m, int row, int col) {
 // SELL-64 layout, element lists per stored entry, uploads.  Requires the CSR
 // pattern in m->row_ptr / m->col_idx.
 static int finish_layout(pfc_mesh* m, const int32_t* en, const std::vector<int>& ndp, const std::vector<int>& ndl) {
-  const int n = m->n, k = m->dim + 1;
+  const int n = m->n, k = m->nloc;
+  const int bits = k <= 4 ? 2 : 4;
   m->n_slices = (n + 63) / 64;
   std::vector<int> sptr(m->n_slices + 1, 0);
   for (int s = 0; s < m->n_slices; ++s) {
@@ -292,7 +320,8 @@ static int finish_layout(pfc_mesh* m, const int32_t* en, const std::vector<int>&
   std::vector<int> fill(cnt.begin(), cnt.end() - 1);
   for (long long e = 0; e < m->n_elem; ++e)
     for (int a = 0; a < k; ++a)
-      for (int b = 0; b < k; ++b) lst[fill[pos_of_pair[(e * k + a) * k + b]]++] = (int)((e << 4) | (a << 2) | b);
+      for (int b = 0; b < k; ++b)
+        lst[fill[pos_of_pair[(e * k + a) * k + b]]++] = (int)((e << (2 * bits)) | (a << bits) | b);
   int rc;
   if ((rc = upload(&m->d_slice_ptr, sptr.data(), sptr.size()))) return rc;
   if ((rc = upload(&m->d_col, scol.data(), scol.size()))) return rc;
@@ -313,6 +342,7 @@ static int finish_layout(pfc_mesh* m, const int32_t* en, const std::vector<int>&
   d.uw = m->uniform_width;
   d.slice_ptr = m->d_slice_ptr; d.col = m->d_col; d.M = m->d_M; d.K = m->d_K; d.Mf = m->d_Mf; d.Kf = m->d_Kf;
   d.dinvM = m->d_dinvM; d.dinvMf = m->d_dinvMf; d.sl_el_ptr = m->d_sl_el_ptr; d.sl_el = m->d_sl_el;
+  d.degree = m->degree; d.nloc = m->nloc;
   d.nd_el_ptr = m->d_nd_el_ptr; d.nd_el = m->d_nd_el; d.elem_nodes = m->d_elem_nodes; d.elem_vol = m->d_vol;
   return PFC_OK;
 }
@@ -433,40 +463,150 @@ extern "C" {
 
 const char* pfc_last_error(void) { return g_err.c_str(); }
 
-int pfc_mesh_create_p1(int dim, int n, int n_elem, const int32_t* elem_nodes, const double* elem_coords,
-                       pfc_mesh** out) {
-  if (!out || !elem_nodes || !elem_coords || (dim != 2 && dim != 3) || n <= 0 || n_elem <= 0 ||
-      n_elem > (1 << 26)) {
-    set_error("pfc_mesh_create_p1: invalid arguments");
+}  // extern "C"
+
+namespace pfc {
+
+// ---- P2 reference tables ---------------------------------------------------------
+// The quadratic Lagrange basis on an m-simplex as polynomials in the
+// barycentric coordinates l_0..l_m: vertex a: l_a (2 l_a - 1); edge (i, j):
+// 4 l_i l_j, edges in the local order of pfc_mesh_create_p2.  Integrals of
+// products follow from int_T prod l^alpha = |T| m! prod(alpha!) / (m + |alpha|)!.
+namespace {
+using Mono = std::array<int, 4>;
+using Poly = std::vector<std::pair<Mono, double>>;
+
+const int kEdges2[3][2] = {{0, 1}, {1, 2}, {0, 2}};
+const int kEdges3[6][2] = {{0, 1}, {1, 2}, {0, 2}, {0, 3}, {1, 3}, {2, 3}};
+
+double fact(int k) { double f = 1.0; for (int i = 2; i <= k; ++i) f *= i; return f; }
+
+double integral(const Poly& p, int m) {  // int_T p / |T|
+  double s = 0.0;
+  for (const auto& t : p) {
+    int deg = 0;
+    double num = fact(m);
+    for (int i = 0; i <= m; ++i) { num *= fact(t.first[i]); deg += t.first[i]; }
+    s += t.second * num / fact(m + deg);
+  }
+  return s;
+}
+
+Poly mul(const Poly& a, const Poly& b) {
+  Poly r;
+  for (const auto& x : a)
+    for (const auto& y : b) {
+      Mono e;
+      for (int i = 0; i < 4; ++i) e[i] = x.first[i] + y.first[i];
+      bool found = false;
+      for (auto& z : r)
+        if (z.first == e) { z.second += x.second * y.second; found = true; break; }
+      if (!found) r.push_back({e, x.second * y.second});
+    }
+  return r;
+}
+
+Poly dl(const Poly& a, int i) {  // d / d l_i
+  Poly r;
+  for (const auto& x : a)
+    if (x.first[i] > 0) {
+      Mono e = x.first;
+      e[i] -= 1;
+      r.push_back({e, x.second * x.first[i]});
+    }
+  return r;
+}
+
+std::vector<Poly> p2_basis(int m) {
+  std::vector<Poly> B;
+  for (int a = 0; a <= m; ++a) {
+    Mono sq{0, 0, 0, 0}, li{0, 0, 0, 0};
+    sq[a] = 2;
+    li[a] = 1;
+    B.push_back({{sq, 2.0}, {li, -1.0}});
+  }
+  const int ne = m == 2 ? 3 : 6;
+  for (int k = 0; k < ne; ++k) {
+    const int i = m == 2 ? kEdges2[k][0] : kEdges3[k][0];
+    const int j = m == 2 ? kEdges2[k][1] : kEdges3[k][1];
+    Mono e{0, 0, 0, 0};
+    e[i] += 1;
+    e[j] += 1;
+    B.push_back({{e, 4.0}});
+  }
+  return B;
+}
+}  // namespace
+
+// M2 [q*q], D [k*k*q*q], C4 [q^4] concatenated
+static std::vector<double> p2_tables(int m) {
+  const std::vector<Poly> B = p2_basis(m);
+  const int q = (int)B.size(), k = m + 1;
+  std::vector<double> t((size_t)q * q + (size_t)k * k * q * q + (size_t)q * q * q * q, 0.0);
+  double* M2 = t.data();
+  double* D = M2 + q * q;
+  double* C4 = D + k * k * q * q;
+  std::vector<Poly> P2((size_t)q * q);
+  for (int a = 0; a < q; ++a)
+    for (int b = 0; b < q; ++b) {
+      P2[a * q + b] = mul(B[a], B[b]);
+      M2[a * q + b] = integral(P2[a * q + b], m);
+    }
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j)
+      for (int a = 0; a < q; ++a)
+        for (int b = 0; b < q; ++b) D[((i * k + j) * q + a) * q + b] = integral(mul(dl(B[a], i), dl(B[b], j)), m);
+  for (int a = 0; a < q; ++a)
+    for (int b = a; b < q; ++b)
+      for (int c = 0; c < q; ++c)
+        for (int d = c; d < q; ++d) {
+          const double v = integral(mul(P2[a * q + b], P2[c * q + d]), m);
+          C4[((a * q + b) * q + c) * q + d] = C4[((b * q + a) * q + c) * q + d] = v;
+          C4[((a * q + b) * q + d) * q + c] = C4[((b * q + a) * q + d) * q + c] = v;
+        }
+  return t;
+}
+
+// Meshes of Lagrange elements of degree 1 or 2 from element nodes and vertex
+// coordinates; M and K assembled on the GPU.
+static int create_lagrange(const char* who, int dim, int degree, int n, int n_elem, const int32_t* elem_nodes,
+                           const double* elem_coords, pfc_mesh** out) {
+  const int kv = dim + 1;                                         // vertices per element
+  const int k = degree == 1 ? kv : (dim + 1) * (dim + 2) / 2;    // nodes per element
+  const int max_elem = degree == 1 ? (1 << 26) : (1 << 22);      // element index fits the packed lists
+  if (!out || !elem_nodes || !elem_coords || (dim != 2 && dim != 3) || n <= 0 || n_elem <= 0 || n_elem > max_elem) {
+    set_error(std::string(who) + ": invalid arguments");
     return PFC_ERR_ARG;
   }
   *out = nullptr;
-  const int k = dim + 1;
-  int rc = check_elements(dim, n, n_elem, elem_nodes);
+  int rc = check_elements(k, n, n_elem, elem_nodes);
   if (rc) return rc;
-  for (long long t = 0; t < (long long)n_elem * k * dim; ++t)
+  for (long long t = 0; t < (long long)n_elem * kv * dim; ++t)
     if (!std::isfinite(elem_coords[t])) {
-      set_error("pfc_mesh_create_p1: non-finite coordinate");
+      set_error(std::string(who) + ": non-finite coordinate");
       return PFC_ERR_ARG;
     }
   pfc_mesh* m = new pfc_mesh();
   m->dim = dim; m->n = n; m->n_elem = n_elem;
+  m->degree = degree; m->nloc = k;
+  const int bits = k <= 4 ? 2 : 4;
   std::vector<int> ndp, ndl;
-  node_elements(dim, n, n_elem, elem_nodes, ndp, ndl);
-  // P1 pattern: every node pair of a common simplex (diagonal included)
+  node_elements(k, n, n_elem, elem_nodes, ndp, ndl);
+  // pattern: every node pair of a common simplex (diagonal included)
   m->row_ptr.assign(n + 1, 0);
   std::vector<int> cols;
   std::vector<int> rowbuf;
   for (int i = 0; i < n; ++i) {
     rowbuf.clear();
     for (int t = ndp[i]; t < ndp[i + 1]; ++t) {
-      const int e = ndl[t] >> 2;
+      const int e = ndl[t] >> bits;
       for (int a = 0; a < k; ++a) rowbuf.push_back(elem_nodes[(long long)e * k + a]);
     }
     if (rowbuf.empty()) rowbuf.push_back(i);
     std::sort(rowbuf.begin(), rowbuf.end());
     rowbuf.erase(std::unique(rowbuf.begin(), rowbuf.end()), rowbuf.end());
     cols.insert(cols.end(), rowbuf.begin(), rowbuf.end());
+    if (cols.size() > 2000000000ULL) { mesh_free(m); set_error(std::string(who) + ": pattern too large"); return PFC_ERR_ARG; }
     m->row_ptr[i + 1] = (int)cols.size();
   }
   m->col_idx.swap(cols);
@@ -475,10 +615,17 @@ int pfc_mesh_create_p1(int dim, int n, int n_elem, const int32_t* elem_nodes, co
   for (int i = 0; i < n; ++i)
     if (ndp[i + 1] == ndp[i]) {
       mesh_free(m);
-      set_error("pfc_mesh_create_p1: node " + std::to_string(i) + " belongs to no element");
+      set_error(std::string(who) + ": node " + std::to_string(i) + " belongs to no element");
       return PFC_ERR_ARG;
     }
   if ((rc = finish_layout(m, elem_nodes, ndp, ndl))) { mesh_free(m); return rc; }
+  if (degree == 2) {
+    const std::vector<double> tab = p2_tables(dim);
+    if ((rc = upload(&m->d_p2tab, tab.data(), tab.size()))) { mesh_free(m); return rc; }
+    m->dev.p2_M2 = m->d_p2tab;
+    m->dev.p2_D = m->d_p2tab + k * k;
+    m->dev.p2_C4 = m->dev.p2_D + kv * kv * k * k;
+  }
   // element geometry and assembly on the GPU
   double* d_X = nullptr;
   double* d_grad = nullptr;
@@ -490,26 +637,32 @@ int pfc_mesh_create_p1(int dim, int n, int n_elem, const int32_t* elem_nodes, co
     mesh_free(m);
     return code;
   };
-  if ((rc = upload(&d_X, elem_coords, (size_t)n_elem * k * dim))) return fail(rc);
-  if ((rc = upload<double>(&d_grad, nullptr, (size_t)n_elem * k * dim))) return fail(rc);
+  if ((rc = upload(&d_X, elem_coords, (size_t)n_elem * kv * dim))) return fail(rc);
+  if ((rc = upload<double>(&d_grad, nullptr, (size_t)n_elem * kv * dim))) return fail(rc);
   if ((rc = upload<double>(&m->d_vol, nullptr, n_elem))) return fail(rc);
   if ((rc = upload<int>(&d_bad, nullptr, 1))) return fail(rc);
   m->dev.elem_vol = m->d_vol;
   if (hipMemset(d_bad, 0, sizeof(int)) != hipSuccess) return fail(hip_fail(hipErrorUnknown, "hipMemset"));
   hipLaunchKernelGGL(k_elem_geom, dim3((n_elem + 255) / 256), dim3(256), 0, 0, dim, n_elem, d_X, m->d_vol, d_grad, d_bad);
-  hipLaunchKernelGGL(k_assemble_MK, dim3((unsigned)((m->nnz_sell + 255) / 256)), dim3(256), 0, 0, m->dev, d_grad,
-                     m->d_M, m->d_K);
-  if ((rc = upload<double>(&m->d_elemK, nullptr, (size_t)n_elem * (k * (k + 1) / 2)))) return fail(rc);
-  m->dev.elem_K = m->d_elemK;
-  hipLaunchKernelGGL(k_elem_stiff, dim3((n_elem + 255) / 256), dim3(256), 0, 0, dim, n_elem, m->d_vol, d_grad,
-                     m->d_elemK);
+  if (degree == 1) {
+    hipLaunchKernelGGL(k_assemble_MK, dim3((unsigned)((m->nnz_sell + 255) / 256)), dim3(256), 0, 0, m->dev, d_grad,
+                       m->d_M, m->d_K);
+    // element stiffness for the mobility matrices of the PFC1 model
+    if ((rc = upload<double>(&m->d_elemK, nullptr, (size_t)n_elem * (kv * (kv + 1) / 2)))) return fail(rc);
+    m->dev.elem_K = m->d_elemK;
+    hipLaunchKernelGGL(k_elem_stiff, dim3((n_elem + 255) / 256), dim3(256), 0, 0, dim, n_elem, m->d_vol, d_grad,
+                       m->d_elemK);
+  } else {
+    hipLaunchKernelGGL(k_assemble_MK_p2, dim3((unsigned)((m->nnz_sell + 255) / 256)), dim3(256), 0, 0, m->dev,
+                       d_grad, m->d_M, m->d_K);
+  }
   hipError_t he = hipGetLastError();
   if (he == hipSuccess) he = hipDeviceSynchronize();
-  if (he != hipSuccess) return fail(hip_fail(he, "P1 assembly"));
+  if (he != hipSuccess) return fail(hip_fail(he, "element assembly"));
   int bad = 0;
   if (hipMemcpy(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return fail(PFC_ERR_HIP);
   if (bad) {
-    set_error("pfc_mesh_create_p1: degenerate simplex");
+    set_error(std::string(who) + ": degenerate simplex");
     return fail(PFC_ERR_ARG);
   }
   (void)hipFree(d_X); d_X = nullptr;
@@ -518,6 +671,20 @@ int pfc_mesh_create_p1(int dim, int n, int n_elem, const int32_t* elem_nodes, co
   if ((rc = derive(m))) { mesh_free(m); return rc; }
   *out = m;
   return PFC_OK;
+}
+
+}  // namespace pfc
+
+extern "C" {
+
+int pfc_mesh_create_p1(int dim, int n, int n_elem, const int32_t* elem_nodes, const double* elem_coords,
+                       pfc_mesh** out) {
+  return create_lagrange("pfc_mesh_create_p1", dim, 1, n, n_elem, elem_nodes, elem_coords, out);
+}
+
+int pfc_mesh_create_p2(int dim, int n, int n_elem, const int32_t* elem_nodes, const double* elem_coords,
+                       pfc_mesh** out) {
+  return create_lagrange("pfc_mesh_create_p2", dim, 2, n, n_elem, elem_nodes, elem_coords, out);
 }
 
 int pfc_mesh_create_csr(int dim, int n, int nnz, const int32_t* row_ptr, const int32_t* col_idx, const double* M_val,
@@ -562,10 +729,11 @@ int pfc_mesh_create_csr(int dim, int n, int nnz, const int32_t* row_ptr, const i
       set_error("pfc_mesh_create_csr: element volumes must be positive");
       return PFC_ERR_ARG;
     }
-  int rc = check_elements(dim, n, n_elem, elem_nodes);
+  int rc = check_elements(dim + 1, n, n_elem, elem_nodes);
   if (rc) return rc;
   pfc_mesh* m = new pfc_mesh();
   m->dim = dim; m->n = n; m->n_elem = n_elem; m->nnz = nnz;
+  m->degree = 1; m->nloc = dim + 1;
   m->row_ptr.assign(row_ptr, row_ptr + n + 1);
   m->col_idx.assign(col_idx, col_idx + nnz);
   // structural symmetry
@@ -577,7 +745,7 @@ int pfc_mesh_create_csr(int dim, int n, int nnz, const int32_t* row_ptr, const i
         return PFC_ERR_ARG;
       }
   std::vector<int> ndp, ndl;
-  node_elements(dim, n, n_elem, elem_nodes, ndp, ndl);
+  node_elements(dim + 1, n, n_elem, elem_nodes, ndp, ndl);
   if ((rc = finish_layout(m, elem_nodes, ndp, ndl))) { mesh_free(m); return rc; }
   std::vector<double> sM((size_t)m->nnz_sell, 0.0), sK((size_t)m->nnz_sell, 0.0);
   for (int t = 0; t < nnz; ++t) {

@@ -54,6 +54,10 @@ struct MeshDev {
   int n, dim, n_slices, n_elem;
   long long nnz_sell;
   int uw, pad_uw;         // common width of all slices (structured meshes), 0 if they differ
+  int degree, nloc;       // Lagrange degree (1, 2) and nodes per element
+  const double* p2_M2;    // P2 reference tables (divided by |T|): M2[a][b],
+  const double* p2_D;     //   D[i][j][a][b] = int d_i phi_a d_j phi_b (i, j barycentric),
+  const double* p2_C4;    //   C4[a][b][c][d] = int phi_a phi_b phi_c phi_d
   const int* slice_ptr;   // [n_slices+1] entry offset of each slice (multiple of 64)
   const int* col;         // [nnz_sell]
   const double* M;        // [nnz_sell]
@@ -63,10 +67,10 @@ struct MeshDev {
   const double* dinvM;    // [n] 1/diag(M)
   const float* dinvMf;
   const int* sl_el_ptr;   // [nnz_sell+1] element contributions of each stored entry
-  const int* sl_el;       // packed (elem << 4) | (a << 2) | b
+  const int* sl_el;       // packed (elem << 4) | (a << 2) | b; P2: (elem << 8) | (a << 4) | b
   const int* nd_el_ptr;   // [n+1] simplices containing each node
-  const int* nd_el;       // packed (elem << 2) | local index
-  const int* elem_nodes;  // [n_elem*(dim+1)]
+  const int* nd_el;       // packed (elem << 2) | local index; P2: (elem << 4) | local index
+  const int* elem_nodes;  // [n_elem*nloc]
   const double* elem_vol; // [n_elem]
   const double* elem_K;   // [n_elem * k(k+1)/2] |T| grad l_a . grad l_b for a <= b (P1 meshes; else null)
   // second-ring pattern of K M_D^{-1} K (built only for the S_D preconditioner)

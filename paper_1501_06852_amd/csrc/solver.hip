@@ -1105,8 +1105,8 @@ int pfc_instance_create(pfc_mesh* m, const pfc_opts* o, pfc_instance** out) {
   if (rc) return rc;
   *out = nullptr;
   if (o->schur_variant == 1 && (rc = build_second_ring(m))) return rc;
-  if (o->model == PFC_MODEL_PFC1 && !m->dev.elem_K) {
-    set_error("pfc_instance_create: the PFC1 model needs the element geometry of a mesh from pfc_mesh_create_p1");
+  if (o->model == PFC_MODEL_PFC1 && (!m->dev.elem_K || m->degree != 1)) {
+    set_error("pfc_instance_create: the PFC1 model needs a P1 mesh with element geometry (pfc_mesh_create_p1)");
     return PFC_ERR_ARG;
   }
   pfc_instance* I = new pfc_instance();

@@ -95,6 +95,7 @@ _sig("pfc_last_error", C.c_char_p, [])
 _sig("pfc_opts_default", None, [C.POINTER(pfc_opts)])
 _sig("pfc_tau_critical", C.c_double, [C.c_double, C.c_double])
 _sig("pfc_mesh_create_p1", C.c_int, [C.c_int, C.c_int, C.c_int, _ip, _dp, C.POINTER(_vp)])
+_sig("pfc_mesh_create_p2", C.c_int, [C.c_int, C.c_int, C.c_int, _ip, _dp, C.POINTER(_vp)])
 _sig("pfc_mesh_create_csr", C.c_int, [C.c_int, C.c_int, C.c_int, _ip, _ip, _dp, _dp, C.c_int, _ip, _dp, C.POINTER(_vp)])
 _sig("pfc_mesh_query", C.c_int, [_vp, _ip, _ip, _ip, _ip])
 _sig("pfc_mesh_export_csr", C.c_int, [_vp, _ip, _ip, _dp, _dp])
@@ -131,7 +132,7 @@ _sig("pfc_server_destroy", None, [_vp])
 
 # every symbol declared in include/pfc.h
 DECLARED = [
-    "pfc_status_str", "pfc_last_error", "pfc_opts_default", "pfc_tau_critical", "pfc_mesh_create_p1",
+    "pfc_status_str", "pfc_last_error", "pfc_opts_default", "pfc_tau_critical", "pfc_mesh_create_p1", "pfc_mesh_create_p2",
     "pfc_mesh_create_csr", "pfc_mesh_query", "pfc_mesh_export_csr", "pfc_mesh_destroy", "pfc_spmv",
     "pfc_assemble_N", "pfc_load_psi3", "pfc_instance_footprint", "pfc_instance_create", "pfc_instance_destroy",
     "pfc_solve", "pfc_solve_x", "pfc_last_inner_counts", "pfc_instance_launch_stats", "pfc_rosenbrock_run",
@@ -219,6 +220,18 @@ def pfc_mesh_create_p1(dim, n, elem_nodes, elem_coords):
         raise ValueError("elem_nodes / elem_coords shapes do not match dim")
     h = _vp()
     _check(_lib.pfc_mesh_create_p1(dim, n, en.size // (dim + 1), pen, pec, C.byref(h)), "pfc_mesh_create_p1")
+    return h
+
+
+def pfc_mesh_create_p2(dim, n, elem_nodes, elem_coords):
+    """elem_nodes [n_elem, (dim+1)(dim+2)/2] (vertices, then edges), elem_coords [n_elem, dim+1, dim]."""
+    en, pen = _host_i32(elem_nodes)
+    ec, pec = _host_f64(elem_coords)
+    q = (dim + 1) * (dim + 2) // 2
+    if en.size % q or ec.size != (en.size // q) * (dim + 1) * dim:
+        raise ValueError("elem_nodes / elem_coords shapes do not match dim")
+    h = _vp()
+    _check(_lib.pfc_mesh_create_p2(dim, n, en.size // q, pen, pec, C.byref(h)), "pfc_mesh_create_p2")
     return h
 
 

@@ -8,8 +8,10 @@ from oracle import assembly
 class Problem:
     """A seeded mesh with its oracle matrices and (lazily) its GPU handles."""
 
-    def __init__(self, dim, N, jitter=0.0, psibar=-0.3, amp=0.01, seed=0, h=wl.H_DEFAULT):
+    def __init__(self, dim, N, jitter=0.0, psibar=-0.3, amp=0.01, seed=0, h=wl.H_DEFAULT, degree=1):
         self.mesh = wl.make_mesh(dim, N, h=h, jitter=jitter, seed=seed)
+        if degree == 2:
+            self.mesh = wl.p2_mesh(self.mesh)
         self.n = self.mesh.n
         self.M, self.K = assembly.mass_stiffness(self.mesh)
         self.psi = wl.psi0(self.n, psibar, amp, seed=seed)
@@ -18,7 +20,8 @@ class Problem:
     def gpu_mesh(self):
         from paper_1501_06852_amd import pfc
         if self._gpu is None:
-            self._gpu = pfc.pfc_mesh_create_p1(self.mesh.dim, self.n, self.mesh.elem_nodes, self.mesh.elem_coords)
+            create = pfc.pfc_mesh_create_p2 if self.mesh.degree == 2 else pfc.pfc_mesh_create_p1
+            self._gpu = create(self.mesh.dim, self.n, self.mesh.elem_nodes, self.mesh.elem_coords)
         return self._gpu
 
     def close(self):
