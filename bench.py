@@ -64,6 +64,17 @@ WORKLOADS = {
     "pfc2d_512_fp64": (2, 512, 0.2, -0.35, -0.3, 1.0, 0, 20),
     "pfc3d_64_mixed": (3, 64, 0.0, -0.3, -0.25, 0.5, 1, 10),
     "pfc2d_64_fp64": (2, 64, 0.0, -0.35, -0.3, 0.1, 0, 1),
+    # the variants of the method beyond the headline path, at the headline size
+    "pfc2d_256_p2_fp64": (2, 256, 0.2, -0.35, -0.3, 1.0, 0, 10),      # P2: 262,144 nodes like 512^2 P1
+    "pfc2d_512_pfc1_fp64": (2, 512, 0.2, -0.35, -0.3, 1.0, 0, 10),    # PFC1 mobility, smooth initial state
+    "pfc2d_512_sd_fp64": (2, 512, 0.2, -0.35, -0.3, 1.0, 0, 10),      # P(S_D) preconditioner
+}
+# options of the variant workloads: Lagrange degree, model, Schur approximation,
+# smooth initial state (amplitude, largest wave number per direction)
+VARIANTS = {
+    "pfc2d_256_p2_fp64": dict(degree=2),
+    "pfc2d_512_pfc1_fp64": dict(model=1, smooth=(0.2, 16)),
+    "pfc2d_512_sd_fp64": dict(schur_variant=1),
 }
 
 
@@ -275,17 +286,28 @@ def main():
     if args.workload == "served":
         return bench_served(args, torch, wl, pfc)
     dim, N, jitter, r, psibar, tau, prec, dsteps = WORKLOADS[args.workload]
+    var = VARIANTS.get(args.workload, {})
     steps = args.steps if args.steps is not None else dsteps
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     mesh = wl.make_mesh(dim, N, jitter=jitter, seed=args.seed)
+    if var.get("degree") == 2:
+        mesh = wl.p2_mesh(mesh)
+        h = pfc.pfc_mesh_create_p2(dim, mesh.n, mesh.elem_nodes, mesh.elem_coords)
+    else:
+        h = pfc.pfc_mesh_create_p1(dim, mesh.n, mesh.elem_nodes, mesh.elem_coords)
     n = mesh.n
-    h = pfc.pfc_mesh_create_p1(dim, n, mesh.elem_nodes, mesh.elem_coords)
     nnz = pfc.pfc_mesh_query(h)["nnz"]
-    z = nnz // n
-    opts = pfc.pfc_opts_default(precision=prec, max_run_steps=max(steps, args.warmup, 1))
+    z = nnz / n
+    model = var.get("model", 0)
+    schur = var.get("schur_variant", 0)
+    opts = pfc.pfc_opts_default(precision=prec, max_run_steps=max(steps, args.warmup, 1), model=model,
+                                schur_variant=schur)
     inst = pfc.pfc_instance_create(h, opts)
-    psi = wl.psi0(n, psibar, 0.01, seed=args.seed)
+    if "smooth" in var:
+        psi = wl.psi_smooth(mesh, psibar, var["smooth"][0], kmax=var["smooth"][1], seed=args.seed)
+    else:
+        psi = wl.psi0(n, psibar, 0.01, seed=args.seed)
     state = torch.zeros(3 * n, dtype=torch.float64, device=dev)
     state[n:2 * n] = torch.tensor(psi, dtype=torch.float64, device=dev)
     # warm-up: consistent initial values and `warmup` steps (not timed)
@@ -304,7 +326,17 @@ def main():
     launches, graphs = pfc.pfc_instance_launch_stats(inst)
     solves = 3 * steps
     w = 4 if prec == 1 else 8
-    alg = sum(roofline.solve_bytes(n, z, w, i) for i in infos) + steps * roofline.step_bytes(n, z, mesh.n_elem, dim)
+    z_sd = None
+    if schur:
+        # entries per row of the second-ring pattern of K M_D^-1 K (host count from the mesh pattern)
+        import scipy.sparse as sp
+        A = sp.csr_matrix((np.ones(mesh.n_elem * mesh.elem_nodes.shape[1] ** 2),
+                           (np.repeat(mesh.elem_nodes, mesh.elem_nodes.shape[1], axis=1).ravel(),
+                            np.tile(mesh.elem_nodes, (1, mesh.elem_nodes.shape[1])).ravel())), shape=(n, n))
+        A.data[:] = 1.0
+        z_sd = (A @ A).nnz / n
+    alg = sum(roofline.solve_bytes(n, z, w, i, model=model, z_sd=z_sd) for i in infos) + \
+        steps * roofline.step_bytes(n, z, mesh.n_elem, dim, nloc=mesh.elem_nodes.shape[1], model=model)
     period_s = gpu_ms * 1e-3 / max(1, launches)
     achieved = alg / max(1, launches) / period_s / 1e9
     res = [i["true_rel_res"] for i in infos]
@@ -324,7 +356,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "dim": dim, "grid": N, "nodes": n, "unknowns": 3 * n,
                    "jitter_h": jitter, "r": r, "psibar": psibar, "tau": tau, "rosenbrock_steps": steps,
-                   "stage_solves": solves, "restart": 30, "outer_tol": 1e-8, "inner_tol": 1e-3},
+                   "stage_solves": solves, "restart": 30, "outer_tol": 1e-8, "inner_tol": 1e-3,
+                   "element_degree": mesh.degree, "model": "PFC1" if model == 1 else "PFC2",
+                   "schur": "S_D" if schur else "S_CH", "initial_state": "smooth" if "smooth" in var else "noise"},
         "status": pfc.pfc_status_str(st),
         "max_true_rel_res": max(res) if res else None,
         "outer_iters_mean": float(np.mean([i["outer_iters"] for i in infos])),
@@ -347,7 +381,7 @@ def main():
         torch.cuda.synchronize()
         out["mixed_vs_fp64_rel_err_1step"] = float(torch.linalg.norm(s32 - s64) / torch.linalg.norm(s64))
         pfc.pfc_instance_destroy(inst64)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not var:
         out["cpu_baseline"] = run_cpu_baseline(dim, N, jitter, r, psibar, tau, args.seed)
     pfc.pfc_instance_destroy(inst)
     pfc.pfc_mesh_destroy(h)
