@@ -88,3 +88,24 @@ def test_product_path_does_not_import_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
+
+
+def test_p2_mesh_and_pfc1_validation_on_host(pfc):
+    h = C.c_void_p()
+    # P2: wrong dimension, node index out of range, repeated node
+    assert pfc._lib.pfc_mesh_create_p2(4, 10, 1, None, None, C.byref(h)) == pfc.PFC_ERR_ARG
+    with pytest.raises(pfc.PFCError):
+        pfc.pfc_mesh_create_p2(2, 6, np.array([[0, 1, 2, 3, 4, 9]]), np.zeros((1, 3, 2)))
+    with pytest.raises(pfc.PFCError):
+        pfc.pfc_mesh_create_p2(2, 6, np.array([[0, 1, 2, 3, 4, 4]]), np.zeros((1, 3, 2)))
+    with pytest.raises(ValueError):   # shapes: 6 nodes but coordinates of 4 vertices
+        pfc.pfc_mesh_create_p2(2, 6, np.array([[0, 1, 2, 3, 4, 5]]), np.zeros((1, 4, 2)))
+    # options: unknown model, non-finite psi_min; the full-state entry points reject null handles
+    o = pfc.pfc_opts_default(model=5)
+    assert pfc._lib.pfc_instance_footprint(C.c_void_p(1), C.byref(o)) == 0
+    o = pfc.pfc_opts_default(psi_min=float("nan"))
+    assert pfc._lib.pfc_instance_footprint(C.c_void_p(1), C.byref(o)) == 0
+    assert pfc._lib.pfc_solve_x(None, None, 0.0, 0.0, 0.1, 1.0, None, None, None, None, None) == pfc.PFC_ERR_ARG
+    assert pfc._lib.pfc_apply_AR_x(None, None, 0.0, 0.1, 1.0, None, None, None) == pfc.PFC_ERR_ARG
+    d = pfc.pfc_opts_default()
+    assert (d.model, d.psi_min) == (pfc.PFC_MODEL_PFC2, -1.5)
