@@ -261,6 +261,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="pfc2d_512_fp64", choices=sorted(WORKLOADS) + ["batched", "served", "copy_calibration"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-check", action="store_true",
+                    help="skip the untimed float64 comparison step of mixed-precision workloads (profiled runs)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--plain-sample", type=int, default=16)
@@ -371,7 +373,7 @@ def main():
                      "algorithmic_bytes": alg, "algorithmic_bytes_per_launch": alg / max(1, launches),
                      "avg_launch_period_us": period_s * 1e6, "kernel_sources_sha256": kernel_source_digest()},
     }
-    if prec == 1:
+    if prec == 1 and not args.no_precision_check:
         # error of the mixed-precision path against float64, one step from the same state (not timed)
         inst64 = pfc.pfc_instance_create(h, pfc.pfc_opts_default(precision=0))
         s32 = state.clone()

@@ -14,8 +14,10 @@
 
 #include "../../include/pfc.h"
 
-#define PFC_WG 1024
+#ifndef PFC_WAVES
 #define PFC_WAVES 16
+#endif
+#define PFC_WG (PFC_WAVES * 64)
 #define PFC_SLICE 64
 #define PFC_MAXM 32
 #define PFC_NSTEPS_P 5
