@@ -32,11 +32,12 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per solver launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs,
 # each scaled by what the counter reads for a plain device copy of known size
 # (fetch x2.0, write x1.0), averaged over every launch of a profiled
-# `--steps 1 --warmup 0` run.  A figure holds only for the kernel sources it
+# `--steps 1 --warmup 0` run (mixed workloads: `--no-precision-check`).  A figure holds only for the kernel sources it
 # was taken on: when their digest differs, `traffic` is reported as null.
 TRAFFIC = {
     # workload: (sha256 of the kernel sources, bytes per launch, algorithmic bytes per launch of the same run)
-    "pfc2d_512_fp64": ("0ecf4fdb166a674ec74466fa5312c6183129b1844f1d48348d16bb0a91ee6a29", 40483035.0, 37986008.0),
+    "pfc2d_512_fp64": ("06897b06eaba9d4e11693eb30e86e75114633f98aa14f78d1fbda2fe3837af92", 40410129.0, 37986008.0),
+    "pfc3d_64_mixed": ("06897b06eaba9d4e11693eb30e86e75114633f98aa14f78d1fbda2fe3837af92", 46153298.0, 37670502.0),
 }
 
 
