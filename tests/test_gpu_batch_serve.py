@@ -116,6 +116,11 @@ def test_server_alone_equals_mix_and_admission(pfc, prec):
             pfc.pfc_rosenbrock_run(inst, P.n, s, p.r, p.psibar, p.tau, 2)
             alone.append(host(s))
             pfc.pfc_instance_destroy(inst)
+            # the served precision reaches the oracle's float64 trajectory as closely as two runs
+            # whose stage solves stop at relative residual 1e-8 can
+            x0 = opfc.consistent_init(P.mesh, P.M, P.K, p.r, psi)
+            xr, _ = osolve.rosenbrock_run(P.mesh, P.M, P.K, x0, p.r, p.tau, 2, tol=1e-8)
+            assert rel(alone[-1], xr) <= 1e-6
         # served with room for everything, then with a budget that fits about two instances
         fp = max(pfc.pfc_instance_footprint(m, pfc.pfc_opts_default(precision=prec)) for m in meshes)
         for slots, budget in [(8, 64 << 30), (8, int(2.2 * fp))]:
