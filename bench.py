@@ -36,21 +36,24 @@ HBM_PEAK_GBS = 8000.0
 # was taken on: when their digest differs, `traffic` is reported as null.
 TRAFFIC = {
     # workload: (sha256 of the kernel sources, bytes per launch, algorithmic bytes per launch of the same run)
-    "pfc2d_512_fp64": ("06897b06eaba9d4e11693eb30e86e75114633f98aa14f78d1fbda2fe3837af92", 40410129.0, 37986008.0),
-    "pfc3d_64_mixed": ("06897b06eaba9d4e11693eb30e86e75114633f98aa14f78d1fbda2fe3837af92", 46153298.0, 37670502.0),
+    "pfc2d_512_fp64": ("1da4003d8227d5af273d26bf430857cad7eae3a696b47dbe2409e9c598084cff", 40410135.0, 37986008.0),
+    "pfc3d_64_mixed": ("1da4003d8227d5af273d26bf430857cad7eae3a696b47dbe2409e9c598084cff", 46155546.0, 37670502.0),
 }
+
+
+# the sources that build the solver kernel and the mesh layout it reads (not the server's host code)
+KERNEL_SOURCES = ["include/pfc.h"] + [f"paper_1501_06852_amd/csrc/{f}" for f in
+                                      ("device.h", "host.h", "mesh.hip", "pfc_internal.h", "solver.h", "solver.hip")]
 
 
 def kernel_source_digest():
     import hashlib
 
     d = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1501_06852_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            d.update(name.encode())
-            with open(os.path.join(csrc, name), "rb") as f:
-                d.update(f.read())
+    for rel in KERNEL_SOURCES:
+        d.update(rel.encode())
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            d.update(f.read())
     return d.hexdigest()
 
 

@@ -36,6 +36,12 @@
  *     returns a message for the calling thread.
  *   - All arithmetic of the outer solver is float64.  In PFC_MIXED precision
  *     the inner PCG solves and their matrix-vector products use float32.
+ *   - A solver call (solve, Rosenbrock run, batch, preconditioner apply)
+ *     that has not finished after a wall-clock limit returns PFC_ERR_STATE
+ *     once the work already enqueued has drained.  The limit is 600 s per
+ *     instance (a batch: per instance of the batch), or the value of the
+ *     environment variable PFC_TIMEOUT_S, in seconds, read when an instance
+ *     is created.
  */
 #ifndef PFC_H
 #define PFC_H

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -59,6 +60,7 @@ struct pfc_server {
   Group grp;
   std::chrono::steady_clock::time_point t0;
   int error = PFC_OK;
+  std::string error_msg;  // pfc_last_error() of the server thread at the error
   double clock() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
 };
 
@@ -179,6 +181,19 @@ int rebuild(pfc_server* S) {
   return PFC_OK;
 }
 
+// the loop stops after an error; callers read the code under the mutex
+void fail(pfc_server* S, int code) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->error = code;
+  S->error_msg = pfc_last_error();
+}
+
+// report the server's error to the calling thread (caller holds the mutex)
+int server_error(const pfc_server* S) {
+  if (S->error) set_error("server stopped after an error: " + S->error_msg);
+  return S->error;
+}
+
 void loop(pfc_server* S) {
   (void)hipSetDevice(S->device);
   for (;;) {
@@ -211,18 +226,23 @@ void loop(pfc_server* S) {
         changed = true;
       }
     }
-    if (changed && rebuild(S)) { S->error = PFC_ERR_HIP; break; }
+    if (changed && rebuild(S)) { fail(S, PFC_ERR_HIP); break; }
     if (S->active.empty()) continue;
     if (hipGraphLaunch(S->grp.exec, S->stream) != hipSuccess || hipStreamSynchronize(S->stream) != hipSuccess) {
-      S->error = PFC_ERR_HIP;
+      fail(S, PFC_ERR_HIP);
       break;
     }
+    // finished requests move to `done`; every other one (also one whose
+    // retirement failed) stays in `active`, so each request sits in exactly
+    // one list and pfc_server_destroy frees it once
     std::vector<Request*> still;
     bool retired = false;
+    int err = PFC_OK;
     for (size_t i = 0; i < S->active.size(); ++i) {
       Request* q = S->active[i];
-      if (((volatile int*)S->grp.h_flags)[i] == PH_DONE) {
-        if (retire(S, q)) { S->error = PFC_ERR_HIP; break; }
+      if (!err && ((volatile int*)S->grp.h_flags)[i] == PH_DONE) {
+        const int rc = retire(S, q);
+        if (rc) { err = rc; still.push_back(q); continue; }
         q->t_done = S->clock();
         std::lock_guard<std::mutex> lk(S->mu);
         S->done.push_back(q);
@@ -231,14 +251,12 @@ void loop(pfc_server* S) {
         still.push_back(q);
       }
     }
-    if (S->error) break;
-    if (retired) {
-      {
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->active.swap(still);
-      }
-      if (rebuild(S)) { S->error = PFC_ERR_HIP; break; }
+    if (retired || err) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->active.swap(still);
     }
+    if (err) { fail(S, err); break; }
+    if (retired && rebuild(S)) { fail(S, PFC_ERR_HIP); break; }
   }
   std::lock_guard<std::mutex> lk(S->mu);
   S->cv_idle.notify_all();
@@ -287,7 +305,7 @@ int pfc_server_submit(pfc_server* S, pfc_mesh* mesh, double r, double psibar, do
   q->psi0.assign(psi0, psi0 + mesh->n);
   {
     std::lock_guard<std::mutex> lk(S->mu);
-    if (S->error) { delete q; set_error("pfc_server_submit: server stopped after an error"); return S->error; }
+    if (S->error) { delete q; return server_error(S); }
     q->t_submit = S->clock();
     S->pending.push_back(q);
   }
@@ -309,7 +327,7 @@ int pfc_server_poll(pfc_server* S, pfc_result* out, int max, int* n_out) {
     delete q;
   }
   *n_out = k;
-  return S->error ? S->error : PFC_OK;
+  return server_error(S);
 }
 
 void pfc_result_free(pfc_result* r) {
@@ -324,7 +342,7 @@ int pfc_server_drain(pfc_server* S) {
   if (!S) { set_error("pfc_server_drain: null server"); return PFC_ERR_ARG; }
   std::unique_lock<std::mutex> lk(S->mu);
   S->cv_idle.wait(lk, [&] { return S->error || (S->pending.empty() && S->active.empty()); });
-  return S->error;
+  return server_error(S);
 }
 
 double pfc_server_clock(const pfc_server* S) { return S ? S->clock() : 0.0; }
@@ -338,7 +356,12 @@ void pfc_server_destroy(pfc_server* S) {
   S->cv_work.notify_all();
   if (S->th.joinable()) S->th.join();
   S->grp.release();
-  for (Request* q : S->active) { if (q->inst) pfc_instance_destroy(q->inst); delete q; }
+  for (Request* q : S->active) {
+    if (q->inst) pfc_instance_destroy(q->inst);
+    std::free(q->state_out);
+    std::free(q->infos_out);
+    delete q;
+  }
   for (Request* q : S->pending) delete q;
   for (Request* q : S->done) { std::free(q->state_out); std::free(q->infos_out); delete q; }
   for (pfc_instance* I : S->pool) pfc_instance_destroy(I);

@@ -11,6 +11,7 @@
 // atomics.  The host captures a fixed number of launches in a graph, replays
 // it, and polls a pinned flag written by a small report kernel at the end of
 // each replay.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -1437,8 +1438,14 @@ int pfc_batch_run(pfc_instance* const* insts, int count, double* const* states, 
       set_error("pfc_batch_run: instance " + std::to_string(i) + " invalid (null, mixed precision, or bad parameters)");
       return PFC_ERR_ARG;
     }
-    for (int k = 0; k < i; ++k)
-      if (insts[k] == insts[i]) { set_error("pfc_batch_run: instances must be distinct"); return PFC_ERR_ARG; }
+  }
+  {
+    std::vector<const pfc_instance*> sorted(insts, insts + count);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) {
+      set_error("pfc_batch_run: instances must be distinct");
+      return PFC_ERR_ARG;
+    }
   }
   hipStream_t s = (hipStream_t)stream;
   std::vector<int> ts(count);

@@ -128,6 +128,11 @@ def test_zero_rhs_and_bad_args(pfc):
         assert st == pfc.PFC_OK and gi["outer_iters"] == 0 and not host(x).any()
         with pytest.raises(pfc.PFCError):
             pfc.pfc_solve(inst, n, dev(P.psi), -0.3, -0.3, -1.0, M11, dev(np.zeros(3 * n)), x)
+        # a batch that names one instance twice is refused before anything runs
+        s0 = dev(np.concatenate([np.zeros(n), P.psi, np.zeros(n)]))
+        with pytest.raises(pfc.PFCError) as e:
+            pfc.pfc_batch_run([inst, inst], [n, n], [s0, dev(host(s0))], [-0.3] * 2, [-0.3] * 2, [0.5] * 2, 1)
+        assert e.value.code == pfc.PFC_ERR_ARG and "distinct" in pfc.pfc_last_error()
     finally:
         if inst is not None:
             pfc.pfc_instance_destroy(inst)
