@@ -180,8 +180,11 @@ double pfc_tau_critical(double r, double psibar);
  *   elem_coords  host float64 [n_elem * (dim+1) * dim], vertex coordinates of
  *                each simplex, unwrapped across periodic boundaries
  *   out          receives the handle
- * Returns PFC_ERR_ARG for out-of-range or repeated nodes, degenerate
- * simplices or non-finite coordinates. */
+ * Returns PFC_ERR_ARG for out-of-range or repeated nodes, a node that belongs
+ * to no simplex, non-finite coordinates, or a degenerate simplex: one whose
+ * |det(x_1 - x_0, ..., x_dim - x_0)| is at most 1e-12 times the product of
+ * the edge lengths |x_a - x_0|.  All of these are checked on the host before
+ * any device call. */
 int pfc_mesh_create_p1(int dim, int n, int n_elem, const int32_t* elem_nodes,
                        const double* elem_coords, pfc_mesh** out);
 

@@ -586,6 +586,30 @@ static int create_lagrange(const char* who, int dim, int degree, int n, int n_el
       set_error(std::string(who) + ": non-finite coordinate");
       return PFC_ERR_ARG;
     }
+  // a simplex of (numerically) zero volume has no barycentric gradients:
+  // |det(x_1 - x_0, ..., x_m - x_0)| must exceed 1e-12 times the product of
+  // its edge lengths from x_0
+  for (long long e = 0; e < n_elem; ++e) {
+    const double* x = elem_coords + e * kv * dim;
+    double J[3][3] = {{0.0}};
+    double scale = 1.0;
+    for (int a = 1; a <= dim; ++a) {
+      double len2 = 0.0;
+      for (int d = 0; d < dim; ++d) {
+        J[a - 1][d] = x[a * dim + d] - x[d];
+        len2 += J[a - 1][d] * J[a - 1][d];
+      }
+      scale *= std::sqrt(len2);
+    }
+    const double det = dim == 2 ? J[0][0] * J[1][1] - J[0][1] * J[1][0]
+                                : J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                      J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                      J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    if (!(std::fabs(det) > 1e-12 * scale)) {
+      set_error(std::string(who) + ": element " + std::to_string(e) + " is degenerate (zero volume)");
+      return PFC_ERR_ARG;
+    }
+  }
   pfc_mesh* m = new pfc_mesh();
   m->dim = dim; m->n = n; m->n_elem = n_elem;
   m->degree = degree; m->nloc = k;

@@ -59,6 +59,25 @@ def test_mesh_validation_on_host(pfc):
         pfc.pfc_mesh_create_p1(2, 4, np.array([[0, 1, 1]]), np.zeros((1, 3, 2)))
     h = C.c_void_p()
     assert pfc._lib.pfc_mesh_create_p1(4, 4, 1, None, None, C.byref(h)) == pfc.PFC_ERR_ARG
+    # empty meshes, a node outside every simplex, zero-volume simplices (collinear / coplanar vertices)
+    assert pfc._lib.pfc_mesh_create_p1(2, 0, 0, None, None, C.byref(h)) == pfc.PFC_ERR_ARG
+    with pytest.raises(pfc.PFCError) as e:
+        pfc.pfc_mesh_create_p1(2, 4, np.array([[0, 1, 2]]), np.array([[[0, 0], [1, 0], [0, 1]]], float))
+    assert e.value.code == pfc.PFC_ERR_ARG and "no element" in str(e.value)
+    with pytest.raises(pfc.PFCError) as e:
+        pfc.pfc_mesh_create_p1(2, 3, np.array([[0, 1, 2]]), np.array([[[0, 0], [1, 0], [2, 0]]], float))
+    assert e.value.code == pfc.PFC_ERR_ARG and "degenerate" in str(e.value)
+    tet = np.array([[[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]]], float)
+    with pytest.raises(pfc.PFCError) as e:
+        pfc.pfc_mesh_create_p1(3, 4, np.array([[0, 1, 2, 3]]), tet)
+    assert e.value.code == pfc.PFC_ERR_ARG and "degenerate" in str(e.value)
+    # a thin but valid simplex passes the host checks (without a device the call then fails in HIP)
+    thin = np.ascontiguousarray([[[0, 0], [1, 0], [0.5, 1e-6]]], dtype=np.float64)
+    en = np.ascontiguousarray([[0, 1, 2]], dtype=np.int32)
+    rc = pfc._lib.pfc_mesh_create_p1(2, 3, 1, en.ctypes.data_as(pfc._ip), thin.ctypes.data_as(pfc._dp), C.byref(h))
+    assert rc in (pfc.PFC_OK, pfc.PFC_ERR_HIP), pfc.pfc_last_error()
+    if rc == pfc.PFC_OK:
+        pfc.pfc_mesh_destroy(h)
     # CSR: missing diagonal, unsorted columns, asymmetric pattern
     rp = np.array([0, 1, 2], np.int32)
     with pytest.raises(pfc.PFCError):

@@ -7,7 +7,8 @@ from oracle import assembly, pfc as opfc, precond
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(2, 16, 0.2), (2, 10, 0.0), (3, 5, 0.2), (3, 4, 0.0)]  # n = 256, 100 (ragged), 125 (ragged), 64
+CASES = [(2, 16, 0.2), (2, 10, 0.0), (3, 5, 0.2), (3, 4, 0.0),   # n = 256, 100 (ragged), 125 (ragged), 64
+         (2, 3, 0.2), (3, 3, 0.2)]                               # n = 9, 27: less than one slice
 
 
 @pytest.fixture(scope="module")
@@ -56,7 +57,7 @@ def test_spmv_N_and_cubic_load(pfc, dim, N, jit):
         P.close()
 
 
-@pytest.mark.parametrize("dim,N,jit", CASES[:3])
+@pytest.mark.parametrize("dim,N,jit", CASES[:3] + CASES[4:])
 def test_apply_AR_and_stage_rhs(pfc, dim, N, jit):
     P = Problem(dim, N, jit, amp=0.2, seed=5)
     inst = None

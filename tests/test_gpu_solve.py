@@ -24,9 +24,11 @@ def _stage1(P, r, tau):
     return x0, b
 
 
-# the last two cases span several workgroups with a ragged last one: 3D float64
-# runs stage the columns in LDS, 2D float64 runs read them from memory
-@pytest.mark.parametrize("dim,N,jit,tau,prec", [(2, 16, 0.2, 0.1, 0), (2, 10, 0.0, 1.0, 0), (3, 5, 0.2, 0.5, 0),
+# the last three cases span several workgroups with a ragged last one: 3D float64
+# runs stage the columns in LDS, 2D float64 runs read them from memory; the
+# first two are smaller than one 64-row slice
+@pytest.mark.parametrize("dim,N,jit,tau,prec", [(2, 3, 0.2, 0.5, 0), (3, 3, 0.2, 0.5, 0),
+                                                (2, 16, 0.2, 0.1, 0), (2, 10, 0.0, 1.0, 0), (3, 5, 0.2, 0.5, 0),
                                                 (2, 24, 0.2, 1.0, 0), (3, 24, 0.1, 0.5, 0), (2, 72, 0.2, 1.0, 0)])
 def test_solve_replay_parity(pfc, dim, N, jit, tau, prec):
     P = Problem(dim, N, jit, seed=7)
