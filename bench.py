@@ -373,6 +373,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "traffic_over_algorithmic": None if traffic is None else traffic / traffic_alg,
+                     "traffic_GBps": None if traffic is None else traffic / period_s / 1e9,
                      "kernel": "k_tick (solver phase launch)", "launches": launches,
                      "algorithmic_bytes": alg, "algorithmic_bytes_per_launch": alg / max(1, launches),
                      "avg_launch_period_us": period_s * 1e6, "kernel_sources_sha256": kernel_source_digest()},
