@@ -106,7 +106,14 @@ typedef struct pfc_server pfc_server;
  *                 from psi_k for a single solve and once from the initial state
  *                 for a Rosenbrock run (the scheme conserves the integral of psi).
  *                 PFC1 needs the element geometry: meshes from pfc_mesh_create_p1.
- *   psi_min       lower bound of the order parameter in the mobility (-1.5) */
+ *   psi_min       lower bound of the order parameter in the mobility (-1.5)
+ *   grid_columns  1 (default): on periodic grid meshes (n = N^dim nodes
+ *                 numbered x + N (y + N z), neighbours at most one step away
+ *                 per direction) the solver kernel computes the column of each
+ *                 stored entry from its row instead of reading it; same
+ *                 columns in the same order, so the same results bit for bit.
+ *                 0: always read the stored columns.  Used only when every
+ *                 thread of the instance's team owns one row. */
 typedef struct pfc_opts {
     int struct_size;
     int precision;
@@ -124,6 +131,8 @@ typedef struct pfc_opts {
     int sd_iters;
     int model;
     double psi_min;
+    int grid_columns;
+    int reserved;
 } pfc_opts;
 
 /* Result record of one stage solve.

@@ -28,31 +28,44 @@ struct Team {
 #define PFC_LCOL (PFC_WAVES * 64 * PFC_LCOL_W)
 __shared__ int pfc_lcol[PFC_LCOL];
 
-// Slice geometry and columns of a SELL pattern.  L: the P1 pattern with its
-// columns staged in pfc_lcol (uniform width uw).
-template <bool L>
+// Where a launch takes the columns of the P1 pattern from: memory, the LDS
+// staging buffer, or computed from the row (periodic grid meshes, grid_col).
+#define PFC_COL_MEM 0
+#define PFC_COL_LDS 1
+#define PFC_COL_GRID 2
+
+// Slice geometry and columns of a SELL pattern.  L: one of PFC_COL_*; the
+// staged and computed forms need a uniform slice width uw.
+template <int L>
 struct PatView {
   const int* sp;    // slice offsets [n_slices + 1]
   const int* col;   // columns [nnz_sell]
   int uw;           // uniform slice width, or 0
-  int lo;           // SELL position of pfc_lcol[0] (L only)
+  int lo;           // SELL position of pfc_lcol[0] (L == PFC_COL_LDS)
+  int n, gN;        // grid columns (L == PFC_COL_GRID): grid_col with
+  float gInv;       //   1/N and the displacement table gd
+  const unsigned char* gd;
   __device__ __forceinline__ int base(int sl) const {
-    if constexpr (L) return sl * 64 * uw;
+    if constexpr (L != PFC_COL_MEM) return sl * 64 * uw;
     else return uw ? sl * 64 * uw : sp[sl];
   }
   __device__ __forceinline__ int width(int sl) const {
-    if constexpr (L) return uw;
+    if constexpr (L != PFC_COL_MEM) return uw;
     else return uw ? uw : ((sp[sl + 1] - sp[sl]) >> 6);
   }
-  __device__ __forceinline__ int at(long long e) const {
-    if constexpr (L) return pfc_lcol[(int)(e - lo)];
+  // column of stored entry e, which belongs to row i (entry e - base(sl) of
+  // slice sl = i / 64 sits at position k = (e >> 6) - sl uw of its row)
+  __device__ __forceinline__ int at(long long e, int i) const {
+    if constexpr (L == PFC_COL_GRID) return grid_col(i, (int)(e >> 6) - (i >> 6) * uw, n, gN, gInv, gd);
+    else if constexpr (L == PFC_COL_LDS) return pfc_lcol[(int)(e - lo)];
     else return col[e];
   }
 };
 
-template <bool L>
+template <int L>
 __device__ __forceinline__ PatView<L> p1_pat(const InstDev& I, const Team& tm) {
-  return PatView<L>{I.m.slice_ptr, I.m.col, I.m.uw, tm.lo};
+  return PatView<L>{I.m.slice_ptr, I.m.col, I.m.uw, tm.lo, I.n, I.m.gN, I.m.gInv,
+                    L == PFC_COL_GRID ? I.m.gord : nullptr};
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -341,8 +354,8 @@ __device__ __forceinline__ double node_Kplus_mu(const MeshDev& m, int i, PsiF ps
 // Every phase returns this thread's contribution to the two partial sums.
 
 // N(psi_k) = -3 Mpsi2 reassembled in place (one value per stored entry).
-template <bool L>
-__device__ Red3 ph_rb_begin(const InstDev& I, const Team& tm) {
+template <int L>
+__device__ __forceinline__ Red3 ph_rb_begin(const InstDev& I, const Team& tm) {
   const int n = I.n;
   const double* xk = I.xk;
   auto psi = [&](int j) { return xk[n + j]; };
@@ -375,7 +388,7 @@ __device__ __forceinline__ double stage_comb(const InstDev& I, int stage, int bl
 // Stage right-hand side at the row of (slice, lane) (Section 3.1): F(x_i) with
 // block 1 multiplied by tau, plus sum_j c_ij M y_j^psi on block 1, with the
 // stage state x_i = x_k + sum_j a_ij y_j formed on the fly.
-template <bool L>
+template <int L>
 __device__ __forceinline__ void stage_rhs_row(const InstDev& I, const PatView<L>& pv, int sl, int lane, int stage,
                                               double& b0, double& b1, double& b2) {
   const int n = I.n;
@@ -386,7 +399,7 @@ __device__ __forceinline__ void stage_rhs_row(const InstDev& I, const PatView<L>
   const long long n3 = 3LL * n;
   for (int k = 0; k < w; ++k) {
     const long long e = (long long)base + k * 64 + lane;
-    const int j = pv.at(e);
+    const int j = pv.at(e, i);
     const double Mv = I.m.M[e], Kv = I.m.K[e];
     const double mu = stage_comb(I, stage, 0, j);
     const double ps = stage_comb(I, stage, 1, j);
@@ -415,8 +428,8 @@ __device__ __forceinline__ void stage_rhs_row(const InstDev& I, const PatView<L>
 
 // Right-hand side of the solve: stage rhs b_i^R for job RB, the caller's rhs
 // for job SOLVE.  Writes W = b with block 1 divided by m11, X = 0.
-template <bool L>
-__device__ Red3 ph_solve_init(const InstDev& I, const State& S, const Team& tm) {
+template <int L>
+__device__ __forceinline__ Red3 ph_solve_init(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   const bool rb = (S.job == JOB_RB);
   const PatView<L> pv = p1_pat<L>(I, tm);
@@ -443,7 +456,7 @@ __device__ Red3 ph_solve_init(const InstDev& I, const State& S, const Team& tm) 
   return red3(a0, a1);
 }
 
-__device__ Red3 ph_rb_update(const InstDev& I, const Team& tm) {
+__device__ __forceinline__ Red3 ph_rb_update(const InstDev& I, const Team& tm) {
   const int n = I.n;
   const long long n3 = 3LL * n;
   PFC_SLICES(I, tm) {
@@ -514,9 +527,11 @@ __device__ __forceinline__ PcgOps<T> pcg_ops(const InstDev& I, int kind) {
 
 // Pattern of the operator of a PCG solve: the P1 pattern (staged columns when
 // L) or, for S_D, the second-ring pattern (never staged).
-template <bool L, typename T>
+template <int L, typename T>
 __device__ __forceinline__ PatView<L> op_pat(const InstDev& I, const PcgOps<T>& o, const Team& tm) {
-  return PatView<L>{o.sp, o.colp, o.sp == I.m.slice_ptr ? I.m.uw : 0, tm.lo};
+  // (the S_D pattern is only ever read with L == PFC_COL_MEM)
+  return PatView<L>{o.sp, o.colp, o.sp == I.m.slice_ptr ? I.m.uw : 0, tm.lo, I.n, I.m.gN, I.m.gInv,
+                    L == PFC_COL_GRID ? I.m.gord : nullptr};
 }
 
 template <typename T>
@@ -525,20 +540,20 @@ __device__ __forceinline__ T opval(const PcgOps<T>& o, long long e) {
 }
 
 // y_i = (A v)_i for a stored operator A (typed) over the row of thread lane
-template <typename T, bool L, typename VF>
+template <typename T, int L, typename VF>
 __device__ __forceinline__ T row_dot(const PatView<L>& pv, int sl, int lane, const T* A, VF v) {
   const int base = pv.base(sl);
   const int w = pv.width(sl);
   T acc = T(0);
   for_width(w, [&](int k) {
     const long long e = (long long)base + k * 64 + lane;
-    acc += A[e] * v(pv.at(e));
+    acc += A[e] * v(pv.at(e, sl * 64 + lane));
   });
   return acc;
 }
 
-template <typename T, bool L>
-__device__ Red3 ph_pcg_setup(const InstDev& I, const State& S, const Team& tm) {
+template <typename T, int L>
+__device__ __forceinline__ Red3 ph_pcg_setup(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   const int kind = S.kind;
   PcgOps<T> o = pcg_ops<T>(I, kind);
@@ -600,7 +615,7 @@ __device__ Red3 ph_pcg_setup(const InstDev& I, const State& S, const Team& tm) {
         double sMp = 0, sKp = 0, sKo = 0;
         for (int k = 0; k < w; ++k) {
           const long long e = (long long)base + k * 64 + lane;
-          const int j = pv.at(e);
+          const int j = pv.at(e, i);
           sMp += I.m.M[e] * I.xk[n + j];
           sKp += I.m.K[e] * I.xk[n + j];
           sKo += I.m.K[e] * I.xk[2 * n + j];
@@ -630,8 +645,8 @@ __device__ __forceinline__ T pval(const T* dinv, const T* r, const T* pold, T be
   return first ? z : (z + beta * pold[j]);
 }
 
-template <typename T, bool L>
-__device__ Red3 ph_pcg_a(const InstDev& I, const State& S, const Team& tm) {
+template <typename T, int L>
+__device__ __forceinline__ Red3 ph_pcg_a(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   PcgOps<T> o = pcg_ops<T>(I, S.kind);
   const PatView<L> pv = op_pat<L>(I, o, tm);
@@ -649,7 +664,7 @@ __device__ Red3 ph_pcg_a(const InstDev& I, const State& S, const Team& tm) {
     T acc = T(0);
     for_width(w, [&](int k) {
       const long long e = (long long)base + k * 64 + tm.lane;
-      const int j = pv.at(e);
+      const int j = pv.at(e, i);
       acc += opval(o, e) * pval(o.dinv, r, pold, beta, first, j);
     });
     if (i < n) {
@@ -663,7 +678,7 @@ __device__ Red3 ph_pcg_a(const InstDev& I, const State& S, const Team& tm) {
 }
 
 template <typename T>
-__device__ Red3 ph_pcg_b(const InstDev& I, const State& S, const Team& tm) {
+__device__ __forceinline__ Red3 ph_pcg_b(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   PcgOps<T> o = pcg_ops<T>(I, S.kind);
   T* r = (T*)I.r_;
@@ -692,7 +707,7 @@ __device__ Red3 ph_pcg_b(const InstDev& I, const State& S, const Team& tm) {
 //   w1 = t K mu + s M psi
 //   w2 = K psi + M omega
 //   PFC1 (MOB): w1 = t K_+ mu + s M psi + t F psi
-template <bool L, bool MOB, typename YF>
+template <int L, bool MOB, typename YF>
 __device__ __forceinline__ void block_row(const InstDev& I, const PatView<L>& pv, int sl, int lane, double t, double s,
                                           YF y, double& w0, double& w1, double& w2) {
   const int base = pv.base(sl);
@@ -701,7 +716,7 @@ __device__ __forceinline__ void block_row(const InstDev& I, const PatView<L>& pv
   w0 = w1 = w2 = 0.0;
   for_width(w, [&](int k) {
     const long long e = (long long)base + k * 64 + lane;
-    const int j = pv.at(e);
+    const int j = pv.at(e, sl * 64 + lane);
     const double Mv = I.m.M[e], Kv = I.m.K[e], Nv = I.N[e];
     double mu, ps, om;
     y(j, mu, ps, om);
@@ -712,8 +727,8 @@ __device__ __forceinline__ void block_row(const InstDev& I, const PatView<L>& pv
   });
 }
 
-template <typename T, bool L, bool MOB>
-__device__ Red3 ph_aspmv(const InstDev& I, const State& S, const Team& tm) {
+template <typename T, int L, bool MOB>
+__device__ __forceinline__ Red3 ph_aspmv(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   const PatView<L> pv = p1_pat<L>(I, tm);
   const long long n3 = 3LL * n;
@@ -737,7 +752,7 @@ __device__ Red3 ph_aspmv(const InstDev& I, const State& S, const Team& tm) {
   return red3(a0, a1);
 }
 
-__device__ Red3 ph_mgs(const InstDev& I, const State& S, const Team& tm, bool last) {
+__device__ __forceinline__ Red3 ph_mgs(const InstDev& I, const State& S, const Team& tm, bool last) {
   const int n = I.n;
   const long long n3 = 3LL * n;
   const int ip = last ? S.j : S.mgs_i - 1;
@@ -759,7 +774,7 @@ __device__ Red3 ph_mgs(const InstDev& I, const State& S, const Team& tm, bool la
   return red3(a0, 0.0);
 }
 
-__device__ Red3 ph_update_x(const InstDev& I, const State& S, const Team& tm, const double* y) {
+__device__ __forceinline__ Red3 ph_update_x(const InstDev& I, const State& S, const Team& tm, const double* y) {
   const int n = I.n;
   const long long n3 = 3LL * n;
   double* X = (S.job == JOB_RB) ? (I.ys + (long long)(S.stage - 1) * n3) : I.x_user;
@@ -778,8 +793,8 @@ __device__ Red3 ph_update_x(const InstDev& I, const State& S, const Team& tm, co
   return red3(0.0, 0.0);
 }
 
-template <bool L, bool MOB>
-__device__ Red3 ph_true_res(const InstDev& I, const State& S, const Team& tm) {
+template <int L, bool MOB>
+__device__ __forceinline__ Red3 ph_true_res(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   const PatView<L> pv = p1_pat<L>(I, tm);
   const long long n3 = 3LL * n;
@@ -806,7 +821,7 @@ __device__ Red3 ph_true_res(const InstDev& I, const State& S, const Team& tm) {
 }
 
 template <typename T>
-__device__ Red3 ph_pch_out(const InstDev& I, const Team& tm) {
+__device__ __forceinline__ Red3 ph_pch_out(const InstDev& I, const Team& tm) {
   const int n = I.n;
   const T* x2 = (const T*)I.x2;
   PFC_SLICES(I, tm) {
@@ -839,8 +854,8 @@ __device__ __forceinline__ T cg_unew(const T* dinv, const T* rc, const T* wc, co
   return dinv[j] * (rc[j] - alpha * cg_s(wc, so, beta, first, j));
 }
 
-template <typename T, bool L>
-__device__ Red3 ph_cg_init(const InstDev& I, const State& S, const Team& tm) {
+template <typename T, int L>
+__device__ __forceinline__ Red3 ph_cg_init(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   PcgOps<T> o = pcg_ops<T>(I, S.kind);
   const PatView<L> pv = op_pat<L>(I, o, tm);
@@ -854,7 +869,7 @@ __device__ Red3 ph_cg_init(const InstDev& I, const State& S, const Team& tm) {
     T acc = T(0);
     for_width(wd, [&](int k) {
       const long long e = (long long)base + k * 64 + tm.lane;
-      const int j = pv.at(e);
+      const int j = pv.at(e, i);
       acc += opval(o, e) * (o.dinv[j] * r[j]);
     });
     if (i < n) {
@@ -868,8 +883,8 @@ __device__ Red3 ph_cg_init(const InstDev& I, const State& S, const Team& tm) {
   return red3(a0, a1, a2);
 }
 
-template <typename T, bool L>
-__device__ Red3 ph_cg_iter(const InstDev& I, const State& S, const Team& tm) {
+template <typename T, int L>
+__device__ __forceinline__ Red3 ph_cg_iter(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   PcgOps<T> o = pcg_ops<T>(I, S.kind);
   const PatView<L> pv = op_pat<L>(I, o, tm);
@@ -891,7 +906,7 @@ __device__ Red3 ph_cg_iter(const InstDev& I, const State& S, const Team& tm) {
     T acc = T(0);
     for_width(wd, [&](int k) {
       const long long e = (long long)base + k * 64 + tm.lane;
-      const int j = pv.at(e);
+      const int j = pv.at(e, i);
       acc += opval(o, e) * cg_unew(o.dinv, rc, wc, so, alpha, beta, first, j);
     });
     if (i < n) {

@@ -13,7 +13,7 @@ struct Group {
   int count = 0, n_wg = 0, graph_ticks = 0;
   TeamEntry* d_teams = nullptr;
   std::vector<TeamEntry> h_teams;
-  bool lds = false;             // launches stage the P1 columns in LDS
+  int cols = 0;                 // where the launches take the P1 columns from (PFC_COL_*)
   InstDev* d_descs = nullptr;
   InstDev* h_descs = nullptr;   // pinned staging of the descriptors
   State* h_states = nullptr;    // pinned staging of the initial states

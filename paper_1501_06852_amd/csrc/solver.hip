@@ -348,7 +348,7 @@ __device__ unsigned long long g_trace_cap = 0;
 // main path.  (Several call sites of one instantiation make the compiler keep
 // it out of line, and the out-of-line call costs a scratch spill of the team
 // record on every launch.)
-template <typename TT, bool L, int PH>
+template <typename TT, int L, int PH>
 __device__ __forceinline__ Red3 pcg_phase_one(const InstDev& I, const State& S, const Team& tm) {
   if constexpr (PH == PH_PCG_SETUP) return ph_pcg_setup<TT, L>(I, S, tm);
   else if constexpr (PH == PH_PCG_A) return ph_pcg_a<TT, L>(I, S, tm);
@@ -357,26 +357,28 @@ __device__ __forceinline__ Red3 pcg_phase_one(const InstDev& I, const State& S, 
   else return ph_cg_iter<TT, L>(I, S, tm);
 }
 
-template <typename T, bool LDS, int PH>
+template <typename T, int COLS, int PH>
 __device__ __forceinline__ Red3 pcg_phase(const InstDev& I, const State& S, const Team& tm, bool sd) {
   constexpr bool uses_pattern = (PH != PH_PCG_SETUP && PH != PH_PCG_B);  // the operator's own SpMV
   if constexpr (!std::is_same<T, double>::value) {
-    if (is_ci(S.kind)) return pcg_phase_one<double, LDS, PH>(I, S, tm);
+    if (is_ci(S.kind)) return pcg_phase_one<double, COLS, PH>(I, S, tm);
   }
-  if constexpr (LDS && uses_pattern) {
-    if (sd) return pcg_phase_one<T, false, PH>(I, S, tm);
+  if constexpr (COLS != PFC_COL_MEM && uses_pattern) {
+    if (sd) return pcg_phase_one<T, PFC_COL_MEM, PH>(I, S, tm);
   }
-  return pcg_phase_one<T, LDS, PH>(I, S, tm);
+  return pcg_phase_one<T, COLS, PH>(I, S, tm);
 }
 
 // One solver launch.  SINGLE: the launch serves one instance and receives its
 // state and partial-sum buffers and its mesh pattern as kernel arguments
 // (preloaded into scalar registers), so the first memory round trip already
 // fetches the state.  Otherwise each workgroup looks up its team entry and
-// instance descriptor.  LDS: the workgroup's P1 columns are staged in LDS in
-// the same round trip (uniform slice width, at most PFC_WAVES slices per
-// workgroup; the host launches this variant only then).
-template <typename T, bool SINGLE, bool LDS>
+// instance descriptor.  COLS: where the P1 columns come from (PFC_COL_*).
+// PFC_COL_LDS stages the workgroup's columns in LDS in the same round trip
+// (uniform slice width, at most PFC_WAVES slices per workgroup); PFC_COL_GRID
+// computes them from the row (periodic grid meshes).  The host picks the
+// variant that the launch's meshes allow.
+template <typename T, bool SINGLE, int COLS>
 __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ teams, const InstDev* __restrict__ insts,
                                                  const State* st_in_arg, State* st_out_arg, const double* part_in_arg,
                                                  double* part_out_arg, int parity, const int* __restrict__ col_arg,
@@ -414,7 +416,7 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   // pattern, issued first and written to LDS once everything has arrived
   int lo = 0, len = 0;
   int cv[PFC_LCOL_W];
-  if (LDS) {
+  if (COLS == PFC_COL_LDS) {
     const int spw = (te.n_slices + te.size - 1) / te.size;
     const int sbeg = te.rank * spw;
     const int send = min(sbeg + spw, te.n_slices);
@@ -430,7 +432,7 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   for (int k = tid; k < te.size; k += PFC_WG) { pre.a += part_in[4 * k]; pre.b += part_in[4 * k + 1]; pre.c += part_in[4 * k + 2]; }
   if (tid < NS) ((int*)&S)[tid] = ((const int*)st_in)[tid];
   else if (tid >= 64 && tid < 64 + ND) ((int*)&sI)[tid - 64] = ((const int*)gI)[tid - 64];
-  if (LDS) {
+  if (COLS == PFC_COL_LDS) {
 #pragma unroll
     for (int q = 0; q < PFC_LCOL_W; ++q) {
       const int idx = tid + q * PFC_WG;
@@ -469,25 +471,25 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   Red3 acc = red3(0.0, 0.0, 0.0);
   switch (S.phase) {
     case PH_SOLVE_INIT:
-    case PH_RB_RHS: acc = ph_solve_init<LDS>(I, S, tm); break;
-    case PH_RB_BEGIN: acc = ph_rb_begin<LDS>(I, tm); break;
+    case PH_RB_RHS: acc = ph_solve_init<COLS>(I, S, tm); break;
+    case PH_RB_BEGIN: acc = ph_rb_begin<COLS>(I, tm); break;
     case PH_RB_UPDATE: acc = ph_rb_update(I, tm); break;
     // the mass solves of the consistent initial values run in float64 in every precision
-    case PH_PCG_SETUP: acc = pcg_phase<T, LDS, PH_PCG_SETUP>(I, S, tm, sd); break;
-    case PH_PCG_A: acc = pcg_phase<T, LDS, PH_PCG_A>(I, S, tm, sd); break;
-    case PH_PCG_B: acc = pcg_phase<T, LDS, PH_PCG_B>(I, S, tm, sd); break;
+    case PH_PCG_SETUP: acc = pcg_phase<T, COLS, PH_PCG_SETUP>(I, S, tm, sd); break;
+    case PH_PCG_A: acc = pcg_phase<T, COLS, PH_PCG_A>(I, S, tm, sd); break;
+    case PH_PCG_B: acc = pcg_phase<T, COLS, PH_PCG_B>(I, S, tm, sd); break;
     case PH_ASPMV:
-      acc = I.model == PFC_MODEL_PFC1 ? ph_aspmv<T, LDS, true>(I, S, tm) : ph_aspmv<T, LDS, false>(I, S, tm);
+      acc = I.model == PFC_MODEL_PFC1 ? ph_aspmv<T, COLS, true>(I, S, tm) : ph_aspmv<T, COLS, false>(I, S, tm);
       break;
     case PH_MGS: acc = ph_mgs(I, S, tm, false); break;
     case PH_MGS_LAST: acc = ph_mgs(I, S, tm, true); break;
     case PH_UPDATE_X: acc = ph_update_x(I, S, tm, ybuf); break;
     case PH_TRUE_RES:
-      acc = I.model == PFC_MODEL_PFC1 ? ph_true_res<LDS, true>(I, S, tm) : ph_true_res<LDS, false>(I, S, tm);
+      acc = I.model == PFC_MODEL_PFC1 ? ph_true_res<COLS, true>(I, S, tm) : ph_true_res<COLS, false>(I, S, tm);
       break;
     case PH_PCH_OUT: acc = ph_pch_out<T>(I, tm); break;
-    case PH_CG_INIT: acc = pcg_phase<T, LDS, PH_CG_INIT>(I, S, tm, sd); break;
-    case PH_CG_ITER: acc = pcg_phase<T, LDS, PH_CG_ITER>(I, S, tm, sd); break;
+    case PH_CG_INIT: acc = pcg_phase<T, COLS, PH_CG_INIT>(I, S, tm, sd); break;
+    case PH_CG_ITER: acc = pcg_phase<T, COLS, PH_CG_ITER>(I, S, tm, sd); break;
     default: break;
   }
   PFC_STAMP(t_work);
@@ -649,10 +651,10 @@ __global__ void k_apply_AR(InstDev I, const double* __restrict__ y, double* __re
   const int i = sl * 64 + lane;
   const int n = I.n;
   double w0, w1, w2;
-  const PatView<false> pv{I.m.slice_ptr, I.m.col, I.m.uw, 0};
+  const PatView<PFC_COL_MEM> pv{I.m.slice_ptr, I.m.col, I.m.uw, 0, I.n, 0, 0.0f, nullptr};
   auto yv = [&](int j, double& mu, double& ps, double& om) { mu = y[j]; ps = y[n + j]; om = y[2 * n + j]; };
-  if (I.model == PFC_MODEL_PFC1) block_row<false, true>(I, pv, sl, lane, I.tau, I.m11, yv, w0, w1, w2);
-  else block_row<false, false>(I, pv, sl, lane, I.tau, I.m11, yv, w0, w1, w2);
+  if (I.model == PFC_MODEL_PFC1) block_row<PFC_COL_MEM, true>(I, pv, sl, lane, I.tau, I.m11, yv, w0, w1, w2);
+  else block_row<PFC_COL_MEM, false>(I, pv, sl, lane, I.tau, I.m11, yv, w0, w1, w2);
   if (i < n) { out[i] = w0; out[n + i] = w1; out[2 * n + i] = w2; }
 }
 
@@ -684,8 +686,8 @@ __global__ void k_stage_rhs(InstDev I, int stage, double* __restrict__ b) {
   const int lane = threadIdx.x & 63;
   const int i = sl * 64 + lane;
   double b0, b1, b2;
-  const PatView<false> pv{I.m.slice_ptr, I.m.col, I.m.uw, 0};
-  stage_rhs_row<false>(I, pv, sl, lane, stage, b0, b1, b2);
+  const PatView<PFC_COL_MEM> pv{I.m.slice_ptr, I.m.col, I.m.uw, 0, I.n, 0, 0.0f, nullptr};
+  stage_rhs_row<PFC_COL_MEM>(I, pv, sl, lane, stage, b0, b1, b2);
   if (i < I.n) { b[i] = b0; b[I.n + i] = b1; b[2 * I.n + i] = b2; }
 }
 
@@ -762,6 +764,7 @@ static int validate_opts(const pfc_opts* o) {
   if (o->sd_iters < 1 || o->sd_iters > 10000) { set_error("pfc_opts: sd_iters must be in 1..10000"); return PFC_ERR_ARG; }
   if (o->model != PFC_MODEL_PFC2 && o->model != PFC_MODEL_PFC1) { set_error("pfc_opts: bad model"); return PFC_ERR_ARG; }
   if (!std::isfinite(o->psi_min)) { set_error("pfc_opts: psi_min must be finite"); return PFC_ERR_ARG; }
+  if (o->grid_columns != 0 && o->grid_columns != 1) { set_error("pfc_opts: grid_columns must be 0 or 1"); return PFC_ERR_ARG; }
   return PFC_OK;
 }
 
@@ -797,8 +800,13 @@ int Group::build(hipStream_t capture, int precision, int ticks) {
   // trip; it pays where that stream is a large share of a launch's bytes
   // (measured: 3D 64^3 mixed +5.7%, the mixed 2D/3D served mix +6%, 2D 512^2
   // float64 -2%, where the 7 columns are 16% of an iteration's bytes), so
-  // float64 runs stage only from 8 columns per row on (3D: 22%).
-  lds = true;
+  // float64 runs stage only from 8 columns per row on (3D: 22%).  When every
+  // mesh of the launch is a periodic grid (MeshDev::gN) and every thread owns
+  // one row, the columns are computed from the row instead and no column
+  // stream is read at all (2D 512^2 float64 +8.8%, 3D 64^3 mixed +3.4%, the
+  // served mix +5.7%; with 4 rows per thread, the batched 128^2 mixed run,
+  // -1.7%, so teams with several rows per thread keep the other forms).
+  bool lds = true, grid = true;
   for (TeamEntry& t : h_teams) {
     const MeshDev& m = h_descs[t.inst].m;
     t.uw = m.uw;
@@ -806,10 +814,13 @@ int Group::build(hipStream_t capture, int precision, int ticks) {
     t.n_slices = m.n_slices;
     if (!(m.uw >= 1 && m.uw <= PFC_LCOL_W && (m.n_slices + t.size - 1) / t.size <= PFC_WAVES)) lds = false;
     if (precision == PFC_FP64 && m.uw < 8) lds = false;
+    if (!(m.gN > 0 && m.uw >= 1 && (m.n_slices + t.size - 1) / t.size <= PFC_WAVES) || !h_descs[t.inst].grid_cols)
+      grid = false;
   }
 #ifdef PFC_NO_COLUMN_STAGING
   lds = false;
 #endif
+  cols = grid ? PFC_COL_GRID : (lds ? PFC_COL_LDS : PFC_COL_MEM);
   PFC_HIP(hipMemcpy(d_teams, h_teams.data(), sizeof(TeamEntry) * h_teams.size(), hipMemcpyHostToDevice));
   const int* pcol = count == 1 ? h_descs[0].m.col : nullptr;
   const int puw = count == 1 ? h_descs[0].m.uw : 0;
@@ -830,14 +841,19 @@ int Group::build(hipStream_t capture, int precision, int ticks) {
 #define PFC_TICK(TT, SG, LD)                                                                                    \
   hipLaunchKernelGGL((k_tick<TT, SG, LD>), dim3(n_wg), dim3(PFC_WG), 0, capture, d_teams, d_descs, sin, sout, pin, pout, \
                      par, pcol, puw, pnsl)
+#define PFC_TICK_COLS(TT, SG)                                      \
+  switch (cols) {                                                  \
+    case PFC_COL_GRID: PFC_TICK(TT, SG, PFC_COL_GRID); break;        \
+    case PFC_COL_LDS: PFC_TICK(TT, SG, PFC_COL_LDS); break;          \
+    default: PFC_TICK(TT, SG, PFC_COL_MEM); break;                   \
+  }
     const bool sg = (count == 1);
     if (precision == PFC_MIXED) {
-      if (sg) { if (lds) PFC_TICK(float, true, true); else PFC_TICK(float, true, false); }
-      else { if (lds) PFC_TICK(float, false, true); else PFC_TICK(float, false, false); }
+      if (sg) { PFC_TICK_COLS(float, true); } else { PFC_TICK_COLS(float, false); }
     } else {
-      if (sg) { if (lds) PFC_TICK(double, true, true); else PFC_TICK(double, true, false); }
-      else { if (lds) PFC_TICK(double, false, true); else PFC_TICK(double, false, false); }
+      if (sg) { PFC_TICK_COLS(double, true); } else { PFC_TICK_COLS(double, false); }
     }
+#undef PFC_TICK_COLS
 #undef PFC_TICK
   }
   hipLaunchKernelGGL(k_report, dim3((count + 255) / 256), dim3(256), 0, capture, d_descs, count, d_flags);
@@ -1082,6 +1098,8 @@ void pfc_opts_default(pfc_opts* o) {
   o->sd_iters = 20;
   o->model = PFC_MODEL_PFC2;
   o->psi_min = -1.5;
+  o->grid_columns = 1;
+  o->reserved = 0;
 }
 
 double pfc_tau_critical(double r, double psibar) {
@@ -1140,6 +1158,7 @@ int pfc_instance_create(pfc_mesh* m, const pfc_opts* o, pfc_instance** out) {
   h.sd_iters = o->sd_iters;
   h.model = o->model;
   h.psi_min = o->psi_min;
+  h.grid_cols = o->grid_columns;
   h.m0 = 1.0;
   h.team_size = I->team_size;
   h.outer_tol = o->outer_tol;

@@ -46,7 +46,8 @@ class pfc_opts(C.Structure):
                 ("outer_tol", C.c_double), ("inner_tol", C.c_double), ("inner_maxit", C.c_int),
                 ("shared_ops", C.c_int), ("rows_per_thread", C.c_int), ("max_run_steps", C.c_int),
                 ("ticks_per_graph", C.c_int), ("single_reduction", C.c_int),
-                ("schur_variant", C.c_int), ("sd_iters", C.c_int), ("model", C.c_int), ("psi_min", C.c_double)]
+                ("schur_variant", C.c_int), ("sd_iters", C.c_int), ("model", C.c_int), ("psi_min", C.c_double),
+                ("grid_columns", C.c_int), ("reserved", C.c_int)]
 
 
 class pfc_solve_info(C.Structure):

@@ -24,9 +24,10 @@ def _stage1(P, r, tau):
     return x0, b
 
 
-# the last three cases span several workgroups with a ragged last one: 3D float64
-# runs stage the columns in LDS, 2D float64 runs read them from memory; the
-# first two are smaller than one 64-row slice
+# the last three cases span several workgroups with a ragged last one; the
+# first two are smaller than one 64-row slice.  All are periodic grids, whose
+# columns the kernel computes; test_column_forms_agree_bitwise ties the stored
+# forms (memory, LDS) to these results bit for bit.
 @pytest.mark.parametrize("dim,N,jit,tau,prec", [(2, 3, 0.2, 0.5, 0), (3, 3, 0.2, 0.5, 0),
                                                 (2, 16, 0.2, 0.1, 0), (2, 10, 0.0, 1.0, 0), (3, 5, 0.2, 0.5, 0),
                                                 (2, 24, 0.2, 1.0, 0), (3, 24, 0.1, 0.5, 0), (2, 72, 0.2, 1.0, 0)])
@@ -292,4 +293,36 @@ def test_schur_D_variant_parity(pfc, dim, N, jit, tau, prec):
     finally:
         if inst is not None:
             pfc.pfc_instance_destroy(inst)
+        P.close()
+
+
+# 2D float64 reads the columns from memory, 3D float64 and mixed runs stage them in
+# LDS; the 3D 24^3 case spans several workgroups with a ragged last one
+@pytest.mark.parametrize("dim,N,jit,prec", [(2, 16, 0.2, 0), (3, 5, 0.2, 0), (3, 6, 0.1, 1), (2, 24, 0.2, 1),
+                                            (3, 24, 0.1, 0)])
+def test_column_forms_agree_bitwise(pfc, dim, N, jit, prec):
+    """On periodic grids the kernel computes the columns (grid_columns = 1): the same columns in the
+    same order as the stored ones, so a stage solve and a Rosenbrock step give the same bits."""
+    P = Problem(dim, N, jit, seed=61)
+    insts = []
+    try:
+        r, psibar, tau = -0.35, -0.3, 0.5
+        n = P.n
+        _, b = _stage1(P, r, tau)
+        out = []
+        for g in (1, 0):
+            inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(precision=prec, grid_columns=g))
+            insts.append(inst)
+            x = dev(np.zeros(3 * n))
+            st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
+            assert st == pfc.PFC_OK
+            s = dev(np.concatenate([np.zeros(n), P.psi, np.zeros(n)]))
+            st, _ = pfc.pfc_rosenbrock_run(inst, n, s, r, psibar, tau, 1, pfc.PFC_INIT_CONSISTENT)
+            assert st == pfc.PFC_OK
+            out.append((host(x), host(s), gi["outer_iters"]))
+        assert out[0][2] == out[1][2]
+        assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    finally:
+        for i in insts:
+            pfc.pfc_instance_destroy(i)
         P.close()
