@@ -304,6 +304,7 @@ def main():
         h = pfc.pfc_mesh_create_p1(dim, mesh.n, mesh.elem_nodes, mesh.elem_coords)
     n = mesh.n
     nnz = pfc.pfc_mesh_query(h)["nnz"]
+    gside = pfc.pfc_mesh_grid_side(h)   # the solver computes the columns of periodic grids
     z = nnz / n
     model = var.get("model", 0)
     schur = var.get("schur_variant", 0)
@@ -364,7 +365,8 @@ def main():
                    "jitter_h": jitter, "r": r, "psibar": psibar, "tau": tau, "rosenbrock_steps": steps,
                    "stage_solves": solves, "restart": 30, "outer_tol": 1e-8, "inner_tol": 1e-3,
                    "element_degree": mesh.degree, "model": "PFC1" if model == 1 else "PFC2",
-                   "schur": "S_D" if schur else "S_CH", "initial_state": "smooth" if "smooth" in var else "noise"},
+                   "schur": "S_D" if schur else "S_CH", "initial_state": "smooth" if "smooth" in var else "noise",
+                   "columns": (f"computed from the row (periodic grid, side {gside})" if gside else "read from memory")},
         "status": pfc.pfc_status_str(st),
         "max_true_rel_res": max(res) if res else None,
         "outer_iters_mean": float(np.mean([i["outer_iters"] for i in infos])),

@@ -226,6 +226,10 @@ int pfc_mesh_create_csr(int dim, int n, int nnz, const int32_t* row_ptr, const i
 /* Sizes of a mesh; any pointer may be NULL. */
 int pfc_mesh_query(const pfc_mesh* mesh, int* dim, int* n, int* nnz, int* n_elem);
 
+/* Side N of a periodic grid mesh whose columns the solver kernel computes from
+ * the row (pfc_opts.grid_columns), or 0 for any other mesh.  N: host int. */
+int pfc_mesh_grid_side(const pfc_mesh* mesh, int* N);
+
 /* Copy the pattern and the values of M and K out in CSR order (host arrays of
  * n+1, nnz, nnz, nnz entries; any of them may be NULL). */
 int pfc_mesh_export_csr(const pfc_mesh* mesh, int32_t* row_ptr, int32_t* col_idx,

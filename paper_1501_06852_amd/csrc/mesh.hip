@@ -854,6 +854,12 @@ int pfc_mesh_query(const pfc_mesh* m, int* dim, int* n, int* nnz, int* n_elem) {
   return PFC_OK;
 }
 
+int pfc_mesh_grid_side(const pfc_mesh* m, int* N) {
+  if (!m || !N) { set_error("pfc_mesh_grid_side: null argument"); return PFC_ERR_ARG; }
+  *N = m->dev.gN;
+  return PFC_OK;
+}
+
 int pfc_mesh_export_csr(const pfc_mesh* m, int32_t* row_ptr, int32_t* col_idx, double* M_val, double* K_val) {
   if (!m) { set_error("pfc_mesh_export_csr: null mesh"); return PFC_ERR_ARG; }
   if (row_ptr) std::memcpy(row_ptr, m->row_ptr.data(), sizeof(int) * (m->n + 1));

@@ -99,6 +99,7 @@ _sig("pfc_mesh_create_p1", C.c_int, [C.c_int, C.c_int, C.c_int, _ip, _dp, C.POIN
 _sig("pfc_mesh_create_p2", C.c_int, [C.c_int, C.c_int, C.c_int, _ip, _dp, C.POINTER(_vp)])
 _sig("pfc_mesh_create_csr", C.c_int, [C.c_int, C.c_int, C.c_int, _ip, _ip, _dp, _dp, C.c_int, _ip, _dp, C.POINTER(_vp)])
 _sig("pfc_mesh_query", C.c_int, [_vp, _ip, _ip, _ip, _ip])
+_sig("pfc_mesh_grid_side", C.c_int, [_vp, _ip])
 _sig("pfc_mesh_export_csr", C.c_int, [_vp, _ip, _ip, _dp, _dp])
 _sig("pfc_mesh_destroy", None, [_vp])
 _sig("pfc_spmv", C.c_int, [_vp, C.c_int, _vp, _vp, _vp])
@@ -134,7 +135,7 @@ _sig("pfc_server_destroy", None, [_vp])
 # every symbol declared in include/pfc.h
 DECLARED = [
     "pfc_status_str", "pfc_last_error", "pfc_opts_default", "pfc_tau_critical", "pfc_mesh_create_p1", "pfc_mesh_create_p2",
-    "pfc_mesh_create_csr", "pfc_mesh_query", "pfc_mesh_export_csr", "pfc_mesh_destroy", "pfc_spmv",
+    "pfc_mesh_create_csr", "pfc_mesh_query", "pfc_mesh_grid_side", "pfc_mesh_export_csr", "pfc_mesh_destroy", "pfc_spmv",
     "pfc_assemble_N", "pfc_load_psi3", "pfc_instance_footprint", "pfc_instance_create", "pfc_instance_destroy",
     "pfc_solve", "pfc_solve_x", "pfc_last_inner_counts", "pfc_instance_launch_stats", "pfc_rosenbrock_run",
     "pfc_rosenbrock_adaptive", "pfc_apply_AR", "pfc_apply_AR_x", "pfc_apply_pch", "pfc_stage_rhs",
@@ -253,6 +254,12 @@ def pfc_mesh_query(mesh):
     d, n, z, e = C.c_int(), C.c_int(), C.c_int(), C.c_int()
     _check(_lib.pfc_mesh_query(mesh, C.byref(d), C.byref(n), C.byref(z), C.byref(e)), "pfc_mesh_query")
     return dict(dim=d.value, n=n.value, nnz=z.value, n_elem=e.value)
+
+
+def pfc_mesh_grid_side(mesh) -> int:
+    N = C.c_int()
+    _check(_lib.pfc_mesh_grid_side(mesh, C.byref(N)), "pfc_mesh_grid_side")
+    return N.value
 
 
 def pfc_mesh_export_csr(mesh):

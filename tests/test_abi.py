@@ -97,6 +97,11 @@ def test_null_handles_rejected(pfc):
     assert pfc._lib.pfc_instance_create(None, C.byref(o), C.byref(v)) == pfc.PFC_ERR_ARG
     assert pfc._lib.pfc_batch_run(None, 0, None, None, None, None, 1, 0, None, None) == pfc.PFC_ERR_ARG
     assert pfc._lib.pfc_spmv(None, 0, None, None, None) == pfc.PFC_ERR_ARG
+    assert pfc._lib.pfc_mesh_grid_side(None, None) == pfc.PFC_ERR_ARG
+    # the grid_columns option takes 0 or 1
+    o = pfc.pfc_opts_default(grid_columns=2)
+    assert pfc.pfc_opts_default().grid_columns == 1
+    assert pfc._lib.pfc_instance_footprint(C.c_void_p(1), C.byref(o)) == 0
 
 
 def test_product_path_does_not_import_oracle():

@@ -28,6 +28,7 @@ def test_p2_assembly_N_and_load(pfc, dim, N, jit):
     P = Problem(dim, N, jit, amp=0.3, seed=31, degree=2)
     try:
         m = P.gpu_mesh()
+        assert pfc.pfc_mesh_grid_side(m) == 0   # P2 rows differ in width: columns stay stored
         rp, ci, mv, kv = pfc.pfc_mesh_export_csr(m)
         assert np.array_equal(rp, P.M.indptr) and np.array_equal(ci, P.M.indices)
         assert np.abs(mv - P.M.data).max() <= 1e-13 * np.abs(P.M.data).max()

@@ -309,6 +309,7 @@ def test_column_forms_agree_bitwise(pfc, dim, N, jit, prec):
         r, psibar, tau = -0.35, -0.3, 0.5
         n = P.n
         _, b = _stage1(P, r, tau)
+        assert pfc.pfc_mesh_grid_side(P.gpu_mesh()) == N
         out = []
         for g in (1, 0):
             inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(precision=prec, grid_columns=g))
