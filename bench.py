@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # was taken on: when their digest differs, `traffic` is reported as null.
 TRAFFIC = {
     # workload: (sha256 of the kernel sources, bytes per launch, algorithmic bytes per launch of the same run)
-    "pfc2d_512_fp64": ("1da4003d8227d5af273d26bf430857cad7eae3a696b47dbe2409e9c598084cff", 40410135.0, 37986008.0),
-    "pfc3d_64_mixed": ("1da4003d8227d5af273d26bf430857cad7eae3a696b47dbe2409e9c598084cff", 46155546.0, 37670502.0),
+    "pfc2d_512_fp64": ("0209158a9ce9df87c0519a9e65bc6c39ac43e4dccb0764dc5bae5fd28718cee3", 34214199.0, 37986008.0),
+    "pfc3d_64_mixed": ("0209158a9ce9df87c0519a9e65bc6c39ac43e4dccb0764dc5bae5fd28718cee3", 30400910.0, 37670502.0),
 }
 
 
