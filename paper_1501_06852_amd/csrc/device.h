@@ -43,8 +43,8 @@ struct PatView {
   int uw;           // uniform slice width, or 0
   int lo;           // SELL position of pfc_lcol[0] (L == PFC_COL_LDS)
   int n, gN;        // grid columns (L == PFC_COL_GRID): grid_col with
-  float gInv;       //   1/N and the displacement table gd
-  const unsigned char* gd;
+  float gInv;       //   1/N and the offset table gd
+  const int* gd;
   __device__ __forceinline__ int base(int sl) const {
     if constexpr (L != PFC_COL_MEM) return sl * 64 * uw;
     else return uw ? sl * 64 * uw : sp[sl];
@@ -65,7 +65,7 @@ struct PatView {
 template <int L>
 __device__ __forceinline__ PatView<L> p1_pat(const InstDev& I, const Team& tm) {
   return PatView<L>{I.m.slice_ptr, I.m.col, I.m.uw, tm.lo, I.n, I.m.gN, I.m.gInv,
-                    L == PFC_COL_GRID ? I.m.gord : nullptr};
+                    L == PFC_COL_GRID ? I.m.glin : nullptr};
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -531,7 +531,7 @@ template <int L, typename T>
 __device__ __forceinline__ PatView<L> op_pat(const InstDev& I, const PcgOps<T>& o, const Team& tm) {
   // (the S_D pattern is only ever read with L == PFC_COL_MEM)
   return PatView<L>{o.sp, o.colp, o.sp == I.m.slice_ptr ? I.m.uw : 0, tm.lo, I.n, I.m.gN, I.m.gInv,
-                    L == PFC_COL_GRID ? I.m.gord : nullptr};
+                    L == PFC_COL_GRID ? I.m.glin : nullptr};
 }
 
 template <typename T>

@@ -252,12 +252,11 @@ static int slot_of(const pfc_mesh* m, int row, int col) {
 // pattern in m->row_ptr / m->col_idx.
 // Whether the columns of the mesh's (sorted) rows follow from grid_col: the
 // mesh is a periodic grid of side N (n = N^dim < 2^22, nodes numbered
-// x + N (y + N z)), every row has w entries, every neighbour lies at most one
-// step away per direction, and rows of one edge class (grid_edge per
-// direction) order their neighbours alike.  The displacement table of a class
-// is read off its first row; every row, that one included, is then checked
-// entry by entry against grid_col.
-static bool detect_grid(const pfc_mesh* m, int w, int& gN, std::vector<unsigned char>& gord) {
+// x + N (y + N z)), every row has w entries, and rows of one edge class
+// (grid_class) have the same column offsets j - i.  The offsets of a class are
+// read off its first row; every row, that one included, is then checked entry
+// by entry against grid_col.
+static bool detect_grid(const pfc_mesh* m, int w, int& gN, std::vector<int>& glin) {
   const int n = m->n, dim = m->dim;
   const int N = (int)std::llround(std::pow((double)n, 1.0 / dim));
   long long p = 1;
@@ -266,31 +265,17 @@ static bool detect_grid(const pfc_mesh* m, int w, int& gN, std::vector<unsigned 
   for (int i = 0; i < n; ++i)
     if (m->row_ptr[i + 1] - m->row_ptr[i] != w) return false;
   const float inv = 1.0f / (float)N;
-  auto coords = [&](int v, int c[3]) { c[0] = v % N; c[1] = (v / N) % N; c[2] = v / N / N; };
-  auto step = [&](int a) { a %= N; if (a < 0) a += N; return a == 0 ? 0 : (a == 1 ? 1 : (a == N - 1 ? -1 : 9)); };
-  gord.assign((size_t)PFC_GRID_CLASSES * PFC_GRID_W, 0);
+  glin.assign((size_t)PFC_GRID_CLASSES * PFC_GRID_W, 0);
   std::vector<char> have(PFC_GRID_CLASSES, 0);
   for (int i = 0; i < n; ++i) {
-    int ci[3];
-    coords(i, ci);
-    const int cls = grid_edge(ci[0], N) + 3 * grid_edge(ci[1], N) + 9 * grid_edge(ci[2], N);
+    const int cls = grid_class(i, N, inv);
     const int* col = m->col_idx.data() + m->row_ptr[i];
     if (!have[cls]) {
-      for (int k = 0; k < w; ++k) {
-        int cj[3];
-        coords(col[k], cj);
-        int packed = 0;
-        for (int c = 0; c < 3; ++c) {
-          const int d = step(cj[c] - ci[c]);
-          if (d > 1) return false;
-          packed |= (d + 1) << (2 * c);
-        }
-        gord[(size_t)cls * PFC_GRID_W + k] = (unsigned char)packed;
-      }
+      for (int k = 0; k < w; ++k) glin[(size_t)cls * PFC_GRID_W + k] = col[k] - i;
       have[cls] = 1;
     }
     for (int k = 0; k < w; ++k)
-      if (grid_col(i, k, n, N, inv, gord.data()) != col[k]) return false;
+      if (grid_col(i, k, n, N, inv, glin.data()) != col[k]) return false;
   }
   gN = N;
   return true;
@@ -326,9 +311,9 @@ static int finish_layout(pfc_mesh* m, const int32_t* en, const std::vector<int>&
   }
   // periodic grids: the kernels can compute the columns (grid_col)
   int gN = 0;
-  std::vector<unsigned char> gord;
+  std::vector<int> glin;
 #ifndef PFC_NO_GRID_COLUMNS
-  if (m->uniform_width > 0 && !detect_grid(m, m->uniform_width, gN, gord)) gN = 0;
+  if (m->uniform_width > 0 && !detect_grid(m, m->uniform_width, gN, glin)) gN = 0;
 #endif
   std::vector<int> scol((size_t)m->nnz_sell);
   m->csr2sell.assign(m->nnz, 0);
@@ -397,8 +382,8 @@ static int finish_layout(pfc_mesh* m, const int32_t* en, const std::vector<int>&
   d.degree = m->degree; d.nloc = m->nloc;
   d.gN = gN;
   d.gInv = gN ? 1.0f / (float)gN : 0.0f;
-  std::memset(d.gord, 0, sizeof(d.gord));
-  if (gN) std::memcpy(d.gord, gord.data(), sizeof(d.gord));
+  std::memset(d.glin, 0, sizeof(d.glin));
+  if (gN) std::memcpy(d.glin, glin.data(), sizeof(d.glin));
   d.nd_el_ptr = m->d_nd_el_ptr; d.nd_el = m->d_nd_el; d.elem_nodes = m->d_elem_nodes; d.elem_vol = m->d_vol;
   return PFC_OK;
 }

@@ -52,33 +52,31 @@ enum { JOB_NONE = 0, JOB_SOLVE = 1, JOB_RB = 2, JOB_PCH = 3 };
 enum { KIND_Y0 = 0, KIND_Y1 = 1, KIND_Z = 2, KIND_X1 = 3, KIND_X2 = 4, KIND_CI_OMEGA = 5, KIND_CI_MU = 6, KIND_SD = 7 };
 // step (3) with the diagonal-mass Schur approximation S_D replaces (3.1), (3.2)
 
-// Periodic grid meshes: n = N^dim nodes numbered x + N (y + N z) whose
-// neighbours all lie at most one step away in each direction (modulo N).  The
-// column of entry k of row i is then computed, not loaded: the stored entries
-// of a row are its columns in ascending order, and that order depends only on
+// Periodic grid meshes: n = N^dim nodes numbered x + N (y + N z) whose rows
+// all have the same length.  The stored entries of a row are its columns in
+// ascending order; when the offsets j - i of those columns depend only on
 // whether the row lies on the low edge, inside or on the high edge in each
-// direction (27 row classes), so gord[class][k] holds the displacement of
-// entry k, packed as (dx + 1) | (dy + 1) << 2 | (dz + 1) << 4.  Rows past n
-// (padding of the last slice) count as row n - 1.  The host checks that this
-// function reproduces every stored column before it enables the form.
+// direction (27 row classes; true for stencils of one step per direction),
+// glin[class][k] holds the offset of entry k and the kernel computes the
+// column instead of loading it.  Rows past n (padding of the last slice) count
+// as row n - 1.  The host checks that this function reproduces every stored
+// column before it enables the form.
 #define PFC_GRID_W 16
 #define PFC_GRID_CLASSES 27
 #define PFC_GRID_MAXN (1 << 22)
-__host__ __device__ __forceinline__ int grid_wrap(int v, int N) { return v < 0 ? v + N : (v >= N ? v - N : v); }
 // floor(v / N) for 0 <= v < 2^22 with inv = float(1/N): (v + 1/2) / N lies at
 // least 1/(2N) from an integer, and the two roundings err by less than that
 __host__ __device__ __forceinline__ int grid_div(int v, float inv) { return (int)(((float)v + 0.5f) * inv); }
 __host__ __device__ __forceinline__ int grid_edge(int v, int N) { return v == 0 ? 0 : (v == N - 1 ? 2 : 1); }
-// (one formula for both dimensions: in 2D, t = y < N gives z = 0, and every
-// displacement has dz = 0)
-__host__ __device__ __forceinline__ int grid_col(int i, int k, int n, int N, float inv, const unsigned char* gord) {
-  const int r = i < n ? i : n - 1;
+// edge class of row i (in 2D, t = y < N gives z = 0)
+__host__ __device__ __forceinline__ int grid_class(int r, int N, float inv) {
   const int t = grid_div(r, inv), x = r - t * N;
   const int z = grid_div(t, inv), y = t - z * N;
-  const int c = grid_edge(x, N) + 3 * grid_edge(y, N) + 9 * grid_edge(z, N);
-  const int d = gord[c * PFC_GRID_W + k];
-  return grid_wrap(x + (d & 3) - 1, N) +
-         N * (grid_wrap(y + ((d >> 2) & 3) - 1, N) + N * grid_wrap(z + ((d >> 4) & 3) - 1, N));
+  return grid_edge(x, N) + 3 * grid_edge(y, N) + 9 * grid_edge(z, N);
+}
+__host__ __device__ __forceinline__ int grid_col(int i, int k, int n, int N, float inv, const int* glin) {
+  const int r = i < n ? i : n - 1;
+  return r + glin[grid_class(r, N, inv) * PFC_GRID_W + k];
 }
 
 struct MeshDev {
@@ -88,7 +86,7 @@ struct MeshDev {
   int degree, nloc;       // Lagrange degree (1, 2) and nodes per element
   int gN;                 // periodic grid side N (grid_col), or 0
   float gInv;             // float(1 / N)
-  unsigned char gord[PFC_GRID_CLASSES * PFC_GRID_W];  // entry displacements per row class (grid_col)
+  int glin[PFC_GRID_CLASSES * PFC_GRID_W];  // column offset of each entry per row class (grid_col)
   const double* p2_M2;    // P2 reference tables (divided by |T|): M2[a][b],
   const double* p2_D;     //   D[i][j][a][b] = int d_i phi_a d_j phi_b (i, j barycentric),
   const double* p2_C4;    //   C4[a][b][c][d] = int phi_a phi_b phi_c phi_d
