@@ -112,8 +112,9 @@ typedef struct pfc_server pfc_server;
  *                 per direction) the solver kernel computes the column of each
  *                 stored entry from its row instead of reading it; same
  *                 columns in the same order, so the same results bit for bit.
- *                 0: always read the stored columns.  Used only when every
- *                 thread of the instance's team owns one row. */
+ *                 0: always read the stored columns.  A launch that serves
+ *                 several instances computes the columns only when all of
+ *                 them allow it and all their meshes are such grids. */
 typedef struct pfc_opts {
     int struct_size;
     int precision;

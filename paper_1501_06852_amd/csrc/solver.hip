@@ -801,11 +801,11 @@ int Group::build(hipStream_t capture, int precision, int ticks) {
   // (measured: 3D 64^3 mixed +5.7%, the mixed 2D/3D served mix +6%, 2D 512^2
   // float64 -2%, where the 7 columns are 16% of an iteration's bytes), so
   // float64 runs stage only from 8 columns per row on (3D: 22%).  When every
-  // mesh of the launch is a periodic grid (MeshDev::gN) and every thread owns
-  // one row, the columns are computed from the row instead and no column
-  // stream is read at all (2D 512^2 float64 +8.8%, 3D 64^3 mixed +3.4%, the
-  // served mix +5.7%; with 4 rows per thread, the batched 128^2 mixed run,
-  // -1.7%, so teams with several rows per thread keep the other forms).
+  // mesh of the launch is a periodic grid (MeshDev::gN), the columns are
+  // computed from the row instead and no column stream is read at all
+  // (measured against the stored forms: 2D 512^2 float64 +8.7%, 3D 64^3 mixed
+  // +17%, the served mix +11%, the batched 128^2 mixed run with 4 rows per
+  // thread +5.5%).
   bool lds = true, grid = true;
   for (TeamEntry& t : h_teams) {
     const MeshDev& m = h_descs[t.inst].m;
@@ -814,8 +814,7 @@ int Group::build(hipStream_t capture, int precision, int ticks) {
     t.n_slices = m.n_slices;
     if (!(m.uw >= 1 && m.uw <= PFC_LCOL_W && (m.n_slices + t.size - 1) / t.size <= PFC_WAVES)) lds = false;
     if (precision == PFC_FP64 && m.uw < 8) lds = false;
-    if (!(m.gN > 0 && m.uw >= 1 && (m.n_slices + t.size - 1) / t.size <= PFC_WAVES) || !h_descs[t.inst].grid_cols)
-      grid = false;
+    if (!(m.gN > 0 && m.uw >= 1) || !h_descs[t.inst].grid_cols) grid = false;
   }
 #ifdef PFC_NO_COLUMN_STAGING
   lds = false;

@@ -297,10 +297,12 @@ def test_schur_D_variant_parity(pfc, dim, N, jit, tau, prec):
 
 
 # 2D float64 reads the columns from memory, 3D float64 and mixed runs stage them in
-# LDS; the 3D 24^3 case spans several workgroups with a ragged last one
-@pytest.mark.parametrize("dim,N,jit,prec", [(2, 16, 0.2, 0), (3, 5, 0.2, 0), (3, 6, 0.1, 1), (2, 24, 0.2, 1),
-                                            (3, 24, 0.1, 0)])
-def test_column_forms_agree_bitwise(pfc, dim, N, jit, prec):
+# LDS; the 3D 24^3 cases span several workgroups with a ragged last one; with 4
+# rows per thread every form reads the stored columns from memory
+@pytest.mark.parametrize("dim,N,jit,prec,rpt", [(2, 16, 0.2, 0, 1), (3, 5, 0.2, 0, 1), (3, 6, 0.1, 1, 1),
+                                                (2, 24, 0.2, 1, 1), (3, 24, 0.1, 0, 1), (2, 40, 0.2, 1, 4),
+                                                (3, 24, 0.1, 0, 4)])
+def test_column_forms_agree_bitwise(pfc, dim, N, jit, prec, rpt):
     """On periodic grids the kernel computes the columns (grid_columns = 1): the same columns in the
     same order as the stored ones, so a stage solve and a Rosenbrock step give the same bits."""
     P = Problem(dim, N, jit, seed=61)
@@ -312,7 +314,8 @@ def test_column_forms_agree_bitwise(pfc, dim, N, jit, prec):
         assert pfc.pfc_mesh_grid_side(P.gpu_mesh()) == N
         out = []
         for g in (1, 0):
-            inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(precision=prec, grid_columns=g))
+            inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(precision=prec, grid_columns=g,
+                                                                              rows_per_thread=rpt))
             insts.append(inst)
             x = dev(np.zeros(3 * n))
             st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
