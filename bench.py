@@ -184,7 +184,7 @@ def bench_served(args, torch, wl, pfc):
         meshes.append((m, pfc.pfc_mesh_create_p1(dim, m.n, m.elem_nodes, m.elem_coords)))
     nreq = args.requests
     steps = args.req_steps
-    rpt = 1 if args.rows_per_thread is None else args.rows_per_thread
+    rpt = 0 if args.rows_per_thread is None else args.rows_per_thread   # 0: chosen per request by load
 
     def stream(rate):
         return wl.served_stream(nreq, rate, 4242)
@@ -274,7 +274,7 @@ def main():
     ap.add_argument("--req-steps", type=int, default=5)
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--rows-per-thread", type=int, default=None,
-                    help="rows per thread of the batched (default 4) and served mixed (default 1) instances")
+                    help="rows per thread of the batched (default 4) and served mixed (default 0: by load) instances")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1"}))

@@ -370,9 +370,13 @@ int pfc_batch_run(pfc_instance* const* insts, int count, double* const* states,
  *   max_slots   maximum number of concurrently active requests
  *   precision   PFC_FP64 or PFC_MIXED
  *   ticks_per_graph  as in pfc_opts (0: default)
- *   rows_per_thread  rows per thread of the request instances (0: one); more
- *               rows per thread give each request fewer, longer workgroups,
- *               which raises throughput when many requests share the GPU
+ *   rows_per_thread  rows per thread of the request instances, 1..8, or 0
+ *               (the default): chosen per request at admission, one row per
+ *               thread while the active requests and the new one fit into one
+ *               round of resident workgroups (CUs x 1024 rows), two beyond.
+ *               More rows per thread give each request fewer, longer
+ *               workgroups: more throughput when many requests share the GPU,
+ *               longer solves when few do.
  *   n_steps ... Rosenbrock steps per request (set per request) */
 typedef struct pfc_server_opts {
     int struct_size;

@@ -60,33 +60,47 @@ struct pfc_server {
   Group grp;
   std::chrono::steady_clock::time_point t0;
   int error = PFC_OK;
+  long long resident_rows = 0;  // rows one round of resident workgroups covers (CUs x workgroup size)
   std::string error_msg;  // pfc_last_error() of the server thread at the error
   double clock() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
 };
 
 namespace {
 
-pfc_opts server_instance_opts(const pfc_server* S) {
+pfc_opts server_instance_opts(const pfc_server* S, int rpt) {
   pfc_opts o;
   pfc_opts_default(&o);
   o.precision = S->o.precision;
   o.ticks_per_graph = S->o.ticks_per_graph;
-  o.rows_per_thread = S->o.rows_per_thread;
+  o.rows_per_thread = rpt;
   return o;
+}
+
+// Rows per thread of a request's instance.  Fixed by the server options, or
+// (0) chosen at admission from the load: one row per thread while the active
+// requests and this one fit into one round of resident workgroups (the
+// shortest time per request), two once they do not (fewer, longer
+// workgroups: more throughput when the GPU is full).
+int choose_rpt(const pfc_server* S, const Request* q) {
+  if (S->o.rows_per_thread > 0) return S->o.rows_per_thread;
+  long long rows = q->mesh->n;
+  for (const Request* a : S->active) rows += a->mesh->n;
+  return rows > S->resident_rows ? 2 : 1;
 }
 
 // take an instance for req: reuse a pooled one on the same mesh, else create
 // one within the budget (evicting pooled instances if needed)
 int acquire(pfc_server* S, Request* q, bool& ok) {
   ok = false;
+  const int rpt = choose_rpt(S, q);
   for (size_t k = 0; k < S->pool.size(); ++k)
-    if (S->pool[k]->mesh == q->mesh) {
+    if (S->pool[k]->mesh == q->mesh && S->pool[k]->opts.rows_per_thread == rpt) {
       q->inst = S->pool[k];
       S->pool.erase(S->pool.begin() + k);
       ok = true;
       return PFC_OK;
     }
-  pfc_opts o = server_instance_opts(S);
+  pfc_opts o = server_instance_opts(S, rpt);
   const size_t need = pfc_instance_footprint(q->mesh, &o);
   while (S->used + need > S->o.hbm_budget && !S->pool.empty()) {
     pfc_instance* v = S->pool.back();
@@ -277,11 +291,15 @@ int pfc_server_create(const pfc_server_opts* o, pfc_server** out) {
   pfc_server* S = new pfc_server();
   S->o = *o;
   S->t0 = std::chrono::steady_clock::now();
-  if (hipGetDevice(&S->device) != hipSuccess || hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+  int cus = 0;
+  if (hipGetDevice(&S->device) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device) != hipSuccess ||
+      hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
     delete S;
     set_error("pfc_server_create: HIP setup failed");
     return PFC_ERR_HIP;
   }
+  S->resident_rows = (long long)cus * PFC_WG;
   S->th = std::thread(loop, S);
   *out = S;
   return PFC_OK;
@@ -294,7 +312,7 @@ int pfc_server_submit(pfc_server* S, pfc_mesh* mesh, double r, double psibar, do
     set_error("pfc_server_submit: invalid arguments");
     return PFC_ERR_ARG;
   }
-  pfc_opts o = server_instance_opts(S);
+  pfc_opts o = server_instance_opts(S, 1);  // the largest team: an upper bound of the footprint
   if (n_steps > o.max_run_steps) { set_error("pfc_server_submit: too many steps"); return PFC_ERR_ARG; }
   if (pfc_instance_footprint(mesh, &o) > S->o.hbm_budget) {
     set_error("pfc_server_submit: request footprint exceeds the server's memory budget");
