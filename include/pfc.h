@@ -83,7 +83,7 @@ typedef struct pfc_server pfc_server;
  *   shared_ops    0: store M + delta K and M + sqrt(delta) K per instance;
  *                 1: form them on the fly from the mesh's M and K (less memory,
  *                 more bytes per iteration; useful when many instances share a mesh)
- *   rows_per_thread  rows of the mesh handled per thread in each phase (1..8, 0 = auto)
+ *   rows_per_thread  rows of the mesh handled per thread in each phase (1..8; 0 means 1)
  *   max_run_steps capacity of per-stage info records of a Rosenbrock run (steps)
  *   ticks_per_graph  solver phases captured per replayed graph (0 = auto)
  *   single_reduction 0: inner PCG in the standard form (two reductions, two
