@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # was taken on: when their digest differs, `traffic` is reported as null.
 TRAFFIC = {
     # workload: (sha256 of the kernel sources, bytes per launch, algorithmic bytes per launch of the same run)
-    "pfc2d_512_fp64": ("655dbdb8cd8433525c10fc40d155b6016c4ecf3e9559655b2c402bc163597ca9", 34197123.0, 37986008.0),
-    "pfc3d_64_mixed": ("655dbdb8cd8433525c10fc40d155b6016c4ecf3e9559655b2c402bc163597ca9", 30406670.0, 37670502.0),
+    "pfc2d_512_fp64": ("e5fc217eb8cfd4c04efc203bb5e98d57740c47fd390056a3efd956647d0b21be", 34197114.0, 37986008.0),
+    "pfc3d_64_mixed": ("e5fc217eb8cfd4c04efc203bb5e98d57740c47fd390056a3efd956647d0b21be", 30416020.0, 37670502.0),
 }
 
 
