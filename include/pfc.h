@@ -68,6 +68,7 @@ enum { PFC_FP64 = 0, PFC_MIXED = 1 };
 enum { PFC_INIT_GIVEN = 0, PFC_INIT_CONSISTENT = 1 };
 enum { PFC_OP_M = 0, PFC_OP_K = 1 };
 enum { PFC_MODEL_PFC2 = 0, PFC_MODEL_PFC1 = 1 };
+enum { PFC_GAMMA_SCALE_ROW = 0, PFC_GAMMA_LITERAL = 1 };
 
 typedef struct pfc_mesh pfc_mesh;
 typedef struct pfc_instance pfc_instance;
@@ -114,7 +115,20 @@ typedef struct pfc_server pfc_server;
  *                 columns in the same order, so the same results bit for bit.
  *                 0: always read the stored columns.  A launch that serves
  *                 several instances computes the columns only when all of
- *                 them allow it and all their meshes are such grids. */
+ *                 them allow it and all their meshes are such grids.
+ *   gamma_mode    how the preconditioner meets the factor m11 of block (1,1)
+ *                 (the paper derives P for m11 = 1 and uses it unchanged):
+ *                 PFC_GAMMA_SCALE_ROW (default): block row 1 of A^R and b is
+ *                 multiplied by 1/m11, which gives [tau/m11 K, M, 0], and P_CH
+ *                 is built for tau_s = tau/m11; the solution is unchanged and
+ *                 the first block column matches the one P was derived for.
+ *                 PFC_GAMMA_LITERAL: the unscaled system with P_CH(tau).
+ *                 Both coincide for m11 = 1.  Residuals are reported for the
+ *                 unscaled system either way.
+ *   inner_fixed   iteration counts of the five inner solves (1), (2), (3.1),
+ *                 (3.2), (5) of every preconditioner application; 0 (the
+ *                 default) runs that solve to inner_tol.  With S_D, entry 2 is
+ *                 the S_D solve (overrides sd_iters) and entry 3 is unused. */
 typedef struct pfc_opts {
     int struct_size;
     int precision;
@@ -133,6 +147,8 @@ typedef struct pfc_opts {
     int model;
     double psi_min;
     int grid_columns;
+    int gamma_mode;
+    int inner_fixed[5];
     int reserved;
 } pfc_opts;
 

@@ -55,10 +55,13 @@ class InnerSolvers:
     mode 'exact': sparse LU of M, M + delta K, M + sqrt(delta) K.
     mode 'pcg'  : Jacobi PCG, tol relative (1e-3 in the paper), maxit cap;
                   records the counts of every apply; with `replay_counts`
-                  (list of 5-lists) runs exactly those counts.
+                  (list of 5-lists) runs exactly those counts; with
+                  `fixed_counts` (one 5-list) every apply runs those counts
+                  where they are positive.
     """
 
-    def __init__(self, M, K, tau, mode="pcg", tol=1e-3, maxit=500, replay_counts=None, schur="CH", sd_iters=20):
+    def __init__(self, M, K, tau, mode="pcg", tol=1e-3, maxit=500, replay_counts=None, schur="CH", sd_iters=20,
+                 fixed_counts=None):
         self.M, self.K = M, K
         self.tau = tau
         self.delta = math.sqrt(tau)
@@ -71,6 +74,7 @@ class InnerSolvers:
         self.mode = mode
         self.tol, self.maxit = tol, maxit
         self.replay = replay_counts
+        self.fixed_counts = fixed_counts  # per step: a fixed iteration count, or 0 for the tolerance
         self.counts: list[list[int]] = []
         self._cur: list[int] = []
         if mode == "exact":
@@ -92,6 +96,8 @@ class InnerSolvers:
         fixed = None
         if which_mat == 3:
             fixed = self.sd_iters  # Table inner_solvers: S_D is solved with a fixed iteration count
+        if self.fixed_counts is not None and self.fixed_counts[step] > 0:
+            fixed = self.fixed_counts[step]
         if self.replay is not None:
             fixed = self.replay[len(self.counts)][step]
         x, it = pcg(lambda v: A @ v, rhs, self.dinv[which_mat], self.tol, self.maxit, fixed)

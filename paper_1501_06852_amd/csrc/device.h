@@ -427,14 +427,14 @@ __device__ __forceinline__ void stage_rhs_row(const InstDev& I, const PatView<L>
 }
 
 // Right-hand side of the solve: stage rhs b_i^R for job RB, the caller's rhs
-// for job SOLVE.  Writes W = b with block 1 divided by m11, X = 0.
+// for job SOLVE.  Writes W = b with block 1 multiplied by rs, X = 0.
 template <int L>
 __device__ __forceinline__ Red3 ph_solve_init(const InstDev& I, const State& S, const Team& tm) {
   const int n = I.n;
   const bool rb = (S.job == JOB_RB);
   const PatView<L> pv = p1_pat<L>(I, tm);
   double* X = rb ? (I.ys + (long long)(S.stage - 1) * 3 * n) : I.x_user;
-  const double im = 1.0 / I.m11;
+  const double im = I.rs;
   double a0 = 0.0, a1 = 0.0;
   PFC_SLICES(I, tm) {
     const int i = sl * 64 + tm.lane;
@@ -739,7 +739,7 @@ __device__ __forceinline__ Red3 ph_aspmv(const InstDev& I, const State& S, const
   PFC_SLICES(I, tm) {
     const int i = sl * 64 + tm.lane;
     double w0, w1, w2;
-    block_row<L, MOB>(I, pv, sl, tm.lane, I.tau_s, 1.0,
+    block_row<L, MOB>(I, pv, sl, tm.lane, I.tau_s, I.m11_s,
               [&](int j, double& mu, double& ps, double& om) { mu = Zj[j]; ps = Zj[n + j]; om = (double)x2[j]; },
               w0, w1, w2);
     if (i < n) {
@@ -801,7 +801,7 @@ __device__ __forceinline__ Red3 ph_true_res(const InstDev& I, const State& S, co
   const bool rb = (S.job == JOB_RB);
   const double* X = rb ? (I.ys + (long long)(S.stage - 1) * n3) : I.x_user;
   const double* bsrc = rb ? I.b : I.b_user;
-  const double im = 1.0 / I.m11;
+  const double im = I.rs;
   double a0 = 0.0, a1 = 0.0;
   PFC_SLICES(I, tm) {
     const int i = sl * 64 + tm.lane;

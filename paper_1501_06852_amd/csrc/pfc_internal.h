@@ -155,10 +155,13 @@ struct InstDev {
   int inner_maxit, shared_ops, team_size, replay;
   int single_reduction, schur_d;
   int sd_iters, model;          // model: PFC_MODEL_PFC2 / PFC_MODEL_PFC1
-  int grid_cols, pad_gc;        // grid_columns option (launch form PFC_COL_GRID allowed)
+  int grid_cols, gamma_mode;    // grid_columns and gamma_mode options
+  int inner_fixed[5], pad_if;   // fixed inner iteration counts (0: to inner_tol)
   double outer_tol, inner_tol, ci_tol;
   // job parameters; tau_p = m0 tau_s is the preconditioner's time step
-  double r, tau, m11, tau_s, delta, sdelta;
+  // rs: factor of block row 1 in the system FGMRES works on (1/m11 for
+  // PFC_GAMMA_SCALE_ROW, 1 for PFC_GAMMA_LITERAL); tau_s = rs tau, m11_s = rs m11
+  double r, tau, m11, tau_s, delta, sdelta, rs, m11_s;
   double psi_min, m0, tau_p;
   int job, n_steps, init_mode, max_infos;
   // typed operator arrays (float or double by precision)

@@ -51,6 +51,7 @@ __device__ __forceinline__ int inner_limit(const InstDev& I, const State& S, boo
     if (S.apply >= meta[3]) return 0;
     return I.sched_inner[(long long)(meta[2] + S.apply) * 5 + count_slot(S.kind)];
   }
+  if (I.inner_fixed[count_slot(S.kind)] > 0) { fixed = true; return I.inner_fixed[count_slot(S.kind)]; }
   if (S.kind == KIND_SD) { fixed = true; return I.sd_iters; }  // Table inner_solvers: fixed count for S_D
   fixed = false;
   return I.inner_maxit;
@@ -93,7 +94,7 @@ __device__ void begin_solve(State& S, const InstDev& I, bool wr, Red3 red) {
   if (!isfinite(S.bnorm)) { finish_solve(S, I, wr, PFC_ERR_BREAKDOWN); return; }
   if (S.bnorm == 0.0) { finish_solve(S, I, wr, PFC_OK); return; }
   if (I.replay && I.sched_meta[4 * solve_index(S) + 1] == 0) { finish_solve(S, I, wr, PFC_OK); return; }
-  S.est_thresh = I.outer_tol * S.bnorm / fmax(1.0, I.m11);
+  S.est_thresh = I.gamma_mode == PFC_GAMMA_LITERAL ? I.outer_tol * S.bnorm : I.outer_tol * S.bnorm / fmax(1.0, I.m11);
   if (wr) I.hist->gpre[0] = S.bnorm_s;
   S.vscale = 1.0 / S.bnorm_s;
   S.kind = KIND_Y0;
@@ -204,7 +205,8 @@ __device__ void givens(State& S, const InstDev& I, bool wr, double hn2, double* 
 // transition below is out of line and its code is fetched only when needed).
 // Same decisions and arithmetic as the PH_CG_ITER case of transition().
 __device__ __forceinline__ bool cg_iter_continues(State& S, const InstDev& I, Red3 red) {
-  if (S.phase != PH_CG_ITER || I.replay || S.kind == KIND_SD || is_ci(S.kind)) return false;
+  if (S.phase != PH_CG_ITER || I.replay || S.kind == KIND_SD || is_ci(S.kind) || I.inner_fixed[count_slot(S.kind)] > 0)
+    return false;
   const int it = S.it + 1;
   const double g = red.a, dl = red.b, rr = red.c;
   const double tol = I.inner_tol;
@@ -765,6 +767,15 @@ static int validate_opts(const pfc_opts* o) {
   if (o->model != PFC_MODEL_PFC2 && o->model != PFC_MODEL_PFC1) { set_error("pfc_opts: bad model"); return PFC_ERR_ARG; }
   if (!std::isfinite(o->psi_min)) { set_error("pfc_opts: psi_min must be finite"); return PFC_ERR_ARG; }
   if (o->grid_columns != 0 && o->grid_columns != 1) { set_error("pfc_opts: grid_columns must be 0 or 1"); return PFC_ERR_ARG; }
+  if (o->gamma_mode != PFC_GAMMA_SCALE_ROW && o->gamma_mode != PFC_GAMMA_LITERAL) {
+    set_error("pfc_opts: bad gamma_mode");
+    return PFC_ERR_ARG;
+  }
+  for (int k = 0; k < 5; ++k)
+    if (o->inner_fixed[k] < 0 || o->inner_fixed[k] > 100000) {
+      set_error("pfc_opts: inner_fixed counts must be in 0..100000");
+      return PFC_ERR_ARG;
+    }
   return PFC_OK;
 }
 
@@ -957,11 +968,16 @@ static int prep_ops(pfc_instance* I, hipStream_t s) {
 
 int prep_ops_public(pfc_instance* I, hipStream_t s) { return prep_ops(I, s); }
 
-// h.m0 (mobility mean, 1 for PFC2) must be current: the preconditioner is
-// built for the time step tau_p = m0 tau / m11
+// h.m0 (mobility mean, 1 for PFC2) and h.gamma_mode must be current: FGMRES
+// sees block row 1 multiplied by rs, and the preconditioner is built for the
+// time step tau_p = m0 rs tau
 void set_params(InstDev& h, double r, double tau, double m11) {
   h.r = r; h.tau = tau; h.m11 = m11;
-  h.tau_s = tau / m11;
+  // (row scaling keeps the arithmetic tau / m11 and an exact unit m11_s)
+  const bool lit = (h.gamma_mode == PFC_GAMMA_LITERAL);
+  h.rs = lit ? 1.0 : 1.0 / m11;
+  h.m11_s = lit ? m11 : 1.0;
+  h.tau_s = lit ? tau : tau / m11;
   h.tau_p = h.m0 * h.tau_s;
   h.delta = std::sqrt(h.tau_p);
   h.sdelta = std::sqrt(h.delta);
@@ -1158,6 +1174,8 @@ int pfc_instance_create(pfc_mesh* m, const pfc_opts* o, pfc_instance** out) {
   h.model = o->model;
   h.psi_min = o->psi_min;
   h.grid_cols = o->grid_columns;
+  h.gamma_mode = o->gamma_mode;
+  for (int k = 0; k < 5; ++k) h.inner_fixed[k] = o->inner_fixed[k];
   h.m0 = 1.0;
   h.team_size = I->team_size;
   h.outer_tol = o->outer_tol;

@@ -39,6 +39,8 @@ PFC_OP_M = 0
 PFC_OP_K = 1
 PFC_MODEL_PFC2 = 0
 PFC_MODEL_PFC1 = 1
+PFC_GAMMA_SCALE_ROW = 0
+PFC_GAMMA_LITERAL = 1
 
 
 class pfc_opts(C.Structure):
@@ -47,7 +49,8 @@ class pfc_opts(C.Structure):
                 ("shared_ops", C.c_int), ("rows_per_thread", C.c_int), ("max_run_steps", C.c_int),
                 ("ticks_per_graph", C.c_int), ("single_reduction", C.c_int),
                 ("schur_variant", C.c_int), ("sd_iters", C.c_int), ("model", C.c_int), ("psi_min", C.c_double),
-                ("grid_columns", C.c_int), ("reserved", C.c_int)]
+                ("grid_columns", C.c_int), ("gamma_mode", C.c_int), ("inner_fixed", C.c_int * 5),
+                ("reserved", C.c_int)]
 
 
 class pfc_solve_info(C.Structure):
@@ -173,6 +176,8 @@ def pfc_opts_default(**over) -> pfc_opts:
     o = pfc_opts()
     _lib.pfc_opts_default(C.byref(o))
     for k, v in over.items():
+        if k == "inner_fixed":
+            v = (C.c_int * 5)(*v)
         setattr(o, k, v)
     return o
 

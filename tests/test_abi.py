@@ -102,6 +102,11 @@ def test_null_handles_rejected(pfc):
     o = pfc.pfc_opts_default(grid_columns=2)
     assert pfc.pfc_opts_default().grid_columns == 1
     assert pfc._lib.pfc_instance_footprint(C.c_void_p(1), C.byref(o)) == 0
+    # gamma_mode takes the two readings, inner_fixed non-negative counts
+    for bad in (pfc.pfc_opts_default(gamma_mode=2), pfc.pfc_opts_default(inner_fixed=[0, -1, 0, 0, 0])):
+        assert pfc._lib.pfc_instance_footprint(C.c_void_p(1), C.byref(bad)) == 0
+    d = pfc.pfc_opts_default()
+    assert d.gamma_mode == pfc.PFC_GAMMA_SCALE_ROW and list(d.inner_fixed) == [0] * 5
 
 
 def test_product_path_does_not_import_oracle():

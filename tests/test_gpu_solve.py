@@ -330,3 +330,40 @@ def test_column_forms_agree_bitwise(pfc, dim, N, jit, prec, rpt):
         for i in insts:
             pfc.pfc_instance_destroy(i)
         P.close()
+
+
+@pytest.mark.parametrize("dim,N,jit,tau", [(2, 16, 0.2, 0.8), (3, 5, 0.2, 0.5)])
+def test_gamma_literal_and_fixed_inner_counts(pfc, dim, N, jit, tau):
+    """The literal reading of Section 4 (P_CH(tau) on the unscaled system) and fixed inner iteration
+    counts, each against the oracle run the same way."""
+    P = Problem(dim, N, jit, seed=71)
+    insts = []
+    try:
+        r, psibar = -0.35, -0.3
+        n = P.n
+        _, b = _stage1(P, r, tau)
+        Nm = assembly.N_matrix(P.mesh, P.psi)
+        x = dev(np.zeros(3 * n))
+        # literal reading: replay parity, then tolerance mode
+        y_ref, info = osolve.solve_stage(P.M, P.K, Nm, r, tau, M11, b, tol=1e-8, gamma_mode="literal")
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(gamma_mode=pfc.PFC_GAMMA_LITERAL))
+        insts.append(inst)
+        s = info["schedule"]
+        st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
+        assert gi["outer_iters"] == info["steps"] and rel(host(x), y_ref) <= 1e-10
+        st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
+        res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, tau, M11, host(x))) / np.linalg.norm(b)
+        assert st == pfc.PFC_OK and res <= 1e-8
+        # fixed inner counts: every application runs exactly these counts, same iterates as the oracle
+        fc = [4, 6, 5, 5, 4]
+        y_f, info_f = osolve.solve_stage(P.M, P.K, Nm, r, tau, M11, b, tol=1e-8, inner_fixed=fc)
+        inst2 = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(inner_fixed=fc))
+        insts.append(inst2)
+        st, gi = pfc.pfc_solve(inst2, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
+        got = pfc.pfc_last_inner_counts(inst2)
+        assert (got == np.array(fc)).all()
+        assert gi["outer_iters"] == info_f["steps"] and rel(host(x), y_f) <= 1e-10
+    finally:
+        for i in insts:
+            pfc.pfc_instance_destroy(i)
+        P.close()

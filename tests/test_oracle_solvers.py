@@ -121,3 +121,40 @@ def test_jacobi_mass_spectrum_element_bounds(dim, N, jit):
     d = np.diag(Md)
     ev = np.linalg.eigvalsh(Md / np.sqrt(np.outer(d, d)))
     assert ev.min() >= 0.5 - 1e-12 and ev.max() <= (dim + 2) / 2 + 1e-12
+
+
+def test_both_gamma_readings_solve_the_same_system():
+    """Section 4 derives P for m11 = 1.  Row scaling with P_CH(tau/m11) and P_CH(tau) on the unscaled
+    system are two readings of using it for m11 = 1/gamma: both reach the dense solution, and for
+    m11 = 1 they are one and the same computation."""
+    mesh, M, K, psi = _prob(2, 8)
+    N = assembly.N_matrix(mesh, psi)
+    b = np.random.default_rng(11).normal(size=3 * mesh.n)
+    r, tau = -0.35, 0.8
+    m11 = 1.0 / pfc.ROS3PW_GAMMA
+    yd = reference.dense_solve(pfc.AR_sparse(M, K, N, r, tau, m11), b)
+    for mode in ("scale_row", "literal"):
+        y, info = solve.solve_stage(M, K, N, r, tau, m11, b, tol=1e-11, gamma_mode=mode)
+        assert info["converged"] and np.linalg.norm(y - yd) <= 1e-8 * np.linalg.norm(yd), mode
+    y1, i1 = solve.solve_stage(M, K, N, r, tau, 1.0, b, tol=1e-8)
+    y2, i2 = solve.solve_stage(M, K, N, r, tau, 1.0, b, tol=1e-8, gamma_mode="literal")
+    assert np.array_equal(y1, y2) and i1["steps"] == i2["steps"]
+    with pytest.raises(ValueError):
+        solve.solve_stage(M, K, N, r, tau, m11, b, gamma_mode="other")
+
+
+def test_fixed_inner_counts():
+    """Fixed counts replace the tolerance test of the steps they name; 0 keeps it."""
+    mesh, M, K, _ = _prob(2, 8)
+    v = np.random.default_rng(12).normal(size=3 * mesh.n)
+    inner = precond.InnerSolvers(M, K, 0.5, fixed_counts=[3, 5, 4, 6, 2])
+    precond.pch_apply(inner, v)
+    assert inner.counts[0] == [3, 5, 4, 6, 2]
+    tol = precond.InnerSolvers(M, K, 0.5)
+    precond.pch_apply(tol, v)
+    mixed = precond.InnerSolvers(M, K, 0.5, fixed_counts=[0, 5, 0, 0, 2])
+    z = precond.pch_apply(mixed, v)
+    assert mixed.counts[0][1] == 5 and mixed.counts[0][4] == 2 and mixed.counts[0][0] == tol.counts[0][0]
+    # replaying the counts of an apply reproduces it exactly
+    rep = precond.InnerSolvers(M, K, 0.5, replay_counts=[mixed.counts[0]])
+    assert np.array_equal(precond.pch_apply(rep, v), z)
