@@ -11,7 +11,12 @@ control to the literature).  Reading taken here, the elementary controller:
     tau  <- tau * min(facmax, max(facmin, safety * err^(-1/3)))
 
 with safety 0.9, facmin 0.2, facmax 5 and the exponent 1/(p_hat + 1), p_hat = 2.
-The error is measured on psi, the differential component of the DAE.
+The error is measured on psi, the differential component of the DAE.  Two
+safeguards of the textbook controller (Hairer, Norsett, Wanner, Solving ODEs I,
+Sec. II.4): the step that follows a rejection may not grow (facmax = 1 there),
+and a step whose linear solves miss their tolerance (the linear_solve raises
+LinearSolveFailed) is rejected without an error estimate and retried with
+tau * facmin.
 
 Pinned by tests/test_oracle_adaptive.py: the embedded solution converges with
 order 2 and ||x - x_hat|| with order 3 per step on a nonlinear ODE; an
@@ -32,31 +37,51 @@ def error_norm(psi_old, psi_new, psi_hat, rtol, atol):
     return float(math.sqrt(np.mean(((psi_new - psi_hat) / sc) ** 2)))
 
 
-def next_tau(tau, err):
+class LinearSolveFailed(Exception):
+    """Raised by a linear_solve whose iteration stopped short of its tolerance."""
+
+
+def next_tau(tau, err, facmax=FACMAX):
     if err == 0.0:
-        return tau * FACMAX
-    return tau * min(FACMAX, max(FACMIN, SAFETY * err ** (-1.0 / 3.0)))
+        return tau * facmax
+    return tau * min(facmax, max(FACMIN, SAFETY * err ** (-1.0 / 3.0)))
 
 
-def rosenbrock_adaptive(prob, x0, tau0, t_end, rtol, atol, linear_solve, max_attempts=10000):
+def rosenbrock_adaptive(prob, x0, tau0, t_end, rtol, atol, linear_solve, max_attempts=10000, log=None):
     """Adaptive Ros3Pw run of a PFCProblem from t = 0 to t_end.
 
-    linear_solve as in PFCProblem.step.  Returns (x, accepted_taus, n_rejected).
+    linear_solve as in PFCProblem.step; it may raise LinearSolveFailed.  If log
+    is a list, (tau, outcome) of every attempt is appended to it, outcome being
+    "accepted", "rejected" (error estimate above 1) or "failed" (linear solve).
+    Returns (x, accepted_taus, n_rejected), n_rejected counting both kinds.
     """
     n = prob.n
     t, tau, x = 0.0, tau0, x0.copy()
-    taus, rejected = [], 0
+    taus, rejected, after_reject = [], 0, False
     for _ in range(max_attempts):
         if t >= t_end * (1 - 1e-14):
             break
         h = min(tau, t_end - t)
-        x_new, x_hat, _ = prob.step(x, h, linear_solve)
+        try:
+            x_new, x_hat, _ = prob.step(x, h, linear_solve)
+        except LinearSolveFailed:
+            rejected += 1
+            after_reject = True
+            tau = h * FACMIN
+            if log is not None:
+                log.append((h, "failed"))
+            continue
         err = error_norm(x[n:2 * n], x_new[n:2 * n], x_hat[n:2 * n], rtol, atol)
         if err <= 1.0:
             t += h
             x = x_new
             taus.append(h)
+            tau = next_tau(h, err, 1.0 if after_reject else FACMAX)
+            after_reject = False
         else:
             rejected += 1
-        tau = next_tau(h, err)
+            tau = next_tau(h, err)
+            after_reject = True
+        if log is not None:
+            log.append((h, "accepted" if err <= 1.0 else "rejected"))
     return x, taus, rejected

@@ -61,3 +61,33 @@ def test_adaptive_run_meets_tolerance_and_rejects():
     # a too large first step (tau0 = 1 at rtol 1e-5) is rejected at least once
     _, taus, rej = adaptive.rosenbrock_adaptive(prob, x0, 1.0, T, 1e-5, 1e-5, lin)
     assert rej >= 1 and max(taus) < 1.0
+
+
+def test_controller_safeguards():
+    """No growth right after a rejection; a failed linear solve rejects the step and shrinks tau by facmin."""
+    mesh, prob, x0, lin = _pfc_setup()
+    T, cap = 2.0, 0.3
+
+    def capped(N_, tau_, bR, i):
+        if tau_ > cap:
+            raise adaptive.LinearSolveFailed()
+        return lin(N_, tau_, bR, i)
+
+    log = []
+    x, taus, rej = adaptive.rosenbrock_adaptive(prob, x0, 1.0, T, 1e-4, 1e-4, capped, log=log)
+    assert abs(sum(taus) - T) <= 1e-12 and max(taus) <= cap
+    kinds = [k for _, k in log]
+    assert kinds[0] == "failed" and kinds.count("failed") >= 1
+    assert rej == kinds.count("failed") + kinds.count("rejected")
+    for (h0, k0), (h1, k1) in zip(log, log[1:]):
+        if k0 == "failed":
+            assert h1 == h0 * adaptive.FACMIN or h1 < h0 * adaptive.FACMIN  # the end time may clip it
+        if k0 == "rejected":
+            assert h1 < h0
+    for a, b, c in zip(log, log[1:], log[2:]):
+        if a[1] != "accepted" and b[1] == "accepted":
+            assert c[0] <= b[0] * (1 + 1e-15)
+    # without failures the log holds the same steps as the accepted taus
+    log2 = []
+    _, taus2, rej2 = adaptive.rosenbrock_adaptive(prob, x0, 1.0, T, 1e-5, 1e-5, lin, log=log2)
+    assert [h for h, k in log2 if k == "accepted"] == taus2 and rej2 == sum(k == "rejected" for _, k in log2)
