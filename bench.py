@@ -244,6 +244,84 @@ def bench_served(args, torch, wl, pfc):
     print(json.dumps(out), flush=True)
 
 
+def bench_adaptive(args, torch, wl, pfc, roofline):
+    """Adaptive Ros3Pw (embedded error estimate, step-size control) on the headline 2D 512^2 float64 problem,
+    from t = 0 to t_end: every attempted step, accepted or rejected, costs three stage solves."""
+    N, r, psibar, jitter = 512, -0.35, -0.3, 0.2
+    tau0, t_end, tol, max_outer = 0.1, 200.0, 1e-3, 300
+    max_attempts = args.steps if args.steps is not None else 400
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    mesh = wl.make_mesh(2, N, jitter=jitter, seed=args.seed)
+    h = pfc.pfc_mesh_create_p1(2, mesh.n, mesh.elem_nodes, mesh.elem_coords)
+    n = mesh.n
+    z = pfc.pfc_mesh_query(h)["nnz"] / n
+    # a stage solve that needs more than max_outer Arnoldi steps rejects its step (tau * 0.2)
+    inst = pfc.pfc_instance_create(h, pfc.pfc_opts_default(precision=0, max_steps=max_outer))
+    state = torch.zeros(3 * n, dtype=torch.float64, device=dev)
+    state[n:2 * n] = torch.tensor(wl.psi0(n, psibar, 0.01, seed=args.seed), dtype=torch.float64, device=dev)
+    # consistent initial values and `warmup` fixed steps of tau0 on a copy (not timed)
+    warm = state.clone()
+    pfc.pfc_rosenbrock_run(inst, n, warm, r, psibar, tau0, max(args.warmup, 0), pfc.PFC_INIT_CONSISTENT)
+    pfc.pfc_rosenbrock_run(inst, n, state, r, psibar, tau0, 0, pfc.PFC_INIT_CONSISTENT)
+    del warm
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    st, taus, rej, infos = pfc.pfc_rosenbrock_adaptive(inst, n, state, r, psibar, tau0, t_end, tol, tol,
+                                                       max_attempts, pfc.PFC_INIT_GIVEN)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    launches, graphs = pfc.pfc_instance_launch_stats(inst)
+    attempts = len(taus) + rej
+    solves = 3 * attempts
+    alg = sum(roofline.solve_bytes(n, z, 8, i) for i in infos) + \
+        attempts * roofline.step_bytes(n, z, mesh.n_elem, 2, nloc=mesh.elem_nodes.shape[1])
+    period_s = gpu_ms * 1e-3 / max(1, launches)
+    achieved = alg / max(1, launches) / period_s / 1e9
+    failed = [a for a in range(attempts) if any(i["status"] == pfc.PFC_NOT_CONVERGED for i in infos[3 * a:3 * a + 3])]
+    res = [i["true_rel_res"] for a in range(attempts) if a not in failed for i in infos[3 * a:3 * a + 3]]
+    out = {
+        "metric": "PFC block solves/s @1e-8 rel residual",
+        "value": solves / wall,
+        "unit": "stage solves/s",
+        "n_gpus": 1,
+        "steps": attempts,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / max(1, attempts),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "pfc2d_512_adaptive_fp64", "dim": 2, "grid": N, "nodes": n, "unknowns": 3 * n,
+                   "jitter_h": jitter, "r": r, "psibar": psibar, "tau0": tau0, "t_end": t_end, "rtol": tol,
+                   "atol": tol, "max_attempts": max_attempts, "restart": 30, "outer_tol": 1e-8, "inner_tol": 1e-3,
+                   "max_outer_steps": max_outer},
+        "status": pfc.pfc_status_str(st),
+        "t_reached": float(np.sum(taus)),
+        "accepted": len(taus), "rejected": rej, "rejected_solve_failed": len(failed),
+        "tau_min": float(np.min(taus)) if len(taus) else None, "tau_max": float(np.max(taus)) if len(taus) else None,
+        "simulated_time_per_s": float(np.sum(taus)) / wall,
+        "max_true_rel_res_converged": max(res) if res else None,
+        "outer_iters_mean": float(np.mean([i["outer_iters"] for i in infos])) if infos else None,
+        "inner_pcg_per_apply_mean": float(np.mean([i["inner_total"] / max(1, i["inner_applies"]) for i in infos]))
+        if infos else None,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_tick (solver phase launch)", "launches": launches,
+                     "algorithmic_bytes": alg, "algorithmic_bytes_per_launch": alg / max(1, launches),
+                     "avg_launch_period_us": period_s * 1e6, "kernel_sources_sha256": kernel_source_digest()},
+    }
+    pfc.pfc_instance_destroy(inst)
+    pfc.pfc_mesh_destroy(h)
+    print(json.dumps(out), flush=True)
+
+
 def bench_copy_calibration(torch):
     """Plain device copy of 1 GiB (float64), three times: the reference kernel whose
     FETCH_SIZE / WRITE_SIZE counter readings calibrate the solver kernel's."""
@@ -263,7 +341,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="pfc2d_512_fp64", choices=sorted(WORKLOADS) + ["batched", "served", "copy_calibration"])
+    ap.add_argument("--workload", default="pfc2d_512_fp64", choices=sorted(WORKLOADS) + ["batched", "served", "adaptive", "copy_calibration"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-check", action="store_true",
                     help="skip the untimed float64 comparison step of mixed-precision workloads (profiled runs)")
@@ -291,6 +369,8 @@ def main():
         return bench_batched(args, torch, wl, pfc)
     if args.workload == "served":
         return bench_served(args, torch, wl, pfc)
+    if args.workload == "adaptive":
+        return bench_adaptive(args, torch, wl, pfc, roofline)
     dim, N, jitter, r, psibar, tau, prec, dsteps = WORKLOADS[args.workload]
     var = VARIANTS.get(args.workload, {})
     steps = args.steps if args.steps is not None else dsteps

@@ -304,7 +304,8 @@ int pfc_solve_x(pfc_instance* inst, const double* x_k, double r, double psibar, 
  * array counts of capacity cap applications; *n_applies receives the count. */
 int pfc_last_inner_counts(const pfc_instance* inst, int* counts, int cap, int* n_applies);
 
-/* Launch statistics of the instance's most recent solve or run: number of
+/* Launch statistics of the instance's most recent solve or run (for
+ * pfc_rosenbrock_adaptive: summed over all its attempted steps): number of
  * solver-kernel launches issued (replayed graphs times launches per graph,
  * including launches that found the instance finished) and number of graph
  * replays.  Host outputs; either may be NULL. */
@@ -330,17 +331,24 @@ int pfc_rosenbrock_run(pfc_instance* inst, double* state, double r, double psiba
  * x_hat = x_k + sum mhat_j y_j of Table rosenbrock_scheme, order 2).  After each
  * step, err = RMS over the psi block of (psi_{k+1} - psi_hat) / (atol + rtol
  * max(|psi_k|, |psi_{k+1}|)); the step is accepted if err <= 1 (otherwise the
- * state is restored), and tau <- tau * min(5, max(0.2, 0.9 err^(-1/3))).  The
- * last step is shortened to end at t_end.
+ * state is restored), and tau <- tau * min(facmax, max(0.2, 0.9 err^(-1/3)))
+ * with facmax = 1 for the step after a rejection, 5 otherwise.  A step whose
+ * stage solves do not all converge (within the instance's max_steps) is
+ * rejected without an error estimate and retried with 0.2 tau.  The last step
+ * is shortened to end at t_end.
  *   state       device float64 [3n], in/out
  *   tau0        first trial step; max_attempts caps accepted + rejected steps
  *   taus        host array of capacity max_attempts: accepted step sizes in order
- *   n_accepted, n_rejected  host outputs
+ *   n_accepted, n_rejected  host outputs (n_rejected counts both kinds of rejection)
+ *   infos       host array of capacity 3 * max_attempts, or NULL: the records
+ *               of the three stage solves of every attempted step (accepted
+ *               and rejected, in order)
  * Returns PFC_NOT_CONVERGED if t_end was not reached within max_attempts, a
- * negative code on failure, otherwise the worst stage-solve status. */
+ * negative code on failure, otherwise the worst status of the accepted steps'
+ * stage solves. */
 int pfc_rosenbrock_adaptive(pfc_instance* inst, double* state, double r, double psibar, double tau0, double t_end,
                             double rtol, double atol, int max_attempts, int init, double* taus, int* n_accepted,
-                            int* n_rejected, void* stream);
+                            int* n_rejected, pfc_solve_info* infos, void* stream);
 
 /* Operator-level entry points of the hot path (device pointers). */
 /* out = A^R y with N(psi_k) reassembled from psi_k; y, out [3n]. */

@@ -1315,7 +1315,7 @@ int pfc_rosenbrock_run(pfc_instance* I, double* state, double r, double psibar, 
 
 int pfc_rosenbrock_adaptive(pfc_instance* I, double* state, double r, double psibar, double tau0, double t_end,
                             double rtol, double atol, int max_attempts, int init, double* taus, int* n_accepted,
-                            int* n_rejected, void* stream) {
+                            int* n_rejected, pfc_solve_info* infos, void* stream) {
   if (!I || !state || !taus || !n_accepted || !n_rejected || !std::isfinite(r) || !std::isfinite(psibar) ||
       !(tau0 > 0.0) || !(t_end > 0.0) || !std::isfinite(t_end) || !(rtol > 0.0) || !(atol > 0.0) || max_attempts < 1 ||
       (init != PFC_INIT_GIVEN && init != PFC_INIT_CONSISTENT)) {
@@ -1333,14 +1333,17 @@ int pfc_rosenbrock_adaptive(pfc_instance* I, double* state, double r, double psi
   *n_rejected = 0;
   int rc = set_mobility_mean(I, state + n, s), worst = PFC_OK;
   std::vector<double> part(ns);
+  long long graphs = 0;  // launch statistics of the whole call (one run per attempted step)
   if (!rc && init == PFC_INIT_CONSISTENT) {
     set_params(h, r, tau0, 1.0 / ROS_GAMMA);
     h.n_steps = 0;
     h.init_mode = PFC_INIT_CONSISTENT;
     rc = prep_ops(I, s);
     if (!rc) rc = run_single(I, s, JOB_RB);
+    graphs += I->grp.graphs_run;
   }
   double t = 0.0, tau = tau0;
+  bool after_reject = false;  // the step after a rejection may not grow
   for (int a = 0; !rc && a < max_attempts && t < t_end * (1.0 - 1e-14); ++a) {
     const double step = std::min(tau, t_end - t);
     if (hipMemcpyAsync(h.xbak, state, sizeof(double) * 3 * (size_t)n, hipMemcpyDeviceToDevice, s) != hipSuccess) { rc = PFC_ERR_HIP; break; }
@@ -1350,9 +1353,22 @@ int pfc_rosenbrock_adaptive(pfc_instance* I, double* state, double r, double psi
     rc = prep_ops(I, s);
     if (!rc) rc = run_single(I, s, JOB_RB);
     if (rc) break;
+    graphs += I->grp.graphs_run;
     State fin;
     if (hipMemcpy(&fin, h.st, sizeof(State), hipMemcpyDeviceToHost) != hipSuccess) { rc = PFC_ERR_HIP; break; }
+    if (infos) {  // the three stage solves of this attempt, accepted or not
+      InfoDev f[3];
+      if (hipMemcpy(f, h.info, sizeof(f), hipMemcpyDeviceToHost) != hipSuccess) { rc = PFC_ERR_HIP; break; }
+      for (int k = 0; k < 3; ++k) fill_info(infos + 3 * (size_t)a + k, f[k]);
+    }
     if (fin.status < 0) { worst = fin.status; break; }
+    if (fin.status == PFC_NOT_CONVERGED) {  // a stage solve missed its tolerance: reject, retry with facmin * step
+      *n_rejected += 1;
+      if (hipMemcpyAsync(state, h.xbak, sizeof(double) * 3 * (size_t)n, hipMemcpyDeviceToDevice, s) != hipSuccess) { rc = PFC_ERR_HIP; break; }
+      tau = step * 0.2;
+      after_reject = true;
+      continue;
+    }
     if (fin.status > worst) worst = fin.status;
     hipLaunchKernelGGL(k_embedded_err, dim3(ns), dim3(64), 0, s, h, h.xbak, state, rtol, atol);
     if (hipGetLastError() != hipSuccess || hipMemcpyAsync(part.data(), h.errpart, sizeof(double) * ns, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -1361,19 +1377,23 @@ int pfc_rosenbrock_adaptive(pfc_instance* I, double* state, double r, double psi
     for (int k = 0; k < ns; ++k) sum += part[k];
     const double err = std::sqrt(sum / n);
     if (!std::isfinite(err)) { worst = PFC_ERR_BREAKDOWN; break; }
+    const double facmax = (err <= 1.0 && after_reject) ? 1.0 : 5.0;
     if (err <= 1.0) {
       t += step;
       taus[*n_accepted] = step;
       *n_accepted += 1;
+      after_reject = false;
       if (*n_accepted >= max_attempts) break;
     } else {
       *n_rejected += 1;
+      after_reject = true;
       if (hipMemcpyAsync(state, h.xbak, sizeof(double) * 3 * (size_t)n, hipMemcpyDeviceToDevice, s) != hipSuccess) { rc = PFC_ERR_HIP; break; }
     }
-    const double fac = err == 0.0 ? 5.0 : std::min(5.0, std::max(0.2, 0.9 * std::pow(err, -1.0 / 3.0)));
+    const double fac = err == 0.0 ? facmax : std::min(facmax, std::max(0.2, 0.9 * std::pow(err, -1.0 / 3.0)));
     tau = step * fac;
   }
   if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = PFC_ERR_HIP;
+  I->grp.graphs_run = graphs;
   h.xk = own_xk;
   if (rc) return rc;
   if (worst < 0) return worst;

@@ -120,7 +120,8 @@ _sig("pfc_instance_launch_stats", C.c_int, [_vp, C.POINTER(C.c_longlong), C.POIN
 _sig("pfc_rosenbrock_run", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
                                      C.POINTER(pfc_schedule), C.POINTER(pfc_solve_info), _vp])
 _sig("pfc_rosenbrock_adaptive", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
-                                          C.c_double, C.c_int, C.c_int, _dp, _ip, _ip, _vp])
+                                          C.c_double, C.c_int, C.c_int, _dp, _ip, _ip, C.POINTER(pfc_solve_info),
+                                          _vp])
 _sig("pfc_apply_AR", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, _vp, _vp, _vp])
 _sig("pfc_apply_AR_x", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, _vp, _vp, _vp])
 _sig("pfc_apply_pch", C.c_int, [_vp, C.c_double, _vp, _vp, _ip, _ip, _vp])
@@ -378,14 +379,16 @@ def pfc_rosenbrock_run(inst, n, state, r, psibar, tau, n_steps, init=PFC_INIT_CO
 
 def pfc_rosenbrock_adaptive(inst, n, state, r, psibar, tau0, t_end, rtol, atol, max_attempts=1000,
                             init=PFC_INIT_CONSISTENT, stream=None):
-    """Returns (status, accepted taus, n_rejected)."""
+    """Returns (status, accepted taus, n_rejected, infos of the 3 stage solves of every attempted step)."""
     taus = np.zeros(max_attempts)
     na, nr = C.c_int(), C.c_int()
+    infos = (pfc_solve_info * (3 * max_attempts))()
     st = _lib.pfc_rosenbrock_adaptive(inst, _dev(state, 3 * n, "state"), r, psibar, tau0, t_end, rtol, atol,
                                       max_attempts, init, taus.ctypes.data_as(_dp), C.byref(na), C.byref(nr),
-                                      _stream(stream))
+                                      infos, _stream(stream))
     _check(st, "pfc_rosenbrock_adaptive")
-    return st, taus[:na.value].copy(), nr.value
+    att = na.value + nr.value
+    return st, taus[:na.value].copy(), nr.value, [infos[k].as_dict() for k in range(3 * att)]
 
 
 def pfc_apply_AR(inst, n, psi_k, r, tau, m11, y, out, stream=None):

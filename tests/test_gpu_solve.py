@@ -211,12 +211,61 @@ def test_adaptive_rosenbrock_matches_oracle(pfc):
         xr, taus_r, rej_r = adaptive.rosenbrock_adaptive(prob, x0, 0.5, T, rtol, rtol, lin)
         inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(outer_tol=1e-12))
         state = dev(np.concatenate([np.zeros(n), P.psi, np.zeros(n)]))
-        st, taus, rej = pfc.pfc_rosenbrock_adaptive(inst, n, state, r, -0.2, 0.5, T, rtol, rtol)
+        st, taus, rej, infos = pfc.pfc_rosenbrock_adaptive(inst, n, state, r, -0.2, 0.5, T, rtol, rtol)
+        assert len(infos) == 3 * (len(taus) + rej) and all(i["true_rel_res"] <= 1e-12 for i in infos)
         assert st >= 0
         assert len(taus) == len(taus_r) and rej == rej_r
         assert np.abs(np.array(taus) - np.array(taus_r)).max() <= 1e-8 * max(taus_r)
         assert abs(sum(taus) - T) <= 1e-12
         assert rel(host(state), xr) <= 1e-8
+    finally:
+        if inst is not None:
+            pfc.pfc_instance_destroy(inst)
+        P.close()
+
+
+def test_adaptive_rejects_steps_whose_solves_fail(pfc):
+    """A stage solve that stops at max_steps rejects the step (tau * 0.2), and the step after a rejection does
+    not grow: same accepted steps, rejections and end state as the oracle's controller with the same capped
+    FGMRES.  Fixed inner counts make the outer iteration counts a property of the method on both sides; the
+    oracle run checks that every count is at least one step from the cap."""
+    from oracle import adaptive
+    P = Problem(2, 8, 0.15, amp=0.3, psibar=-0.2, seed=31, h=2.0)
+    inst = None
+    try:
+        r, T, rtol, cap, fixed = -0.35, 5.0, 1e-4, 34, [2] * 5
+        n = P.n
+        x0 = opfc.consistent_init(P.mesh, P.M, P.K, r, P.psi)
+        prob = opfc.PFCProblem(P.mesh, P.M, P.K, r)
+        kw = dict(tol=1e-8, inner_fixed=fixed)
+
+        def lin(N_, tau_, bR, i):
+            y, info = osolve.solve_stage(P.M, P.K, N_, r, tau_, M11, bR, max_steps=cap, **kw)
+            if not info["converged"]:
+                assert not osolve.solve_stage(P.M, P.K, N_, r, tau_, M11, bR, max_steps=cap + 1, **kw)[1]["converged"]
+                raise adaptive.LinearSolveFailed()
+            assert info["steps"] <= cap - 1
+            return y
+
+        log = []
+        xr, taus_r, rej_r = adaptive.rosenbrock_adaptive(prob, x0, 0.5, T, rtol, rtol, lin, log=log)
+        n_failed = sum(k == "failed" for _, k in log)
+        assert n_failed >= 2 and any(k == "rejected" for _, k in log)
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(max_steps=cap, inner_fixed=fixed))
+        state = dev(np.concatenate([np.zeros(n), P.psi, np.zeros(n)]))
+        st, taus, rej, infos = pfc.pfc_rosenbrock_adaptive(inst, n, state, r, -0.2, 0.5, T, rtol, rtol)
+        assert st >= 0
+        assert len(taus) == len(taus_r) and rej == rej_r
+        assert np.abs(np.array(taus) - np.array(taus_r)).max() <= 1e-8 * max(taus_r)
+        assert rel(host(state), xr) <= 1e-8
+        # three records per attempt; the attempts the oracle saw fail hold a stage that stopped at the cap
+        assert len(infos) == 3 * len(log)
+        for a, (_, kind) in enumerate(log):
+            att = infos[3 * a:3 * a + 3]
+            failed = [i["status"] == pfc.PFC_NOT_CONVERGED for i in att]
+            assert any(failed) == (kind == "failed"), (a, kind, att)
+            if kind == "failed":
+                assert att[failed.index(True)]["outer_iters"] == cap
     finally:
         if inst is not None:
             pfc.pfc_instance_destroy(inst)
