@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # was taken on: when their digest differs, `traffic` is reported as null.
 TRAFFIC = {
     # workload: (sha256 of the kernel sources, bytes per launch, algorithmic bytes per launch of the same run)
-    "pfc2d_512_fp64": ("9f4fc1f6c5675526cae6d8c1636d22258c24f8daa5d37b15d73db59067203f7d", 34200428.0, 37986008.0),
-    "pfc3d_64_mixed": ("9f4fc1f6c5675526cae6d8c1636d22258c24f8daa5d37b15d73db59067203f7d", 30411960.0, 37670502.0),
+    "pfc2d_512_fp64": ("bb883c337584e49e583b0b4f0ba75726a98714c2952df7a2ff2cccee4cc6a4c7", 34201080.0, 37986008.0),
+    "pfc3d_64_mixed": ("bb883c337584e49e583b0b4f0ba75726a98714c2952df7a2ff2cccee4cc6a4c7", 30416156.0, 37670502.0),
 }
 
 
