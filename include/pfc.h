@@ -128,7 +128,20 @@ typedef struct pfc_server pfc_server;
  *   inner_fixed   iteration counts of the five inner solves (1), (2), (3.1),
  *                 (3.2), (5) of every preconditioner application; 0 (the
  *                 default) runs that solve to inner_tol.  With S_D, entry 2 is
- *                 the S_D solve (overrides sd_iters) and entry 3 is unused. */
+ *                 the S_D solve (overrides sd_iters) and entry 3 is unused.
+ *   pcg_steps_per_launch  2 (default): where the launch allows it, the five
+ *                 inner solves run two PCG iterations per solver launch in the
+ *                 s-step form (basis p, Tp, T^2 p, u, Tu of T = D^{-1} C, one
+ *                 reduction of their D-weighted Gram matrix, halo rows staged
+ *                 in LDS): same iterates and the same stopping decisions as the
+ *                 standard iteration in exact arithmetic, and the same count
+ *                 of iterations.  It applies to float64 instances with
+ *                 single_reduction = 1 on 2D periodic grid meshes with
+ *                 grid_columns = 1 and rows_per_thread <= 1, in launches that
+ *                 serve the instance alone; elsewhere, and with 1, one
+ *                 iteration per launch.  Results then differ from a launch
+ *                 that serves the instance together with others by rounding
+ *                 (1 gives the same bits alone and in a batch). */
 typedef struct pfc_opts {
     int struct_size;
     int precision;
@@ -149,7 +162,7 @@ typedef struct pfc_opts {
     int grid_columns;
     int gamma_mode;
     int inner_fixed[5];
-    int reserved;
+    int pcg_steps_per_launch;
 } pfc_opts;
 
 /* Result record of one stage solve.

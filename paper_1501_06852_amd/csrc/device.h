@@ -928,4 +928,193 @@ __device__ __forceinline__ Red3 ph_cg_iter(const InstDev& I, const State& S, con
   return red3(a0, a1, a2);
 }
 
+// ---- two Jacobi-PCG iterations per launch (s-step form, s = 2) ---------------
+// With T = D^{-1} C (D = diag C) the Jacobi PCG is CG for T in the D-weighted
+// inner product <a, b> = a^T D b: u = D^{-1} r, (r, u) = <u, u>, (p, C p) =
+// <p, T p>, ||r||^2 = u^T D^2 u.  From the basis B = [p, Tp, T^2 p, u, Tu] of a
+// launch, the next two iterates are combinations of B whose coefficients follow
+// from the Gram matrices G = B^T D B and H = B'^T D^2 B' (B' = [Tp, T^2 p, u,
+// Tu]), so one reduction serves two iterations.  A launch forms the new p, u as
+// such combinations on its own rows and on the rows two (p) or one (u) stencil
+// steps around them, keeps them in LDS, and applies T there: Tp on the rows one
+// step around, T^2 p and Tu on its own rows.  The halo is a contiguous range of
+// rows (mod n) on 2D periodic grids, whose neighbours lie within N + 1 rows.
+#define PFC_SS_LDS 8192
+#define PFC_SS_NG 25  // 15 entries of G, 10 of H
+__shared__ double pfc_ss[PFC_SS_LDS];
+__shared__ double pfc_ssred[32 * 32];
+#ifdef PFC_TICK_TIMING
+__shared__ unsigned long long pfc_sst[4];  // optional instrumentation (separate build only)
+#define PFC_SS_STAMP(k) \
+  if (threadIdx.x == 0) pfc_sst[k] = wall_clock64()
+#else
+#define PFC_SS_STAMP(k)
+#endif
+
+// Cross-lane moves of a double through DPP (register to register, no LDS).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Sum over each row of 16 lanes, in every lane of the row (fixed order).
+__device__ __forceinline__ double dpp_row_sum(double v) {
+  v += dpp_f64<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141, 0xf>(v);  // row_half_mirror
+  v += dpp_f64<0x140, 0xf>(v);  // row_mirror
+  return v;
+}
+// Sum over lanes 0-31 in lane 31 and over lanes 32-63 in lane 63.
+__device__ __forceinline__ double dpp_half_sum(double v) {
+  v = dpp_row_sum(v);
+  return v + dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+}
+// Sum over the wave in lane 63.
+__device__ __forceinline__ double dpp_wave_sum(double v) {
+  v = dpp_half_sum(v);
+  return v + dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+}
+
+__device__ __forceinline__ int ss_wrap(int g, int n) { return g < 0 ? g + n : (g >= n ? g - n : g); }
+// offset j - g of a neighbour as a step within the grid (|step| <= N + 1 < n / 2)
+__device__ __forceinline__ int ss_step(int d, int n) { return d > (n >> 1) ? d - n : (d < -(n >> 1) ? d + n : d); }
+
+// upper-triangle index of (i, j), i <= j, in a k x k symmetric matrix
+__host__ __device__ __forceinline__ int ss_tri(int i, int j, int k) { return i * k - i * (i - 1) / 2 + (j - i); }
+
+// coef: x increment [0..4], new p [5..9], new u [10..14] over B; final: x only.
+template <int L>
+__device__ __forceinline__ void ph_scg(const InstDev& I, const State& S, const Team& tm, const double* coef, bool init,
+                                       double* spart_out) {
+  const int n = I.n, H = I.sH;
+  PcgOps<double> o = pcg_ops<double>(I, S.kind);
+  const PatView<L> pv = op_pat<L>(I, o, tm);
+  const int uw = pv.uw;
+  const int spw = (I.m.n_slices + tm.size - 1) / tm.size;
+  const int lo = min(tm.rank * spw * 64, n);
+  const int R = min(lo + spw * 64, n) - lo;  // own rows [lo, lo + R), at most PFC_WG
+  const int L1 = R + 2 * H, L2 = R + 4 * H;
+  const int tid = threadIdx.x;
+  const long long nn = n;
+  const double* bin = I.sbas + (long long)(S.cur ^ 1) * 5 * nn;
+  double* bout = I.sbas + (long long)S.cur * 5 * nn;
+  if (!init && S.pcur) {  // the solve ends within these two iterations: x only
+    for (int q = tid; q < R; q += PFC_WG) {
+      const int g = lo + q;
+      vst(o.x + g, o.x[g] + (coef[0] * bin[g] + coef[1] * bin[nn + g] + coef[3] * bin[3 * nn + g]));
+    }
+    return;
+  }
+  double* sp = pfc_ss;     // new p on [lo - 2H, lo + R + 2H)
+  double* su = sp + L2;    // new u on [lo - H, lo + R + H)
+  double* stp = su + L1;   // T p on [lo - H, lo + R + H)
+  const double* r = (const double*)I.r_;
+  for (int q = tid; q < L2; q += PFC_WG) {
+    const int g = ss_wrap(lo - 2 * H + q, n);
+    const bool own = q >= 2 * H && q < 2 * H + R;
+    double pn, un;
+    if (init) {
+      pn = o.dinv[g] * r[g];
+      un = pn;
+    } else {
+      const double b0 = bin[g], b1 = bin[nn + g], b2 = bin[2 * nn + g], b3 = bin[3 * nn + g], b4 = bin[4 * nn + g];
+      pn = coef[5] * b0 + coef[6] * b1 + coef[7] * b2 + coef[8] * b3 + coef[9] * b4;
+      un = coef[10] * b0 + coef[11] * b1 + coef[12] * b2 + coef[13] * b3 + coef[14] * b4;
+      if (own) vst(o.x + g, o.x[g] + (coef[0] * b0 + coef[1] * b1 + coef[3] * b3));
+    }
+    sp[q] = pn;
+    if (q >= H && q < H + L1) su[q - H] = un;
+    if (own) { vst(bout + g, pn); vst(bout + 3 * nn + g, un); }
+  }
+  __syncthreads();
+  PFC_SS_STAMP(0);
+  // T p on the one-step halo; T u on the own rows (at most one own row per thread)
+  int q1o = -1;
+  double tpo = 0.0, tuo = 0.0, dgo = 0.0;
+  for (int q1 = tid; q1 < L1; q1 += PFC_WG) {
+    const int g = ss_wrap(lo - H + q1, n);
+    const bool own = q1 >= H && q1 < H + R;
+    const int base = (g >> 6) * 64 * uw + (g & 63);
+    double acc = 0.0, acc2 = 0.0, dg = 0.0;
+    for_width(uw, [&](int k) {
+      const long long e = (long long)base + k * 64;
+      const int d = ss_step(pv.at(e, g) - g, n);
+      const double a = opval(o, e);
+      acc += a * sp[q1 + H + d];
+      if (own) acc2 += a * su[q1 + d];
+      dg += d == 0 ? a : 0.0;
+    });
+    const double tp = o.dinv[g] * acc;
+    stp[q1] = tp;
+    if (own) {
+      q1o = q1; tpo = tp; tuo = o.dinv[g] * acc2; dgo = dg;
+      vst(bout + nn + g, tpo);
+      vst(bout + 4 * nn + g, tuo);
+    }
+  }
+  __syncthreads();
+  PFC_SS_STAMP(1);
+  double gp[PFC_SS_NG];
+#pragma unroll
+  for (int m = 0; m < PFC_SS_NG; ++m) gp[m] = 0.0;
+  if (q1o >= 0) {
+    const int g = lo + (q1o - H);
+    const int base = (g >> 6) * 64 * uw + (g & 63);
+    double acc = 0.0;
+    for_width(uw, [&](int k) {
+      const long long e = (long long)base + k * 64;
+      acc += opval(o, e) * stp[q1o + ss_step(pv.at(e, g) - g, n)];
+    });
+    const double ttp = o.dinv[g] * acc;
+    vst(bout + 2 * nn + g, ttp);
+    const double v[5] = {sp[q1o + H], tpo, ttp, su[q1o], tuo};
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      const double di = dgo * v[i];
+#pragma unroll
+      for (int j = i; j < 5; ++j) gp[ss_tri(i, j, 5)] = di * v[j];
+    }
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+      const double di = dgo * dgo * v[i];
+#pragma unroll
+      for (int j = i; j < 5; ++j) gp[15 + ss_tri(i - 1, j - 1, 4)] = di * v[j];
+    }
+  }
+  PFC_SS_STAMP(2);
+  // workgroup sums, fixed order: lanes within a wave (DPP), then the waves
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int m = 0; m < PFC_SS_NG; ++m) {
+    const double w = dpp_wave_sum(gp[m]);
+    if (lane == 63) pfc_ssred[wave * 32 + m] = w;
+  }
+  __syncthreads();
+  if (tid < PFC_SS_NG) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < PFC_WAVES; ++w) t += pfc_ssred[w * 32 + tid];
+    vst(spart_out + (long long)tm.rank * 32 + tid, t);
+  }
+  PFC_SS_STAMP(3);
+}
+
+// Sum of the Gram partials of a team ([size][32], fixed order) into g[0..24].
+__device__ __forceinline__ void ss_gram(const double* part, int size, double* g) {
+  const int tid = threadIdx.x, v = tid & 31, grp = tid >> 5;
+  double s = 0.0;
+  if (v < PFC_SS_NG)
+    for (int k = grp; k < size; k += 32) s += part[(long long)k * 32 + v];
+  pfc_ssred[grp * 32 + v] = s;
+  __syncthreads();
+  // wave w sums value w over the 32 groups in lanes 0-31 and value w + 16 in lanes 32-63
+  const int lane = tid & 63, w = tid >> 6, vv = w + (lane >> 5) * 16;
+  const double t = dpp_half_sum(vv < PFC_SS_NG ? pfc_ssred[(lane & 31) * 32 + vv] : 0.0);
+  if ((lane & 31) == 31 && vv < PFC_SS_NG) g[vv] = t;
+  __syncthreads();
+}
+
 }  // namespace pfc

@@ -43,6 +43,8 @@ enum {
   PH_PCH_OUT,     // z_out = P_CH^{-1} v (preconditioner-only job)
   PH_CG_INIT,     // single-reduction PCG: w_0 = C D^{-1} r_0, partials (r,u), (w,u), (r,r)
   PH_CG_ITER,     // single-reduction PCG iteration (one launch per iteration)
+  PH_SCG_INIT,    // s-step PCG: basis p, Tp, T^2 p, u, Tu of u_0 = D^{-1} r_0, Gram partials
+  PH_SCG_ITER,    // s-step PCG: two iterations from the Gram matrix, next basis (or x only)
 };
 
 enum { JOB_NONE = 0, JOB_SOLVE = 1, JOB_RB = 2, JOB_PCH = 3 };
@@ -157,6 +159,7 @@ struct InstDev {
   int sd_iters, model;          // model: PFC_MODEL_PFC2 / PFC_MODEL_PFC1
   int grid_cols, gamma_mode;    // grid_columns and gamma_mode options
   int inner_fixed[5], pad_if;   // fixed inner iteration counts (0: to inner_tol)
+  int sstep, sH;                // two PCG iterations per launch allowed; halo rows (N + 1)
   double outer_tol, inner_tol, ci_tol;
   // job parameters; tau_p = m0 tau_s is the preconditioner's time step
   // rs: factor of block row 1 in the system FGMRES works on (1/m11 for
@@ -186,6 +189,8 @@ struct InstDev {
   void *r_, *pA, *pB, *q, *y0, *y1, *zt, *x1, *x2;
   void *rB, *wB, *sA, *sB;      // extra buffers of the single-reduction PCG
   double* part;                 // [2][team_size][4] partial sums
+  double* sbas;                 // s-step basis [2][5][n] (p, Tp, T^2 p, u, Tu), or null
+  double* spart;                // s-step Gram partial sums [2][team_size][32], or null
   State* st;                    // [2]
   Hist* hist;
   const int* sched_meta;        // replay: per solve {cycle offset, cycles, apply offset, applies}

@@ -220,7 +220,60 @@ __device__ __forceinline__ bool cg_iter_continues(State& S, const InstDev& I, Re
   return true;
 }
 
-__device__ void transition(State& S, const InstDev& I, bool wr, Red3 red, double* ybuf, double* col) {
+// inner solves that may run two iterations per launch: the five P_CH solves on
+// the P1 pattern (not S_D, not the consistent-initial-value mass solves)
+__device__ __forceinline__ bool scg_kind(int kind) { return kind >= KIND_Y0 && kind <= KIND_X2; }
+
+// s-step PCG: the next two iterations from the Gram sums g of the basis B = [p,
+// Tp, T^2 p, u, Tu] (g[0..14]: B^T D B, g[15..24]: D^2-weighted Gram of B[1..4]),
+// with the stopping test of the standard iteration after each of them.  coef
+// receives the increment of x and the new p and u as combinations of B;
+// S.pcur = 1 marks a launch that only adds the increment (the solve ends there).
+__device__ void scg_transition(State& S, const InstDev& I, bool wr, const double* g, double* coef) {
+  if (S.phase == PH_SCG_ITER && S.pcur) { pcg_done(S, I, wr); return; }
+  S.phase = PH_SCG_ITER;
+  S.cur ^= 1;
+  double G[5][5], Hm[5][5];
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) {
+      const int a = i < j ? i : j, b = i < j ? j : i;
+      G[i][j] = g[ss_tri(a, b, 5)];
+      Hm[i][j] = a == 0 ? 0.0 : g[15 + ss_tri(a - 1, b - 1, 4)];
+    }
+  auto form = [](const double* x, const double* y, const double (*M)[5]) {
+    double s = 0.0;
+    for (int i = 0; i < 5; ++i)
+      for (int j = 0; j < 5; ++j) s += x[i] * M[i][j] * y[j];
+    return s;
+  };
+  for (int m = 0; m < 15; ++m) coef[m] = 0.0;
+  bool fixed; double tol;
+  const int lim = inner_limit(I, S, fixed, tol);
+  const double rho0 = G[3][3];
+  const double a0 = rho0 / G[0][1];
+  const double u1[5] = {0.0, -a0, 0.0, 1.0, 0.0};
+  const double rho1 = form(u1, u1, G), rr1 = form(u1, u1, Hm);
+  coef[0] = a0;
+  S.it += 1;
+  S.pcur = 1;
+  if (S.it >= lim || (!fixed && rr1 <= tol * tol * S.bb) || rho1 == 0.0 || !isfinite(rr1)) return;
+  const double b0 = rho1 / rho0;
+  const double p1[5] = {b0, -a0, 0.0, 1.0, 0.0}, tp1[5] = {0.0, b0, -a0, 0.0, 1.0};
+  const double a1 = rho1 / form(p1, tp1, G);
+  double u2[5];
+  for (int k = 0; k < 5; ++k) u2[k] = u1[k] - a1 * tp1[k];
+  const double rho2 = form(u2, u2, G), rr2 = form(u2, u2, Hm);
+  coef[0] = a0 + a1 * p1[0];
+  coef[1] = a1 * p1[1];
+  coef[3] = a1 * p1[3];
+  S.it += 1;
+  if (S.it >= lim || (!fixed && rr2 <= tol * tol * S.bb) || rho2 == 0.0 || !isfinite(rr2)) return;
+  const double b1 = rho2 / rho1;
+  for (int k = 0; k < 5; ++k) { coef[5 + k] = u2[k] + b1 * p1[k]; coef[10 + k] = u2[k]; }
+  S.pcur = 0;
+}
+
+__device__ void transition(State& S, const InstDev& I, bool wr, Red3 red, double* ybuf, double* col, bool ss) {
   switch (S.phase) {
     case PH_START:
       if (S.job == JOB_SOLVE) S.phase = PH_SOLVE_INIT;
@@ -250,7 +303,8 @@ __device__ void transition(State& S, const InstDev& I, bool wr, Red3 red, double
       bool fixed; double tol;
       const int lim = inner_limit(I, S, fixed, tol);
       if (S.bb == 0.0 || lim == 0) pcg_done(S, I, wr);
-      else S.phase = I.single_reduction ? PH_CG_INIT : PH_PCG_A;
+      else if (!I.single_reduction) S.phase = PH_PCG_A;
+      else S.phase = (ss && scg_kind(S.kind)) ? PH_SCG_INIT : PH_CG_INIT;
     } break;
     case PH_CG_INIT:
       S.rho = red.a;             // gamma_0 = (r_0, D^{-1} r_0)
@@ -390,6 +444,10 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   __shared__ Red3 lds4[PFC_WAVES];
   __shared__ double ybuf[PFC_MAXM];
   __shared__ double gcol[PFC_MAXM + 1];
+  // two PCG iterations per launch: float64 launches that serve one instance on a periodic grid
+  constexpr bool SS = SINGLE && COLS == PFC_COL_GRID && std::is_same<T, double>::value;
+  __shared__ double ss_g[SS ? 32 : 1];
+  __shared__ double ss_coef[SS ? 16 : 1];
   PFC_STAMP(t_entry);
   const int tid = threadIdx.x;
   TeamEntry te;
@@ -456,13 +514,22 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     if (writer && tid < NS) ((int*)st_out)[tid] = ((const int*)&S)[tid];
     return;
   }
+  bool scg = false;
+  if constexpr (SS) {
+    scg = (S.phase == PH_SCG_INIT || S.phase == PH_SCG_ITER);
+    if (scg && !(S.phase == PH_SCG_ITER && S.pcur)) ss_gram(I.spart + (long long)S.cur * te.size * 32, te.size, ss_g);
+  }
   if (tid == 0) {
-    Red3 red = red3(0.0, 0.0, 0.0);
-    if (phase_partials(S.phase)) {
+    if (scg) {
+      if constexpr (SS) scg_transition(S, I, writer, ss_g, ss_coef);
+    } else {
+      Red3 red = red3(0.0, 0.0, 0.0);
+      if (phase_partials(S.phase)) {
 #pragma unroll
-      for (int w = 0; w < PFC_WAVES; ++w) { red.a += lds4[w].a; red.b += lds4[w].b; red.c += lds4[w].c; }
+        for (int w = 0; w < PFC_WAVES; ++w) { red.a += lds4[w].a; red.b += lds4[w].b; red.c += lds4[w].c; }
+      }
+      if (!cg_iter_continues(S, I, red)) transition(S, I, writer, red, ybuf, gcol, SS && I.sstep);
     }
-    if (!cg_iter_continues(S, I, red)) transition(S, I, writer, red, ybuf, gcol);
   }
   __syncthreads();
   PFC_STAMP(t_trans);
@@ -492,6 +559,11 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     case PH_PCH_OUT: acc = ph_pch_out<T>(I, tm); break;
     case PH_CG_INIT: acc = pcg_phase<T, COLS, PH_CG_INIT>(I, S, tm, sd); break;
     case PH_CG_ITER: acc = pcg_phase<T, COLS, PH_CG_ITER>(I, S, tm, sd); break;
+    case PH_SCG_INIT:
+    case PH_SCG_ITER:
+      if constexpr (SS)
+        ph_scg<COLS>(I, S, tm, ss_coef, S.phase == PH_SCG_INIT, I.spart + (long long)S.cur * te.size * 32);
+      break;
     default: break;
   }
   PFC_STAMP(t_work);
@@ -518,10 +590,11 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   if (tid == 0 && (te.rank == 0 || te.rank == te.size - 1) && g_trace) {
     const unsigned long long k = atomicAdd(&g_trace_n, 1ULL);
     if (k < g_trace_cap) {
-      unsigned long long* r = g_trace + 8 * k;
+      unsigned long long* r = g_trace + 12 * k;
       r[0] = (unsigned long long)S.phase | ((unsigned long long)te.rank << 8) | ((unsigned long long)S.kind << 40) |
              ((unsigned long long)(S.it & 0xffff) << 48);
       r[1] = t_entry; r[2] = t_ld; r[3] = t_trans; r[4] = t_work; r[5] = t_exit; r[6] = blockIdx.x; r[7] = t_red;
+      for (int q = 0; q < 4; ++q) r[8 + q] = (SS && (S.phase == PH_SCG_INIT || S.phase == PH_SCG_ITER)) ? pfc_sst[q] : 0;
     }
   }
 #endif
@@ -697,6 +770,29 @@ __global__ void k_stage_rhs(InstDev I, int stage, double* __restrict__ b) {
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Halo of the two-iterations-per-launch PCG (N + 1 rows), or 0 where it does not
+// apply: float64 single-reduction instances on 2D periodic grids with computed
+// columns, at most PFC_WAVES slices per workgroup, every neighbour within N + 1
+// rows of its row (mod n), and the three LDS arrays within PFC_SS_LDS.
+static int sstep_halo(const pfc_mesh* m, const pfc_opts& o, int team_size) {
+  const MeshDev& d = m->dev;
+  if (o.pcg_steps_per_launch != 2 || o.precision != PFC_FP64 || o.single_reduction != 1 || o.grid_columns != 1) return 0;
+  if (d.dim != 2 || d.gN < 3 || d.uw < 1 || team_size < 1) return 0;
+  const int spw = (d.n_slices + team_size - 1) / team_size;
+  if (spw > PFC_WAVES) return 0;
+  const int n = d.n, H = d.gN + 1;
+  if (2 * H >= n) return 0;
+  for (int c = 0; c < 9; ++c)  // the row classes of a 2D grid
+    for (int k = 0; k < d.uw; ++k) {
+      int s = d.glin[c * PFC_GRID_W + k];
+      s = s > n / 2 ? s - n : (s < -(n / 2) ? s + n : s);
+      if (s > H || s < -H) return 0;
+    }
+  const int rmax = std::min(spw * 64, n);
+  if (3 * rmax + 8 * H > PFC_SS_LDS) return 0;
+  return H;
+}
+
 // Carve the instance arena.  With base == nullptr only the size is computed.
 size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int team_size) {
   size_t off = 0;
@@ -739,6 +835,10 @@ size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int t
   h.xbak = (double*)take(n3 * 8);
   h.errpart = (double*)take((size_t)m->n_slices * 2 * 8);
   h.part = (double*)take(2 * (size_t)team_size * 4 * sizeof(double));
+  h.sH = sstep_halo(m, o, team_size);
+  h.sstep = h.sH > 0;
+  h.sbas = h.sstep ? (double*)take(10 * n * 8) : nullptr;
+  h.spart = h.sstep ? (double*)take(2 * (size_t)team_size * 32 * sizeof(double)) : nullptr;
   h.st = (State*)take(2 * sizeof(State));
   h.hist = (Hist*)take(sizeof(Hist));
   h.rec_inner = (int*)take((size_t)o.max_steps * 5 * sizeof(int));
@@ -767,6 +867,10 @@ static int validate_opts(const pfc_opts* o) {
   if (o->model != PFC_MODEL_PFC2 && o->model != PFC_MODEL_PFC1) { set_error("pfc_opts: bad model"); return PFC_ERR_ARG; }
   if (!std::isfinite(o->psi_min)) { set_error("pfc_opts: psi_min must be finite"); return PFC_ERR_ARG; }
   if (o->grid_columns != 0 && o->grid_columns != 1) { set_error("pfc_opts: grid_columns must be 0 or 1"); return PFC_ERR_ARG; }
+  if (o->pcg_steps_per_launch != 1 && o->pcg_steps_per_launch != 2) {
+    set_error("pfc_opts: pcg_steps_per_launch must be 1 or 2");
+    return PFC_ERR_ARG;
+  }
   if (o->gamma_mode != PFC_GAMMA_SCALE_ROW && o->gamma_mode != PFC_GAMMA_LITERAL) {
     set_error("pfc_opts: bad gamma_mode");
     return PFC_ERR_ARG;
@@ -1114,7 +1218,7 @@ void pfc_opts_default(pfc_opts* o) {
   o->model = PFC_MODEL_PFC2;
   o->psi_min = -1.5;
   o->grid_columns = 1;
-  o->reserved = 0;
+  o->pcg_steps_per_launch = 2;
 }
 
 double pfc_tau_critical(double r, double psibar) {

@@ -50,7 +50,7 @@ class pfc_opts(C.Structure):
                 ("ticks_per_graph", C.c_int), ("single_reduction", C.c_int),
                 ("schur_variant", C.c_int), ("sd_iters", C.c_int), ("model", C.c_int), ("psi_min", C.c_double),
                 ("grid_columns", C.c_int), ("gamma_mode", C.c_int), ("inner_fixed", C.c_int * 5),
-                ("reserved", C.c_int)]
+                ("pcg_steps_per_launch", C.c_int)]
 
 
 class pfc_solve_info(C.Structure):

@@ -107,6 +107,11 @@ def test_null_handles_rejected(pfc):
         assert pfc._lib.pfc_instance_footprint(C.c_void_p(1), C.byref(bad)) == 0
     d = pfc.pfc_opts_default()
     assert d.gamma_mode == pfc.PFC_GAMMA_SCALE_ROW and list(d.inner_fixed) == [0] * 5
+    # one or two PCG iterations per launch
+    assert d.pcg_steps_per_launch == 2
+    for bad in (0, 3, -1):
+        o = pfc.pfc_opts_default(pcg_steps_per_launch=bad)
+        assert pfc._lib.pfc_instance_footprint(C.c_void_p(1), C.byref(o)) == 0
 
 
 def test_product_path_does_not_import_oracle():

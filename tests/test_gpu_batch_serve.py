@@ -38,7 +38,8 @@ def test_batch_alone_equals_mix(pfc, prec):
         steps = 1
         for k, pi in enumerate(owners):
             P = probs[pi]
-            o = pfc.pfc_opts_default(precision=prec, shared_ops=1 if pi == 0 else 0)
+            # one PCG iteration per launch alone as in the batch, for the same bits
+            o = pfc.pfc_opts_default(precision=prec, shared_ops=1 if pi == 0 else 0, pcg_steps_per_launch=1)
             insts.append(pfc.pfc_instance_create(P.gpu_mesh(), o))
             psi = wl.psi0(P.n, prm[k].psibar, 0.01, seed=prm[k].seed)
             s0 = np.concatenate([np.zeros(P.n), psi, np.zeros(P.n)])

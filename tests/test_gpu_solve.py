@@ -353,7 +353,8 @@ def test_schur_D_variant_parity(pfc, dim, N, jit, tau, prec):
                                                 (3, 24, 0.1, 0, 4)])
 def test_column_forms_agree_bitwise(pfc, dim, N, jit, prec, rpt):
     """On periodic grids the kernel computes the columns (grid_columns = 1): the same columns in the
-    same order as the stored ones, so a stage solve and a Rosenbrock step give the same bits."""
+    same order as the stored ones, so a stage solve and a Rosenbrock step give the same bits (one PCG
+    iteration per launch in both; the two-iteration form is compared in its own test)."""
     P = Problem(dim, N, jit, seed=61)
     insts = []
     try:
@@ -364,7 +365,8 @@ def test_column_forms_agree_bitwise(pfc, dim, N, jit, prec, rpt):
         out = []
         for g in (1, 0):
             inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(precision=prec, grid_columns=g,
-                                                                              rows_per_thread=rpt))
+                                                                              rows_per_thread=rpt,
+                                                                              pcg_steps_per_launch=1))
             insts.append(inst)
             x = dev(np.zeros(3 * n))
             st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
@@ -412,6 +414,56 @@ def test_gamma_literal_and_fixed_inner_counts(pfc, dim, N, jit, tau):
         got = pfc.pfc_last_inner_counts(inst2)
         assert (got == np.array(fc)).all()
         assert gi["outer_iters"] == info_f["steps"] and rel(host(x), y_f) <= 1e-10
+    finally:
+        for i in insts:
+            pfc.pfc_instance_destroy(i)
+        P.close()
+
+
+# 2D float64 periodic grids: one workgroup smaller than a slice (3^2), one workgroup (16^2, 24^2), several
+# workgroups with a ragged last one (72^2: six workgroups of 896 rows, the last 704), and the halo of
+# N + 1 rows wrapping round the grid in every case
+@pytest.mark.parametrize("N,jit,tau", [(3, 0.2, 0.5), (16, 0.2, 0.1), (24, 0.2, 1.0), (72, 0.2, 1.0)])
+def test_two_pcg_iterations_per_launch(pfc, N, jit, tau):
+    """The s-step form (two PCG iterations per launch) against one iteration per launch and the oracle:
+    the same inner iteration counts and Arnoldi steps, the same solution to rounding, odd fixed counts
+    (a launch that ends after the first of its two iterations), and fewer launches."""
+    P = Problem(2, N, jit, seed=71)
+    insts = []
+    try:
+        r, psibar = -0.35, -0.3
+        n = P.n
+        _, b = _stage1(P, r, tau)
+        res = []
+        for spl in (2, 1):
+            inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(pcg_steps_per_launch=spl))
+            insts.append(inst)
+            x = dev(np.zeros(3 * n))
+            st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
+            assert st == pfc.PFC_OK
+            counts = pfc.pfc_last_inner_counts(inst)
+            launches, _ = pfc.pfc_instance_launch_stats(inst)
+            res.append((host(x), gi, counts, launches))
+        (x2, g2, c2, l2), (x1, g1, c1, l1) = res
+        assert g2["outer_iters"] == g1["outer_iters"] and np.array_equal(c2, c1)
+        assert rel(x2, x1) <= 1e-10 and g2["true_rel_res"] <= 1e-8
+        if g1["inner_total"] >= 200:
+            assert l2 < 0.8 * l1, (l2, l1)
+        # against the oracle under replay of its schedule
+        Nm = assembly.N_matrix(P.mesh, P.psi)
+        y_ref, info = osolve.solve_stage(P.M, P.K, Nm, r, tau, M11, b, tol=1e-8)
+        s = info["schedule"]
+        x = dev(np.zeros(3 * n))
+        st, gi = pfc.pfc_solve(insts[0], n, dev(P.psi), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
+        assert gi["outer_iters"] == info["steps"] and rel(host(x), y_ref) <= 1e-10
+        # odd and even fixed counts, including 1
+        fixed = [3, 1, 4, 5, 2]
+        y_fix, info_f = osolve.solve_stage(P.M, P.K, Nm, r, tau, M11, b, tol=1e-8, inner_fixed=fixed, max_steps=6)
+        inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(inner_fixed=fixed, max_steps=6))
+        insts.append(inst)
+        x = dev(np.zeros(3 * n))
+        st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
+        assert gi["outer_iters"] == info_f["steps"] and rel(host(x), y_fix) <= 1e-10
     finally:
         for i in insts:
             pfc.pfc_instance_destroy(i)
