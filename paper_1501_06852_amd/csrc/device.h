@@ -129,14 +129,30 @@ __device__ __forceinline__ void for_width(int w, F f) {
 #define PFC_STORE_POLICY 1
 #endif
 
+// Every phase output and every operand lives in device memory (never LDS).  The
+// solver's pointers come from the instance record in LDS, so the compiler cannot
+// see that and issues flat accesses, which count against the LDS wait counter as
+// well and complete in no guaranteed order: every wait for an LDS access then
+// also waits for all memory accesses in flight.  Stores, and the loads of the
+// phases that issue loads ahead of their use, therefore name the global address
+// space explicitly.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gp(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+
 template <typename T>
 __device__ __forceinline__ void vst(T* p, T v) {
 #if PFC_STORE_POLICY == 1
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #elif PFC_STORE_POLICY == 2
-  __builtin_nontemporal_store(v, p);
+  __builtin_nontemporal_store(v, gp(p));
 #else
-  *p = v;
+  *gp(p) = v;
 #endif
 }
 
@@ -537,6 +553,10 @@ __device__ __forceinline__ PatView<L> op_pat(const InstDev& I, const PcgOps<T>& 
 template <typename T>
 __device__ __forceinline__ T opval(const PcgOps<T>& o, long long e) {
   return o.C ? o.C[e] : (o.Mv[e] + o.cK * o.Kv[e]);
+}
+template <typename T>
+__device__ __forceinline__ T opval_g(const PcgOps<T>& o, long long e) {
+  return o.C ? gld(o.C + e) : (gld(o.Mv + e) + o.cK * gld(o.Kv + e));
 }
 
 // y_i = (A v)_i for a stored operator A (typed) over the row of thread lane
@@ -941,10 +961,12 @@ __device__ __forceinline__ Red3 ph_cg_iter(const InstDev& I, const State& S, con
 // rows (mod n) on 2D periodic grids, whose neighbours lie within N + 1 rows.
 #define PFC_SS_LDS 8192
 #define PFC_SS_NG 25  // 15 entries of G, 10 of H
+#define PFC_SS_NA 4   // passes of a workgroup over the two-step halo (R + 4H <= 4096 rows)
+#define PFC_SS_NB 3   // passes over the one-step halo (R + 2H <= 3072 rows); 7 entries per row
 __shared__ double pfc_ss[PFC_SS_LDS];
-__shared__ double pfc_ssred[32 * 32];
+__shared__ double pfc_ssred[64 * 32];
 #ifdef PFC_TICK_TIMING
-__shared__ unsigned long long pfc_sst[4];  // optional instrumentation (separate build only)
+__shared__ unsigned long long pfc_sst[6];  // optional instrumentation (separate build only)
 #define PFC_SS_STAMP(k) \
   if (threadIdx.x == 0) pfc_sst[k] = wall_clock64()
 #else
@@ -978,6 +1000,62 @@ __device__ __forceinline__ double dpp_wave_sum(double v) {
   return v + dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
 }
 
+// Workgroup barrier that orders LDS only: the global loads and stores of the
+// two-iterations-per-launch phase are never read back within the launch, so
+// loads issued ahead stay in flight across it (a full __syncthreads would wait
+// for every outstanding memory operation).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Halving exchange between the lanes of a pair: the lane that keeps the lower
+// half returns a + (partner's a), the other b + (partner's b).  Partners: lanes
+// l and l ^ 32 (permlane32 swap), rows 2k and 2k + 1 (permlane16 swap), or the
+// DPP pairs of CTRL within a row.
+__device__ __forceinline__ double ss_pair(unsigned hi, unsigned lo) {
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <bool ROWS16>
+__device__ __forceinline__ double ss_swap(double a, double b, bool upper) {
+  const unsigned long long ia = (unsigned long long)__double_as_longlong(a), ib = (unsigned long long)__double_as_longlong(b);
+  if constexpr (ROWS16) {
+    const auto l = __builtin_amdgcn_permlane16_swap((unsigned)ia, (unsigned)ib, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap((unsigned)(ia >> 32), (unsigned)(ib >> 32), false, false);
+    return upper ? b + ss_pair(h[0], l[0]) : a + ss_pair(h[1], l[1]);
+  } else {
+    const auto l = __builtin_amdgcn_permlane32_swap((unsigned)ia, (unsigned)ib, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap((unsigned)(ia >> 32), (unsigned)(ib >> 32), false, false);
+    return upper ? b + ss_pair(h[0], l[0]) : a + ss_pair(h[1], l[1]);
+  }
+}
+template <int CTRL>
+__device__ __forceinline__ double ss_dppx(double a, double b, bool upper) {
+  return (upper ? b : a) + dpp_f64<CTRL, 0xf>(upper ? a : b);
+}
+// Sums of 32 values over the 64 lanes of a wave by recursive halving (32 value
+// exchanges in all instead of 6 per value): the total of value idx ends in lanes
+// 2m and 2m + 1 with idx = 16 [l >= 32] + 8 [row odd] + 4 [l mod 16 >= 8] +
+// 2 [l mod 8 >= 4] + [l & 2].  Returns the total of the lane's idx.
+__device__ __forceinline__ double ss_wave_sums32(const double* v, int lane) {
+  double w16[16], w8[8], w4[4], w2[2];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) w16[k] = ss_swap<false>(v[k], v[k + 16], lane >= 32);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) w8[k] = ss_swap<true>(w16[k], w16[k + 8], (lane >> 4) & 1);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w4[k] = ss_dppx<0x140>(w8[k], w8[k + 4], (lane & 15) >= 8);  // row_mirror
+#pragma unroll
+  for (int k = 0; k < 2; ++k) w2[k] = ss_dppx<0x141>(w4[k], w4[k + 2], (lane & 7) >= 4);   // row_half_mirror
+  const double w1 = ss_dppx<0x4e>(w2[0], w2[1], (lane & 2) != 0);                          // quad_perm [2,3,0,1]
+  return w1 + dpp_f64<0xb1, 0xf>(w1);                                                      // quad_perm [1,0,3,2]
+}
+__device__ __forceinline__ int ss_wave_sums32_index(int lane) {
+  return (lane >= 32 ? 16 : 0) + (((lane >> 4) & 1) ? 8 : 0) + ((lane & 15) >= 8 ? 4 : 0) + ((lane & 7) >= 4 ? 2 : 0) +
+         ((lane & 2) ? 1 : 0);
+}
+
 __device__ __forceinline__ int ss_wrap(int g, int n) { return g < 0 ? g + n : (g >= n ? g - n : g); }
 // offset j - g of a neighbour as a step within the grid (|step| <= N + 1 < n / 2)
 __device__ __forceinline__ int ss_step(int d, int n) { return d > (n >> 1) ? d - n : (d < -(n >> 1) ? d + n : d); }
@@ -985,90 +1063,171 @@ __device__ __forceinline__ int ss_step(int d, int n) { return d > (n >> 1) ? d -
 // upper-triangle index of (i, j), i <= j, in a k x k symmetric matrix
 __host__ __device__ __forceinline__ int ss_tri(int i, int j, int k) { return i * k - i * (i - 1) / 2 + (j - i); }
 
-// coef: x increment [0..4], new p [5..9], new u [10..14] over B; final: x only.
+// Rows of a workgroup in the two-iterations-per-launch form: own rows [lo, lo + R)
+// (at most PFC_WG), halo H; thread tid's passes over the two-step halo are
+// q = tid + c PFC_WG, and its own row (if any) is pass position qo.
+struct SsRows {
+  int lo, R, H, L1, L2, qo, go;
+  bool own;
+};
+__device__ __forceinline__ SsRows ss_rows(const InstDev& I, int rank, int size) {
+  SsRows w;
+  const int n = I.n;
+  const int spw = (I.m.n_slices + size - 1) / size;
+  w.lo = min(rank * spw * 64, n);
+  w.R = min(w.lo + spw * 64, n) - w.lo;
+  w.H = I.sH;
+  w.L1 = w.R + 2 * w.H;
+  w.L2 = w.R + 4 * w.H;
+  const int tid = threadIdx.x;
+  w.qo = 2 * w.H + (((tid - 2 * w.H) % PFC_WG) + PFC_WG) % PFC_WG;
+  w.own = w.qo < 2 * w.H + w.R;
+  w.go = w.lo + (w.qo - 2 * w.H);
+  return w;
+}
+
+// Loads of the current basis on the two-step halo (and x on the own row), issued
+// before the launch's reductions so that their latency overlaps them.
+struct SsPre {
+  double bv[PFC_SS_NA][5];
+  double xo;
+};
+__device__ __forceinline__ void ss_load(const InstDev& I, const State& S, const SsRows& w, SsPre& P) {
+  const int n = I.n;
+  const long long nn = n;
+  const int tid = threadIdx.x;
+  const double* bin = I.sbas + (long long)S.cur * 5 * nn;  // the basis of the previous launch
+#pragma unroll
+  for (int c = 0; c < PFC_SS_NA; ++c) {
+    const int g = ss_wrap(w.lo - 2 * w.H + min(tid + c * PFC_WG, w.L2 - 1), n);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) P.bv[c][k] = gld(bin + k * nn + g);
+  }
+  P.xo = gld(pcg_ops<double>(I, S.kind).x + min(w.go, n - 1));  // used on the own row only
+}
+
+// coef: x increment [0..4], new p [5..9], new u [10..14] over B; S.pcur: x only.
 template <int L>
 __device__ __forceinline__ void ph_scg(const InstDev& I, const State& S, const Team& tm, const double* coef, bool init,
-                                       double* spart_out) {
-  const int n = I.n, H = I.sH;
+                                       double* spart_out, const SsRows& w, SsPre& P) {
+  const int n = I.n, H = w.H, R = w.R, L1 = w.L1, L2 = w.L2, lo = w.lo;
   PcgOps<double> o = pcg_ops<double>(I, S.kind);
   const PatView<L> pv = op_pat<L>(I, o, tm);
   const int uw = pv.uw;
-  const int spw = (I.m.n_slices + tm.size - 1) / tm.size;
-  const int lo = min(tm.rank * spw * 64, n);
-  const int R = min(lo + spw * 64, n) - lo;  // own rows [lo, lo + R), at most PFC_WG
-  const int L1 = R + 2 * H, L2 = R + 4 * H;
   const int tid = threadIdx.x;
   const long long nn = n;
-  const double* bin = I.sbas + (long long)(S.cur ^ 1) * 5 * nn;
   double* bout = I.sbas + (long long)S.cur * 5 * nn;
+  if (init) {  // u_0 = p_0 = D^{-1} r_0
+    const double* r = (const double*)I.r_;
+#pragma unroll
+    for (int c = 0; c < PFC_SS_NA; ++c) {
+      const int g = ss_wrap(lo - 2 * H + min(tid + c * PFC_WG, L2 - 1), n);
+      P.bv[c][0] = gld(o.dinv + g);
+      P.bv[c][1] = gld(r + g);
+    }
+  }
   if (!init && S.pcur) {  // the solve ends within these two iterations: x only
-    for (int q = tid; q < R; q += PFC_WG) {
-      const int g = lo + q;
-      vst(o.x + g, o.x[g] + (coef[0] * bin[g] + coef[1] * bin[nn + g] + coef[3] * bin[3 * nn + g]));
+    if (w.own) {
+#pragma unroll
+      for (int c = 0; c < PFC_SS_NA; ++c)
+        if (tid + c * PFC_WG == w.qo)
+          vst(o.x + w.go, P.xo + (coef[0] * P.bv[c][0] + coef[1] * P.bv[c][1] + coef[3] * P.bv[c][3]));
     }
     return;
   }
   double* sp = pfc_ss;     // new p on [lo - 2H, lo + R + 2H)
   double* su = sp + L2;    // new u on [lo - H, lo + R + H)
   double* stp = su + L1;   // T p on [lo - H, lo + R + H)
-  const double* r = (const double*)I.r_;
-  for (int q = tid; q < L2; q += PFC_WG) {
-    const int g = ss_wrap(lo - 2 * H + q, n);
-    const bool own = q >= 2 * H && q < 2 * H + R;
-    double pn, un;
-    if (init) {
-      pn = o.dinv[g] * r[g];
-      un = pn;
-    } else {
-      const double b0 = bin[g], b1 = bin[nn + g], b2 = bin[2 * nn + g], b3 = bin[3 * nn + g], b4 = bin[4 * nn + g];
-      pn = coef[5] * b0 + coef[6] * b1 + coef[7] * b2 + coef[8] * b3 + coef[9] * b4;
-      un = coef[10] * b0 + coef[11] * b1 + coef[12] * b2 + coef[13] * b3 + coef[14] * b4;
-      if (own) vst(o.x + g, o.x[g] + (coef[0] * b0 + coef[1] * b1 + coef[3] * b3));
+#pragma unroll
+  for (int c = 0; c < PFC_SS_NA; ++c) {
+    const int q = tid + c * PFC_WG;
+    if (q < L2) {
+      const double* b = P.bv[c];
+      double pn, un;
+      if (init) {
+        pn = b[0] * b[1];
+        un = pn;
+      } else {
+        pn = coef[5] * b[0] + coef[6] * b[1] + coef[7] * b[2] + coef[8] * b[3] + coef[9] * b[4];
+        un = coef[10] * b[0] + coef[11] * b[1] + coef[12] * b[2] + coef[13] * b[3] + coef[14] * b[4];
+      }
+      sp[q] = pn;
+      if (q >= H && q < H + L1) su[q - H] = un;
+      if (q == w.qo && w.own) {
+        if (!init) vst(o.x + w.go, P.xo + (coef[0] * b[0] + coef[1] * b[1] + coef[3] * b[3]));
+        vst(bout + w.go, pn);
+        vst(bout + 3 * nn + w.go, un);
+      }
     }
-    sp[q] = pn;
-    if (q >= H && q < H + L1) su[q - H] = un;
-    if (own) { vst(bout + g, pn); vst(bout + 3 * nn + g, un); }
   }
-  __syncthreads();
+  // operator rows of the one-step halo (two passes; the rows past 2 PFC_WG, if
+  // any, load after the barrier), in flight across it
+  double av[2][7], dv[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int g = ss_wrap(lo - H + min(tid + c * PFC_WG, L1 - 1), n);
+    const int base = (g >> 6) * 64 * 7 + (g & 63);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) av[c][k] = opval_g(o, (long long)base + k * 64);
+    dv[c] = gld(o.dinv + g);
+  }
+  lds_barrier();
   PFC_SS_STAMP(0);
   // T p on the one-step halo; T u on the own rows (at most one own row per thread)
   int q1o = -1;
-  double tpo = 0.0, tuo = 0.0, dgo = 0.0;
-  for (int q1 = tid; q1 < L1; q1 += PFC_WG) {
+  double tpo = 0.0, tuo = 0.0, dgo = 0.0, dvo = 0.0;
+  double ao[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) ao[k] = 0.0;
+  auto trow = [&](int q1, const double* a, double di) {
     const int g = ss_wrap(lo - H + q1, n);
     const bool own = q1 >= H && q1 < H + R;
-    const int base = (g >> 6) * 64 * uw + (g & 63);
+    const int base = (g >> 6) * 64 * 7 + (g & 63);
     double acc = 0.0, acc2 = 0.0, dg = 0.0;
-    for_width(uw, [&](int k) {
-      const long long e = (long long)base + k * 64;
-      const int d = ss_step(pv.at(e, g) - g, n);
-      const double a = opval(o, e);
-      acc += a * sp[q1 + H + d];
-      if (own) acc2 += a * su[q1 + d];
-      dg += d == 0 ? a : 0.0;
-    });
-    const double tp = o.dinv[g] * acc;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      const int d = ss_step(pv.at((long long)base + k * 64, g) - g, n);
+      acc += a[k] * sp[q1 + H + d];
+      dg += d == 0 ? a[k] : 0.0;
+    }
+    if (own) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) acc2 += a[k] * su[q1 + ss_step(pv.at((long long)base + k * 64, g) - g, n)];
+    }
+    const double tp = di * acc;
     stp[q1] = tp;
     if (own) {
-      q1o = q1; tpo = tp; tuo = o.dinv[g] * acc2; dgo = dg;
+      q1o = q1; tpo = tp; tuo = di * acc2; dgo = dg; dvo = di;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) ao[k] = a[k];
       vst(bout + nn + g, tpo);
       vst(bout + 4 * nn + g, tuo);
     }
+  };
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+    if (tid + c * PFC_WG < L1) trow(tid + c * PFC_WG, av[c], dv[c]);
+  if (tid + 2 * PFC_WG < L1) {  // third pass (at most PFC_SS_NB): loads here
+    const int q1 = tid + 2 * PFC_WG;
+    const int g = ss_wrap(lo - H + q1, n);
+    const int base = (g >> 6) * 64 * 7 + (g & 63);
+    double a3[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) a3[k] = opval_g(o, (long long)base + k * 64);
+    trow(q1, a3, gld(o.dinv + g));
   }
-  __syncthreads();
+  lds_barrier();
   PFC_SS_STAMP(1);
   double gp[PFC_SS_NG];
 #pragma unroll
   for (int m = 0; m < PFC_SS_NG; ++m) gp[m] = 0.0;
   if (q1o >= 0) {
     const int g = lo + (q1o - H);
-    const int base = (g >> 6) * 64 * uw + (g & 63);
+    const int base = (g >> 6) * 64 * 7 + (g & 63);
     double acc = 0.0;
-    for_width(uw, [&](int k) {
-      const long long e = (long long)base + k * 64;
-      acc += opval(o, e) * stp[q1o + ss_step(pv.at(e, g) - g, n)];
-    });
-    const double ttp = o.dinv[g] * acc;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) acc += ao[k] * stp[q1o + ss_step(pv.at((long long)base + k * 64, g) - g, n)];
+    const double ttp = dvo * acc;
     vst(bout + 2 * nn + g, ttp);
     const double v[5] = {sp[q1o + H], tpo, ttp, su[q1o], tuo};
 #pragma unroll
@@ -1085,14 +1244,18 @@ __device__ __forceinline__ void ph_scg(const InstDev& I, const State& S, const T
     }
   }
   PFC_SS_STAMP(2);
-  // workgroup sums, fixed order: lanes within a wave (DPP), then the waves
+  // workgroup sums, fixed order: over each wave by recursive halving, then over
+  // the waves
   const int lane = tid & 63, wave = tid >> 6;
+  {
+    double v32[32];
 #pragma unroll
-  for (int m = 0; m < PFC_SS_NG; ++m) {
-    const double w = dpp_wave_sum(gp[m]);
-    if (lane == 63) pfc_ssred[wave * 32 + m] = w;
+    for (int m = 0; m < 32; ++m) v32[m] = m < PFC_SS_NG ? gp[m] : 0.0;
+    const double tot = ss_wave_sums32(v32, lane);
+    const int idx = ss_wave_sums32_index(lane);
+    if ((lane & 1) == 0) pfc_ssred[wave * 32 + idx] = tot;
   }
-  __syncthreads();
+  lds_barrier();
   if (tid < PFC_SS_NG) {
     double t = 0.0;
 #pragma unroll
@@ -1103,18 +1266,33 @@ __device__ __forceinline__ void ph_scg(const InstDev& I, const State& S, const T
 }
 
 // Sum of the Gram partials of a team ([size][32], fixed order) into g[0..24].
-__device__ __forceinline__ void ss_gram(const double* part, int size, double* g) {
+// Issued before the basis loads (the memory counters complete in order, so the
+// reduction then waits for these loads only); teams of more than 256 add the rest.
+#define PFC_SS_GL 8
+__device__ __forceinline__ void ss_gram_load(const double* part, int size, double* pl) {
+  const int tid = threadIdx.x, v = tid & 31, grp = tid >> 5;
+  // unconditional loads at clamped positions (straight-line code keeps the wait
+  // for them separate from the later loads), masked afterwards
+#pragma unroll
+  for (int c = 0; c < PFC_SS_GL; ++c) {
+    const int k = min(grp + 32 * c, size - 1);
+    pl[c] = gld(part + (long long)k * 32 + min(v, PFC_SS_NG - 1));
+  }
+}
+__device__ __forceinline__ void ss_gram(const double* part, int size, const double* pl, double* g) {
   const int tid = threadIdx.x, v = tid & 31, grp = tid >> 5;
   double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < PFC_SS_GL; ++c) s += (v < PFC_SS_NG && grp + 32 * c < size) ? pl[c] : 0.0;
   if (v < PFC_SS_NG)
-    for (int k = grp; k < size; k += 32) s += part[(long long)k * 32 + v];
+    for (int k = grp + 32 * PFC_SS_GL; k < size; k += 32) s += gld(part + (long long)k * 32 + v);
   pfc_ssred[grp * 32 + v] = s;
-  __syncthreads();
+  lds_barrier();
   // wave w sums value w over the 32 groups in lanes 0-31 and value w + 16 in lanes 32-63
   const int lane = tid & 63, w = tid >> 6, vv = w + (lane >> 5) * 16;
   const double t = dpp_half_sum(vv < PFC_SS_NG ? pfc_ssred[(lane & 31) * 32 + vv] : 0.0);
   if ((lane & 31) == 31 && vv < PFC_SS_NG) g[vv] = t;
-  __syncthreads();
+  lds_barrier();
 }
 
 }  // namespace pfc

@@ -233,43 +233,43 @@ __device__ void scg_transition(State& S, const InstDev& I, bool wr, const double
   if (S.phase == PH_SCG_ITER && S.pcur) { pcg_done(S, I, wr); return; }
   S.phase = PH_SCG_ITER;
   S.cur ^= 1;
-  double G[5][5], Hm[5][5];
-  for (int i = 0; i < 5; ++i)
-    for (int j = 0; j < 5; ++j) {
-      const int a = i < j ? i : j, b = i < j ? j : i;
-      G[i][j] = g[ss_tri(a, b, 5)];
-      Hm[i][j] = a == 0 ? 0.0 : g[15 + ss_tri(a - 1, b - 1, 4)];
-    }
-  auto form = [](const double* x, const double* y, const double (*M)[5]) {
-    double s = 0.0;
-    for (int i = 0; i < 5; ++i)
-      for (int j = 0; j < 5; ++j) s += x[i] * M[i][j] * y[j];
-    return s;
-  };
+  // entries (i <= j) of G = B^T D B and of H = B'^T D^2 B' (basis indices 1..4)
+  auto G = [&](int i, int j) { return g[ss_tri(i, j, 5)]; };
+  auto Hq = [&](int i, int j) { return g[15 + ss_tri(i - 1, j - 1, 4)]; };
   for (int m = 0; m < 15; ++m) coef[m] = 0.0;
   bool fixed; double tol;
   const int lim = inner_limit(I, S, fixed, tol);
-  const double rho0 = G[3][3];
-  const double a0 = rho0 / G[0][1];
-  const double u1[5] = {0.0, -a0, 0.0, 1.0, 0.0};
-  const double rho1 = form(u1, u1, G), rr1 = form(u1, u1, Hm);
+  // first iteration: alpha_0 = <u,u> / <p,Tp>, u_1 = u - alpha_0 Tp
+  const double rho0 = G(3, 3);
+  const double a0 = rho0 / G(0, 1);
+  const double rho1 = G(3, 3) - 2.0 * a0 * G(1, 3) + a0 * a0 * G(1, 1);
+  const double rr1 = Hq(3, 3) - 2.0 * a0 * Hq(1, 3) + a0 * a0 * Hq(1, 1);
   coef[0] = a0;
   S.it += 1;
   S.pcur = 1;
   if (S.it >= lim || (!fixed && rr1 <= tol * tol * S.bb) || rho1 == 0.0 || !isfinite(rr1)) return;
+  // second: p_1 = u_1 + beta_0 p = b0 e0 - a0 e1 + e3, T p_1 = b0 e1 - a0 e2 + e4
   const double b0 = rho1 / rho0;
-  const double p1[5] = {b0, -a0, 0.0, 1.0, 0.0}, tp1[5] = {0.0, b0, -a0, 0.0, 1.0};
-  const double a1 = rho1 / form(p1, tp1, G);
-  double u2[5];
-  for (int k = 0; k < 5; ++k) u2[k] = u1[k] - a1 * tp1[k];
-  const double rho2 = form(u2, u2, G), rr2 = form(u2, u2, Hm);
-  coef[0] = a0 + a1 * p1[0];
-  coef[1] = a1 * p1[1];
-  coef[3] = a1 * p1[3];
+  const double ptp = b0 * (b0 * G(0, 1) - a0 * G(0, 2) + G(0, 4)) - a0 * (b0 * G(1, 1) - a0 * G(1, 2) + G(1, 4)) +
+                     (b0 * G(1, 3) - a0 * G(2, 3) + G(3, 4));
+  const double a1 = rho1 / ptp;
+  // u_2 = u_1 - alpha_1 T p_1 = c1 e1 + c2 e2 + e3 + c4 e4
+  const double c1 = -a0 - a1 * b0, c2 = a1 * a0, c4 = -a1;
+  auto quad = [&](auto M) {
+    return c1 * c1 * M(1, 1) + c2 * c2 * M(2, 2) + M(3, 3) + c4 * c4 * M(4, 4) +
+           2.0 * (c1 * c2 * M(1, 2) + c1 * M(1, 3) + c1 * c4 * M(1, 4) + c2 * M(2, 3) + c2 * c4 * M(2, 4) + c4 * M(3, 4));
+  };
+  const double rho2 = quad(G), rr2 = quad(Hq);
+  // x += alpha_0 p + alpha_1 p_1
+  coef[0] = a0 + a1 * b0;
+  coef[1] = -a1 * a0;
+  coef[3] = a1;
   S.it += 1;
   if (S.it >= lim || (!fixed && rr2 <= tol * tol * S.bb) || rho2 == 0.0 || !isfinite(rr2)) return;
+  // p_2 = u_2 + beta_1 p_1, u_2
   const double b1 = rho2 / rho1;
-  for (int k = 0; k < 5; ++k) { coef[5 + k] = u2[k] + b1 * p1[k]; coef[10 + k] = u2[k]; }
+  coef[5] = b1 * b0; coef[6] = c1 - b1 * a0; coef[7] = c2; coef[8] = 1.0 + b1; coef[9] = c4;
+  coef[11] = c1; coef[12] = c2; coef[13] = 1.0; coef[14] = c4;
   S.pcur = 0;
 }
 
@@ -515,13 +515,26 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     return;
   }
   bool scg = false;
+  SsPre ssp;
   if constexpr (SS) {
     scg = (S.phase == PH_SCG_INIT || S.phase == PH_SCG_ITER);
-    if (scg && !(S.phase == PH_SCG_ITER && S.pcur)) ss_gram(I.spart + (long long)S.cur * te.size * 32, te.size, ss_g);
+    if (scg && !(S.phase == PH_SCG_ITER && S.pcur)) {
+      const double* gpart = I.spart + (long long)S.cur * te.size * 32;
+      double pl[PFC_SS_GL];
+      ss_gram_load(gpart, te.size, pl);
+      ss_load(I, S, ss_rows(I, te.rank, te.size), ssp);  // in flight during the reduction and the transition
+      ss_gram(gpart, te.size, pl, ss_g);
+#ifdef PFC_TICK_TIMING
+      if (tid == 0) pfc_sst[4] = wall_clock64();
+#endif
+    }
   }
   if (tid == 0) {
     if (scg) {
       if constexpr (SS) scg_transition(S, I, writer, ss_g, ss_coef);
+#ifdef PFC_TICK_TIMING
+      if constexpr (SS) pfc_sst[5] = wall_clock64();
+#endif
     } else {
       Red3 red = red3(0.0, 0.0, 0.0);
       if (phase_partials(S.phase)) {
@@ -531,7 +544,12 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
       if (!cg_iter_continues(S, I, red)) transition(S, I, writer, red, ybuf, gcol, SS && I.sstep);
     }
   }
-  __syncthreads();
+  if constexpr (SS) {
+    if (scg) lds_barrier();  // the basis loads issued in the prologue stay in flight
+    else __syncthreads();
+  } else {
+    __syncthreads();
+  }
   PFC_STAMP(t_trans);
   // the new state is final: workgroup 0 stores it while the phase runs
   if (writer && tid < NS) ((int*)st_out)[tid] = ((const int*)&S)[tid];
@@ -562,7 +580,8 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     case PH_SCG_INIT:
     case PH_SCG_ITER:
       if constexpr (SS)
-        ph_scg<COLS>(I, S, tm, ss_coef, S.phase == PH_SCG_INIT, I.spart + (long long)S.cur * te.size * 32);
+        ph_scg<COLS>(I, S, tm, ss_coef, S.phase == PH_SCG_INIT, I.spart + (long long)S.cur * te.size * 32,
+                     ss_rows(I, te.rank, te.size), ssp);
       break;
     default: break;
   }
@@ -590,11 +609,11 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   if (tid == 0 && (te.rank == 0 || te.rank == te.size - 1) && g_trace) {
     const unsigned long long k = atomicAdd(&g_trace_n, 1ULL);
     if (k < g_trace_cap) {
-      unsigned long long* r = g_trace + 12 * k;
+      unsigned long long* r = g_trace + 14 * k;
       r[0] = (unsigned long long)S.phase | ((unsigned long long)te.rank << 8) | ((unsigned long long)S.kind << 40) |
              ((unsigned long long)(S.it & 0xffff) << 48);
       r[1] = t_entry; r[2] = t_ld; r[3] = t_trans; r[4] = t_work; r[5] = t_exit; r[6] = blockIdx.x; r[7] = t_red;
-      for (int q = 0; q < 4; ++q) r[8 + q] = (SS && (S.phase == PH_SCG_INIT || S.phase == PH_SCG_ITER)) ? pfc_sst[q] : 0;
+      for (int q = 0; q < 6; ++q) r[8 + q] = (SS && (S.phase == PH_SCG_INIT || S.phase == PH_SCG_ITER)) ? pfc_sst[q] : 0;
     }
   }
 #endif
@@ -771,13 +790,14 @@ __global__ void k_stage_rhs(InstDev I, int stage, double* __restrict__ b) {
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Halo of the two-iterations-per-launch PCG (N + 1 rows), or 0 where it does not
-// apply: float64 single-reduction instances on 2D periodic grids with computed
-// columns, at most PFC_WAVES slices per workgroup, every neighbour within N + 1
-// rows of its row (mod n), and the three LDS arrays within PFC_SS_LDS.
+// apply: float64 single-reduction instances on 2D periodic grids (7 entries per
+// row) with computed columns, at most PFC_WAVES slices per workgroup, every
+// neighbour within N + 1 rows of its row (mod n), the three LDS arrays within
+// PFC_SS_LDS and the halo ranges within the kernel's unrolled passes.
 static int sstep_halo(const pfc_mesh* m, const pfc_opts& o, int team_size) {
   const MeshDev& d = m->dev;
   if (o.pcg_steps_per_launch != 2 || o.precision != PFC_FP64 || o.single_reduction != 1 || o.grid_columns != 1) return 0;
-  if (d.dim != 2 || d.gN < 3 || d.uw < 1 || team_size < 1) return 0;
+  if (d.dim != 2 || d.gN < 3 || d.uw != 7 || team_size < 1) return 0;
   const int spw = (d.n_slices + team_size - 1) / team_size;
   if (spw > PFC_WAVES) return 0;
   const int n = d.n, H = d.gN + 1;
@@ -789,7 +809,7 @@ static int sstep_halo(const pfc_mesh* m, const pfc_opts& o, int team_size) {
       if (s > H || s < -H) return 0;
     }
   const int rmax = std::min(spw * 64, n);
-  if (3 * rmax + 8 * H > PFC_SS_LDS) return 0;
+  if (3 * rmax + 8 * H > PFC_SS_LDS || rmax + 4 * H > PFC_SS_NA * PFC_WG || rmax + 2 * H > PFC_SS_NB * PFC_WG) return 0;
   return H;
 }
 
