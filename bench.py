@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # was taken on: when their digest differs, `traffic` is reported as null.
 TRAFFIC = {
     # workload: (sha256 of the kernel sources, bytes per launch, algorithmic bytes per launch of the same run)
-    "pfc2d_512_fp64": ("bb883c337584e49e583b0b4f0ba75726a98714c2952df7a2ff2cccee4cc6a4c7", 34201080.0, 37986008.0),
-    "pfc3d_64_mixed": ("bb883c337584e49e583b0b4f0ba75726a98714c2952df7a2ff2cccee4cc6a4c7", 30416156.0, 37670502.0),
+    "pfc2d_512_fp64": ("b07215e0002a65e8f728cfef5e76eddf7dcbb10e0e2755370485305e62fc71a7", 34714714.0, 59487522.0),
+    "pfc3d_64_mixed": ("b07215e0002a65e8f728cfef5e76eddf7dcbb10e0e2755370485305e62fc71a7", 30401861.0, 37670502.0),
 }
 
 
@@ -446,7 +446,8 @@ def main():
                    "stage_solves": solves, "restart": 30, "outer_tol": 1e-8, "inner_tol": 1e-3,
                    "element_degree": mesh.degree, "model": "PFC1" if model == 1 else "PFC2",
                    "schur": "S_D" if schur else "S_CH", "initial_state": "smooth" if "smooth" in var else "noise",
-                   "columns": (f"computed from the row (periodic grid, side {gside})" if gside else "read from memory")},
+                   "columns": (f"computed from the row (periodic grid, side {gside})" if gside else "read from memory"),
+                   "pcg_steps_per_launch": opts.pcg_steps_per_launch},
         "status": pfc.pfc_status_str(st),
         "max_true_rel_res": max(res) if res else None,
         "outer_iters_mean": float(np.mean([i["outer_iters"] for i in infos])),

@@ -1160,9 +1160,9 @@ __device__ __forceinline__ void ph_scg(const InstDev& I, const State& S, const T
       }
     }
   }
-  // operator rows of the one-step halo (two passes; the rows past 2 PFC_WG, if
-  // any, load after the barrier), in flight across it
-  double av[2][7], dv[2];
+  // operator rows of the one-step halo (at most three passes; the third, if any,
+  // holds a few rows of the first wave), in flight across the barrier
+  double av[3][7], dv[3];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const int g = ss_wrap(lo - H + min(tid + c * PFC_WG, L1 - 1), n);
@@ -1170,6 +1170,13 @@ __device__ __forceinline__ void ph_scg(const InstDev& I, const State& S, const T
 #pragma unroll
     for (int k = 0; k < 7; ++k) av[c][k] = opval_g(o, (long long)base + k * 64);
     dv[c] = gld(o.dinv + g);
+  }
+  if (L1 > 2 * PFC_WG && tid < 64) {
+    const int g = ss_wrap(lo - H + min(tid + 2 * PFC_WG, L1 - 1), n);
+    const int base = (g >> 6) * 64 * 7 + (g & 63);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) av[2][k] = opval_g(o, (long long)base + k * 64);
+    dv[2] = gld(o.dinv + g);
   }
   lds_barrier();
   PFC_SS_STAMP(0);
@@ -1207,14 +1214,18 @@ __device__ __forceinline__ void ph_scg(const InstDev& I, const State& S, const T
 #pragma unroll
   for (int c = 0; c < 2; ++c)
     if (tid + c * PFC_WG < L1) trow(tid + c * PFC_WG, av[c], dv[c]);
-  if (tid + 2 * PFC_WG < L1) {  // third pass (at most PFC_SS_NB): loads here
-    const int q1 = tid + 2 * PFC_WG;
-    const int g = ss_wrap(lo - H + q1, n);
-    const int base = (g >> 6) * 64 * 7 + (g & 63);
-    double a3[7];
+  if (tid + 2 * PFC_WG < L1) {  // third pass (at most PFC_SS_NB)
+    if (tid < 64) {
+      trow(tid + 2 * PFC_WG, av[2], dv[2]);
+    } else {
+      const int q1 = tid + 2 * PFC_WG;
+      const int g = ss_wrap(lo - H + q1, n);
+      const int base = (g >> 6) * 64 * 7 + (g & 63);
+      double a3[7];
 #pragma unroll
-    for (int k = 0; k < 7; ++k) a3[k] = opval_g(o, (long long)base + k * 64);
-    trow(q1, a3, gld(o.dinv + g));
+      for (int k = 0; k < 7; ++k) a3[k] = opval_g(o, (long long)base + k * 64);
+      trow(q1, a3, gld(o.dinv + g));
+    }
   }
   lds_barrier();
   PFC_SS_STAMP(1);

@@ -19,6 +19,11 @@ LIB_PATH = os.path.join(_HERE, "libpfc.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1501_06852_amd.build` (or __graft_entry__.build())")
 
+# torch first: its ROCm build carries its own HIP runtime, which must be the one
+# loaded in the process before this library binds to libamdhip64 (the other
+# order leaves torch's runtime without a device)
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 # status codes (pfc.h)
