@@ -960,7 +960,7 @@ __device__ __forceinline__ Red3 ph_cg_iter(const InstDev& I, const State& S, con
 // step around, T^2 p and Tu on its own rows.  The halo is a contiguous range of
 // rows (mod n) on 2D periodic grids, whose neighbours lie within N + 1 rows.
 #define PFC_SS_LDS 8192
-#define PFC_SS_NG 25  // 15 entries of G, 10 of H
+#define PFC_SS_NG 26  // 15 entries of G, 10 of H, and ||b||^2 in the first launch of a solve
 #define PFC_SS_NA 4   // passes of a workgroup over the two-step halo (R + 4H <= 4096 rows)
 #define PFC_SS_NB 3   // passes over the one-step halo (R + 2H <= 3072 rows); 7 entries per row
 __shared__ double pfc_ss[PFC_SS_LDS];
@@ -1117,13 +1117,57 @@ __device__ __forceinline__ void ph_scg(const InstDev& I, const State& S, const T
   const int tid = threadIdx.x;
   const long long nn = n;
   double* bout = I.sbas + (long long)S.cur * 5 * nn;
-  if (init) {  // u_0 = p_0 = D^{-1} r_0
-    const double* r = (const double*)I.r_;
+  double bbo = 0.0;  // ||b||^2 over the own rows (first launch of a solve)
+  if (init) {
+    // the solve's right-hand side b (the set-up of the inner solve, on the own
+    // rows and the two-step halo) and u_0 = p_0 = D^{-1} b; x_0 = 0
+    const long long n3 = 3 * nn;
+    const double* Vj = I.V + (long long)S.j * n3;
+    // b = t - s (A v) with, per solve: (1) t = w / ||w||; (2) t = (v_j)_psi, s = tau_p,
+    // A v = K y0; (3.1) A v = M y1; (3.2) A v = M z; (5) t = (v_j)_omega, s = 1, A v = K x1
+    const int kind = S.kind;
+    const double* A = (kind == KIND_Y1 || kind == KIND_X2) ? o.Kv : (kind == KIND_Y0 ? nullptr : o.Mv);
+    const double* v = kind == KIND_Y1 ? (const double*)I.y0
+                      : kind == KIND_Z ? (const double*)I.y1
+                      : kind == KIND_X1 ? (const double*)I.zt
+                                        : (const double*)I.x1;
+    const double* t = kind == KIND_Y0 ? I.W : (kind == KIND_Y1 ? Vj + nn : (kind == KIND_X2 ? Vj + 2 * nn : nullptr));
+    const double ts = kind == KIND_Y0 ? S.vscale : 1.0, sa = kind == KIND_Y1 ? I.tau_p : 1.0;
+    double bo = 0.0;
 #pragma unroll
     for (int c = 0; c < PFC_SS_NA; ++c) {
       const int g = ss_wrap(lo - 2 * H + min(tid + c * PFC_WG, L2 - 1), n);
+      const int base = (g >> 6) * 64 * 7 + (g & 63);
+      double d = 0.0;
+      if (A) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+          const long long e = (long long)base + k * 64;
+          d += gld(A + e) * gld(v + pv.at(e, g));
+        }
+      }
+      const double tt = t ? gld(t + g) * ts : 0.0;
+      const double b = !A ? tt : (t ? tt - sa * d : d);
       P.bv[c][0] = gld(o.dinv + g);
-      P.bv[c][1] = gld(r + g);
+      P.bv[c][1] = b;
+      if (tid + c * PFC_WG == w.qo) bo = b;
+    }
+    if (w.own) {
+      const int g = w.go;
+      bbo = bo * bo;
+      vst(o.x + g, 0.0);
+      if (S.kind == KIND_Y0) {  // the Arnoldi vector v_j = w / ||w||
+        double* Vw = (double*)Vj;
+        vst(Vw + g, bo);
+        vst(Vw + nn + g, gld(I.W + nn + g) * S.vscale);
+        vst(Vw + 2 * nn + g, gld(I.W + 2 * nn + g) * S.vscale);
+      } else if (S.kind == KIND_X2) {  // (4): z_j = (y0 + (y1 - x1) / delta, x1, x2)
+        double* Zj = I.Z + (long long)S.j * n3;
+        const double y0i = gld((const double*)I.y0 + g), y1i = gld((const double*)I.y1 + g);
+        const double x1i = gld((const double*)I.x1 + g);
+        vst(Zj + g, y0i + (y1i - x1i) / I.delta);
+        vst(Zj + nn + g, x1i);
+      }
     }
   }
   if (!init && S.pcur) {  // the solve ends within these two iterations: x only
@@ -1254,6 +1298,7 @@ __device__ __forceinline__ void ph_scg(const InstDev& I, const State& S, const T
       for (int j = i; j < 5; ++j) gp[15 + ss_tri(i - 1, j - 1, 4)] = di * v[j];
     }
   }
+  gp[25] = bbo;
   PFC_SS_STAMP(2);
   // workgroup sums, fixed order: over each wave by recursive halving, then over
   // the waves

@@ -43,8 +43,8 @@ enum {
   PH_PCH_OUT,     // z_out = P_CH^{-1} v (preconditioner-only job)
   PH_CG_INIT,     // single-reduction PCG: w_0 = C D^{-1} r_0, partials (r,u), (w,u), (r,r)
   PH_CG_ITER,     // single-reduction PCG iteration (one launch per iteration)
-  PH_SCG_INIT,    // s-step PCG: basis p, Tp, T^2 p, u, Tu of u_0 = D^{-1} r_0, Gram partials
-  PH_SCG_ITER,    // s-step PCG: two iterations from the Gram matrix, next basis (or x only)
+  PH_SCG_ITER,    // s-step PCG: two iterations from the Gram matrix, next basis (or x only); its
+                  // first basis is formed by PH_PCG_SETUP (right-hand side on the halo, u_0 = D^{-1} b)
 };
 
 enum { JOB_NONE = 0, JOB_SOLVE = 1, JOB_RB = 2, JOB_PCH = 3 };

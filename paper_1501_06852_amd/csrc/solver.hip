@@ -231,6 +231,7 @@ __device__ __forceinline__ bool scg_kind(int kind) { return kind >= KIND_Y0 && k
 // S.pcur = 1 marks a launch that only adds the increment (the solve ends there).
 __device__ void scg_transition(State& S, const InstDev& I, bool wr, const double* g, double* coef) {
   if (S.phase == PH_SCG_ITER && S.pcur) { pcg_done(S, I, wr); return; }
+  const bool first = (S.phase == PH_PCG_SETUP);  // that launch formed the solve's first basis
   S.phase = PH_SCG_ITER;
   S.cur ^= 1;
   // entries (i <= j) of G = B^T D B and of H = B'^T D^2 B' (basis indices 1..4)
@@ -239,6 +240,12 @@ __device__ void scg_transition(State& S, const InstDev& I, bool wr, const double
   for (int m = 0; m < 15; ++m) coef[m] = 0.0;
   bool fixed; double tol;
   const int lim = inner_limit(I, S, fixed, tol);
+  if (first) {
+    S.bb = g[25];
+    S.it = 0;
+    S.pcur = 0;
+    if (S.bb == 0.0 || lim == 0) { pcg_done(S, I, wr); return; }  // x_0 = 0 stands
+  }
   // first iteration: alpha_0 = <u,u> / <p,Tp>, u_1 = u - alpha_0 Tp
   const double rho0 = G(3, 3);
   const double a0 = rho0 / G(0, 1);
@@ -304,7 +311,7 @@ __device__ void transition(State& S, const InstDev& I, bool wr, Red3 red, double
       const int lim = inner_limit(I, S, fixed, tol);
       if (S.bb == 0.0 || lim == 0) pcg_done(S, I, wr);
       else if (!I.single_reduction) S.phase = PH_PCG_A;
-      else S.phase = (ss && scg_kind(S.kind)) ? PH_SCG_INIT : PH_CG_INIT;
+      else S.phase = PH_CG_INIT;
     } break;
     case PH_CG_INIT:
       S.rho = red.a;             // gamma_0 = (r_0, D^{-1} r_0)
@@ -517,7 +524,8 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   bool scg = false;
   SsPre ssp;
   if constexpr (SS) {
-    scg = (S.phase == PH_SCG_INIT || S.phase == PH_SCG_ITER);
+    // launches after a two-iteration launch, or after the set-up that formed the first basis
+    scg = S.phase == PH_SCG_ITER || (S.phase == PH_PCG_SETUP && I.sstep && scg_kind(S.kind));
     if (scg && !(S.phase == PH_SCG_ITER && S.pcur)) {
       const double* gpart = I.spart + (long long)S.cur * te.size * 32;
       double pl[PFC_SS_GL];
@@ -556,13 +564,24 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   Team tm{te.rank, te.size, tid >> 6, tid & 63, lo};
   const bool sd = (S.kind == KIND_SD);  // second-ring pattern, never staged
   Red3 acc = red3(0.0, 0.0, 0.0);
+  bool fused = false;  // a set-up launch that formed a two-iteration solve's first basis (Gram partials only)
   switch (S.phase) {
     case PH_SOLVE_INIT:
     case PH_RB_RHS: acc = ph_solve_init<COLS>(I, S, tm); break;
     case PH_RB_BEGIN: acc = ph_rb_begin<COLS>(I, tm); break;
     case PH_RB_UPDATE: acc = ph_rb_update(I, tm); break;
     // the mass solves of the consistent initial values run in float64 in every precision
-    case PH_PCG_SETUP: acc = pcg_phase<T, COLS, PH_PCG_SETUP>(I, S, tm, sd); break;
+    case PH_PCG_SETUP:
+      if constexpr (SS) {
+        if (I.sstep && scg_kind(S.kind)) {  // set-up and first basis of a two-iteration solve
+          fused = true;
+          ph_scg<COLS>(I, S, tm, ss_coef, true, I.spart + (long long)S.cur * te.size * 32, ss_rows(I, te.rank, te.size),
+                       ssp);
+          break;
+        }
+      }
+      acc = pcg_phase<T, COLS, PH_PCG_SETUP>(I, S, tm, sd);
+      break;
     case PH_PCG_A: acc = pcg_phase<T, COLS, PH_PCG_A>(I, S, tm, sd); break;
     case PH_PCG_B: acc = pcg_phase<T, COLS, PH_PCG_B>(I, S, tm, sd); break;
     case PH_ASPMV:
@@ -577,16 +596,15 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     case PH_PCH_OUT: acc = ph_pch_out<T>(I, tm); break;
     case PH_CG_INIT: acc = pcg_phase<T, COLS, PH_CG_INIT>(I, S, tm, sd); break;
     case PH_CG_ITER: acc = pcg_phase<T, COLS, PH_CG_ITER>(I, S, tm, sd); break;
-    case PH_SCG_INIT:
     case PH_SCG_ITER:
       if constexpr (SS)
-        ph_scg<COLS>(I, S, tm, ss_coef, S.phase == PH_SCG_INIT, I.spart + (long long)S.cur * te.size * 32,
-                     ss_rows(I, te.rank, te.size), ssp);
+        ph_scg<COLS>(I, S, tm, ss_coef, false, I.spart + (long long)S.cur * te.size * 32, ss_rows(I, te.rank, te.size),
+                     ssp);
       break;
     default: break;
   }
   PFC_STAMP(t_work);
-  if (phase_partials(S.phase)) {
+  if (phase_partials(S.phase) && !fused) {
     acc.a = wave_sum(acc.a);
     acc.b = wave_sum(acc.b);
     acc.c = wave_sum(acc.c);
@@ -613,7 +631,7 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
       r[0] = (unsigned long long)S.phase | ((unsigned long long)te.rank << 8) | ((unsigned long long)S.kind << 40) |
              ((unsigned long long)(S.it & 0xffff) << 48);
       r[1] = t_entry; r[2] = t_ld; r[3] = t_trans; r[4] = t_work; r[5] = t_exit; r[6] = blockIdx.x; r[7] = t_red;
-      for (int q = 0; q < 6; ++q) r[8 + q] = (SS && (S.phase == PH_SCG_INIT || S.phase == PH_SCG_ITER)) ? pfc_sst[q] : 0;
+      for (int q = 0; q < 6; ++q) r[8 + q] = (SS && (fused || S.phase == PH_SCG_ITER)) ? pfc_sst[q] : 0;
     }
   }
 #endif
