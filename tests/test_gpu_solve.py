@@ -468,3 +468,36 @@ def test_two_pcg_iterations_per_launch(pfc, N, jit, tau):
         for i in insts:
             pfc.pfc_instance_destroy(i)
         P.close()
+
+
+def test_two_pcg_iterations_per_launch_large_team(pfc):
+    """A 2D 600^2 grid: a team of 352 workgroups (Gram partials beyond the first 256 per thread group are
+    summed by the remainder loop) and a halo of 601 rows.  Two iterations per launch against one, both on
+    the GPU (the one-iteration path is tied to the oracle by the replay tests): the same counts, the same
+    solution to rounding, and the true residual of the tolerance."""
+    import workloads as wl
+    mesh = wl.make_mesh(2, 600, jitter=0.2, seed=5)
+    n = mesh.n
+    h = pfc.pfc_mesh_create_p1(2, n, mesh.elem_nodes, mesh.elem_coords)
+    insts = []
+    try:
+        assert pfc.pfc_mesh_grid_side(h) == 600
+        r, psibar, tau = -0.35, -0.3, 1.0
+        psi = wl.psi0(n, psibar, 0.01, seed=5)
+        b = np.random.default_rng(9).normal(size=3 * n)
+        out = []
+        for spl in (2, 1):
+            inst = pfc.pfc_instance_create(h, pfc.pfc_opts_default(pcg_steps_per_launch=spl))
+            insts.append(inst)
+            x = dev(np.zeros(3 * n))
+            st, gi = pfc.pfc_solve(inst, n, dev(psi), r, psibar, tau, M11, dev(b), x)
+            assert st == pfc.PFC_OK and gi["true_rel_res"] <= 1e-8
+            out.append((host(x), gi, pfc.pfc_last_inner_counts(inst), pfc.pfc_instance_launch_stats(inst)[0]))
+        (x2, g2, c2, l2), (x1, g1, c1, l1) = out
+        assert g2["outer_iters"] == g1["outer_iters"] and np.array_equal(c2, c1)
+        assert rel(x2, x1) <= 1e-10
+        assert l2 < 0.8 * l1, (l2, l1)
+    finally:
+        for i in insts:
+            pfc.pfc_instance_destroy(i)
+        pfc.pfc_mesh_destroy(h)
