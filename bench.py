@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # was taken on: when their digest differs, `traffic` is reported as null.
 TRAFFIC = {
     # workload: (sha256 of the kernel sources, bytes per launch, algorithmic bytes per launch of the same run)
-    "pfc2d_512_fp64": ("a55a41196211857e2f6a2eac07ef823dd376c96ab8cacd8e87f6f0c8d69147cd", 37884568.0, 65684139.0),
-    "pfc3d_64_mixed": ("a55a41196211857e2f6a2eac07ef823dd376c96ab8cacd8e87f6f0c8d69147cd", 30393599.0, 37670502.0),
+    "pfc2d_512_fp64": ("dac8c0381e82123297bf9c3e8d2d0034ab235a02a27c6175a0387ed512b6d813", 37884839.0, 65684139.0),
+    "pfc3d_64_mixed": ("dac8c0381e82123297bf9c3e8d2d0034ab235a02a27c6175a0387ed512b6d813", 30398905.0, 37670502.0),
 }
 
 

@@ -994,11 +994,6 @@ __device__ __forceinline__ double dpp_half_sum(double v) {
   v = dpp_row_sum(v);
   return v + dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
 }
-// Sum over the wave in lane 63.
-__device__ __forceinline__ double dpp_wave_sum(double v) {
-  v = dpp_half_sum(v);
-  return v + dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-}
 
 // Workgroup barrier that orders LDS only: the global loads and stores of the
 // two-iterations-per-launch phase are never read back within the launch, so
@@ -1113,7 +1108,6 @@ __device__ __forceinline__ void ph_scg(const InstDev& I, const State& S, const T
   const int n = I.n, H = w.H, R = w.R, L1 = w.L1, L2 = w.L2, lo = w.lo;
   PcgOps<double> o = pcg_ops<double>(I, S.kind);
   const PatView<L> pv = op_pat<L>(I, o, tm);
-  const int uw = pv.uw;
   const int tid = threadIdx.x;
   const long long nn = n;
   double* bout = I.sbas + (long long)S.cur * 5 * nn;
