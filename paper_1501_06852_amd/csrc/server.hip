@@ -73,6 +73,12 @@ pfc_opts server_instance_opts(const pfc_server* S, int rpt) {
   o.precision = S->o.precision;
   o.ticks_per_graph = S->o.ticks_per_graph;
   o.rows_per_thread = rpt;
+  // a request shares its launches with whichever requests are resident, and the
+  // set changes between launches while it runs: one PCG iteration per launch is
+  // valid in every launch set (the two-iteration form needs launches that serve
+  // the instance alone) and gives the same bits in any of them.  A server with a
+  // single slot runs every request alone and keeps the two-iteration form.
+  o.pcg_steps_per_launch = S->o.max_slots == 1 ? 2 : 1;
   return o;
 }
 

@@ -389,6 +389,9 @@ __device__ void transition(State& S, const InstDev& I, bool wr, Red3 red, double
     case PH_PCH_OUT:
       S.phase = PH_DONE;
       break;
+    case PH_SCG_ITER:  // a two-iteration solve in a launch without that form: refuse, loudly
+      finish_solve(S, I, wr, PFC_ERR_STATE);
+      break;
     default:
       S.phase = PH_DONE;
       break;

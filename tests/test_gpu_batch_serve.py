@@ -98,7 +98,7 @@ def _serve(pfc, meshes, reqs, prec, slots, budget):
         pfc._lib.pfc_server_destroy(srv)
 
 
-@pytest.mark.parametrize("prec", [1])
+@pytest.mark.parametrize("prec", [1, 0])
 def test_server_alone_equals_mix_and_admission(pfc, prec):
     probs = _problems()
     meshes = [P.gpu_mesh() for P in probs]
@@ -112,7 +112,8 @@ def test_server_alone_equals_mix_and_admission(pfc, prec):
         alone = []
         for mi, p, psi in reqs:
             P = probs[mi]
-            inst = pfc.pfc_instance_create(meshes[mi], pfc.pfc_opts_default(precision=prec))
+            # served instances run one PCG iteration per launch (their launch sets change while they run)
+            inst = pfc.pfc_instance_create(meshes[mi], pfc.pfc_opts_default(precision=prec, pcg_steps_per_launch=1))
             s = dev(np.concatenate([np.zeros(P.n), psi, np.zeros(P.n)]))
             pfc.pfc_rosenbrock_run(inst, P.n, s, p.r, p.psibar, p.tau, 2)
             alone.append(host(s))
