@@ -210,3 +210,28 @@ def test_full_size_3d_64_mixed_vs_fft_exact(pfc):
         if inst is not None:
             pfc.pfc_instance_destroy(inst)
         P.close()
+
+
+def test_single_slot_server_keeps_two_iterations(pfc):
+    """A float64 server with one slot runs every request alone, with two PCG iterations per launch: each
+    result equals, bit for bit, a plain run of an instance with the default options (the same form)."""
+    P = Problem(2, 24, 0.2, seed=21)
+    mesh = P.gpu_mesh()
+    prm = wl.draw_params(3, 500)
+    reqs = [(0, p, wl.psi0(P.n, p.psibar, 0.01, seed=p.seed)) for p in prm]
+    try:
+        alone = []
+        for _, p, psi in reqs:
+            inst = pfc.pfc_instance_create(mesh, pfc.pfc_opts_default(precision=0))
+            s = dev(np.concatenate([np.zeros(P.n), psi, np.zeros(P.n)]))
+            pfc.pfc_rosenbrock_run(inst, P.n, s, p.r, p.psibar, p.tau, 2)
+            alone.append(host(s))
+            pfc.pfc_instance_destroy(inst)
+        out = _serve(pfc, [mesh], reqs, 0, 1, 64 << 30)
+        assert sorted(out) == list(range(len(reqs)))
+        for k in range(len(reqs)):
+            st, state, res, _ = out[k]
+            assert st >= 0 and max(res) <= 1e-8
+            assert np.array_equal(state, alone[k]), k
+    finally:
+        P.close()
