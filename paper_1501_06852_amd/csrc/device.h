@@ -981,20 +981,6 @@ __device__ __forceinline__ double dpp_f64(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-// Sum over each row of 16 lanes, in every lane of the row (fixed order).
-__device__ __forceinline__ double dpp_row_sum(double v) {
-  v += dpp_f64<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141, 0xf>(v);  // row_half_mirror
-  v += dpp_f64<0x140, 0xf>(v);  // row_mirror
-  return v;
-}
-// Sum over lanes 0-31 in lane 31 and over lanes 32-63 in lane 63.
-__device__ __forceinline__ double dpp_half_sum(double v) {
-  v = dpp_row_sum(v);
-  return v + dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-}
-
 // Workgroup barrier that orders LDS only: the global loads and stores of the
 // two-iterations-per-launch phase are never read back within the launch, so
 // loads issued ahead stay in flight across it (a full __syncthreads would wait
@@ -1338,11 +1324,18 @@ __device__ __forceinline__ void ss_gram(const double* part, int size, const doub
     for (int k = grp + 32 * PFC_SS_GL; k < size; k += 32) s += gld(part + (long long)k * 32 + v);
   pfc_ssred[grp * 32 + v] = s;
   lds_barrier();
-  // wave w sums value w over the 32 groups in lanes 0-31 and value w + 16 in lanes 32-63
-  const int lane = tid & 63, w = tid >> 6, vv = w + (lane >> 5) * 16;
-  const double t = dpp_half_sum(vv < PFC_SS_NG ? pfc_ssred[(lane & 31) * 32 + vv] : 0.0);
-  if ((lane & 31) == 31 && vv < PFC_SS_NG) g[vv] = t;
-  lds_barrier();
+  // only thread 0 (the transition) reads the totals: the first wave forms them,
+  // lane v over groups 0-15 and lane v + 32 over groups 16-31, added across the
+  // halves by a permlane32 swap; its LDS writes precede thread 0's reads in the
+  // wave's own order, so no barrier follows
+  if (tid < 64) {
+    const int half = tid >> 5;
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += pfc_ssred[(half * 16 + q) * 32 + v];
+    t = ss_swap<false>(t, t, half != 0);
+    if (tid < PFC_SS_NG) g[tid] = t;
+  }
 }
 
 }  // namespace pfc
