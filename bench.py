@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # was taken on: when their digest differs, `traffic` is reported as null.
 TRAFFIC = {
     # workload: (sha256 of the kernel sources, bytes per launch, algorithmic bytes per launch of the same run)
-    "pfc2d_512_fp64": ("e6e83cee517b8ecd5a2aa93eb5aea7b64f5e9f5bc4e4efda627f20d7cdf99c66", 37897473.0, 65684139.0),
-    "pfc3d_64_mixed": ("e6e83cee517b8ecd5a2aa93eb5aea7b64f5e9f5bc4e4efda627f20d7cdf99c66", 30388318.0, 37670502.0),
+    "pfc2d_512_fp64": ("b024f9995be3e40259003c58458c2c3ae1cb61e377efba39eb20a191389fe2dc", 37899747.0, 65684139.0),
+    "pfc3d_64_mixed": ("b024f9995be3e40259003c58458c2c3ae1cb61e377efba39eb20a191389fe2dc", 30396108.0, 37670502.0),
 }
 
 
