@@ -13,6 +13,11 @@ algorithmic bytes of the solver kernel (paper_1501_06852_amd.roofline) per
 launch over the average launch period measured with HIP events on the solver
 stream.  `cpu_baseline` times the float64 oracle on one Rosenbrock step of the
 same workload on the host (single thread).
+
+Other workloads (`--workload`): 3D 64^3 mixed precision, the P2 / PFC1 / S_D
+variants at the headline size, 256 batched 128^2 instances, a served stream of
+six mesh classes, adaptive Ros3Pw on the headline problem (t = 0 to 200), and
+the device-copy calibration of the traffic counters.
 """
 from __future__ import annotations
 
