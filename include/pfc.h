@@ -12,7 +12,7 @@
  *     m11 = 1/gamma for Rosenbrock stages and m11 = 1 for the linearised Euler
  *     system (eq. systemmatrix);
  *   - right-preconditioned flexible GMRES(restart) with modified Gram-Schmidt
- *     (Section 4 and the solver settings of Section 6);
+ *     (Section 4 and the solver settings of Section 7);
  *   - the preconditioner P_CH = P(S_CH) of eq. preconditioner_S with
  *     S_CH = (M + sqrt(delta) K) M^{-1} (M + sqrt(delta) K), delta = sqrt(tau),
  *     applied in five steps with Jacobi-PCG inner solves (Section 4.2,
@@ -323,6 +323,16 @@ int pfc_last_inner_counts(const pfc_instance* inst, int* counts, int cap, int* n
  * including launches that found the instance finished) and number of graph
  * replays.  Host outputs; either may be NULL. */
 int pfc_instance_launch_stats(const pfc_instance* inst, long long* launches, long long* graphs);
+
+/* Launch configuration an instance runs with when a launch serves it alone
+ * (host outputs; any may be NULL): its team of workgroups, rows per thread,
+ * PCG iterations per solver launch (2 where the two-iteration form applies,
+ * see pcg_steps_per_launch, else 1) and whether the solver kernel computes the
+ * mesh's columns from the row (1) or reads them (0).  In a launch that serves
+ * several instances (batches, the server) every instance runs one PCG
+ * iteration per launch. */
+int pfc_instance_config(const pfc_instance* inst, int* team_size, int* rows_per_thread, int* pcg_steps_per_launch,
+                        int* grid_columns);
 
 /* n_steps Ros3Pw steps (eqs. rosenbrock, rosenbrock-update; Table
  * rosenbrock_scheme) of the PFC2 system from state = (mu, psi, omega):

@@ -94,18 +94,3 @@ def load_psi3(mesh, psi: np.ndarray) -> np.ndarray:
     ge = vol[:, None] * np.einsum("abci,ea,eb,ec->ei", I4, pe, pe, pe)
     return _assemble_vec(mesh.elem_nodes, ge, mesh.n)
 
-
-def energy(mesh, M, K, psi: np.ndarray, r: float) -> float:
-    """Discrete Swift-Hohenberg energy (Section 2, eq. for F(psi)) of the P1 state.
-
-    F = int psi^4/4 + (1/2) psi (r + (1 + Delta)^2) psi
-      = int psi^4/4 + (1+r)/2 psi^2 - |grad psi|^2 + (1/2)(Delta psi)^2,
-    with Delta psi represented by omega solving M omega = -K psi.
-    Diagnostic only; it plays no role in the solve.
-    """
-    import scipy.sparse.linalg as spla
-
-    g = load_psi3(mesh, psi)
-    quart = 0.25 * float(g @ psi)  # int psi^4 = sum_i psi_i int psi^3 phi_i
-    omega = spla.spsolve(M.tocsc(), -(K @ psi))
-    return quart + 0.5 * (1.0 + r) * float(psi @ (M @ psi)) - float(psi @ (K @ psi)) + 0.5 * float(omega @ (M @ omega))

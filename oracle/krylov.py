@@ -7,7 +7,7 @@
           A fixed-count mode replays a recorded iteration count.
 * fgmres  flexible GMRES with restart m (30 in the paper), modified
           Gram-Schmidt and Givens rotations, right preconditioning
-          A P^{-1} (P x) = b (Section 4; solver settings in Section 6).
+          A P^{-1} (P x) = b (Section 4; solver settings in Section 7).
           x_0 = 0; the iteration count is the number of Arnoldi steps.
 
 Pinned by tests/test_oracle_solvers.py: PCG against a direct solve and the

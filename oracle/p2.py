@@ -1,7 +1,7 @@
 """P2 (quadratic Lagrange) finite-element matrices of the PFC system (oracle, test infrastructure).
 
 Section 3 takes V_h with local polynomials of degree p = 1, 2; the studies of
-Section 6 (Tables 3-5) use p = 2.  On a simplex with barycentric coordinates
+Section 7 (Tables 3-5) use p = 2.  On a simplex with barycentric coordinates
 lambda_0..lambda_m the P2 basis is
     vertex a:          lambda_a (2 lambda_a - 1)
     edge (i, j):       4 lambda_i lambda_j

@@ -1,6 +1,6 @@
 """Fourier analysis of the preconditioner (oracle, test infrastructure).
 
-Symbols (Section 5) in terms of k2 = |k|^2, with the psibar stabilisation of
+Symbols (Section 6) in terms of k2 = |k|^2, with the psibar stabilisation of
 eq. A_mod (c = 3 psibar^2 + 1 + r):
     A    = [[1, -c + 2 k2, k2], [tau k2, 1, 0], [0, k2, 1]]
     A0   = 1 + tau (c k2 - 2 k2^2 + k2^3)                    (eq. A0_mod)
@@ -78,7 +78,7 @@ def rho_interval(lo: float, hi: float) -> float:
 
 
 def k2_grid(dim: int, kmax: float = 4.0, samples: int = 4001):
-    """|k|^2 over [0, dim*kmax^2] (k_i in [0, kmax], Section 5.3)."""
+    """|k|^2 over [0, dim*kmax^2] (k_i in [0, kmax], Section 6.3)."""
     return np.linspace(0.0, dim * kmax * kmax, samples)
 
 

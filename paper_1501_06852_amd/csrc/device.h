@@ -1326,8 +1326,9 @@ __device__ __forceinline__ void ss_gram(const double* part, int size, const doub
   lds_barrier();
   // only thread 0 (the transition) reads the totals: the first wave forms them,
   // lane v over groups 0-15 and lane v + 32 over groups 16-31, added across the
-  // halves by a permlane32 swap; its LDS writes precede thread 0's reads in the
-  // wave's own order, so no barrier follows
+  // halves by a permlane32 swap.  Writers and the reader are lanes of that one
+  // wave, so a wave barrier between LDS-only fences orders the writes before
+  // thread 0's reads (no workgroup barrier needed)
   if (tid < 64) {
     const int half = tid >> 5;
     double t = 0.0;
@@ -1335,6 +1336,9 @@ __device__ __forceinline__ void ss_gram(const double* part, int size, const doub
     for (int q = 0; q < 16; ++q) t += pfc_ssred[(half * 16 + q) * 32 + v];
     t = ss_swap<false>(t, t, half != 0);
     if (tid < PFC_SS_NG) g[tid] = t;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
   }
 }
 

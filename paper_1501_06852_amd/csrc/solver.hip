@@ -1408,6 +1408,16 @@ int pfc_instance_launch_stats(const pfc_instance* I, long long* launches, long l
   return PFC_OK;
 }
 
+int pfc_instance_config(const pfc_instance* I, int* team_size, int* rows_per_thread, int* pcg_steps_per_launch,
+                        int* grid_columns) {
+  if (!I) { set_error("pfc_instance_config: null instance"); return PFC_ERR_ARG; }
+  if (team_size) *team_size = I->team_size;
+  if (rows_per_thread) *rows_per_thread = I->opts.rows_per_thread > 0 ? I->opts.rows_per_thread : 1;
+  if (pcg_steps_per_launch) *pcg_steps_per_launch = I->h.sstep ? 2 : 1;
+  if (grid_columns) *grid_columns = (I->h.grid_cols && I->mesh->dev.gN > 0 && I->mesh->dev.uw >= 1) ? 1 : 0;
+  return PFC_OK;
+}
+
 int pfc_last_inner_counts(const pfc_instance* I, int* counts, int cap, int* n_applies) {
   if (!I || !counts || cap < 0 || !n_applies) { set_error("pfc_last_inner_counts: invalid arguments"); return PFC_ERR_ARG; }
   const int na = std::min(I->last_applies, I->opts.max_steps);

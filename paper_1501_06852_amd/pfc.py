@@ -122,6 +122,7 @@ _sig("pfc_solve_x", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_
                               C.POINTER(pfc_schedule), C.POINTER(pfc_solve_info), _vp])
 _sig("pfc_last_inner_counts", C.c_int, [_vp, _ip, C.c_int, _ip])
 _sig("pfc_instance_launch_stats", C.c_int, [_vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)])
+_sig("pfc_instance_config", C.c_int, [_vp, _ip, _ip, _ip, _ip])
 _sig("pfc_rosenbrock_run", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
                                      C.POINTER(pfc_schedule), C.POINTER(pfc_solve_info), _vp])
 _sig("pfc_rosenbrock_adaptive", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -146,7 +147,8 @@ DECLARED = [
     "pfc_status_str", "pfc_last_error", "pfc_opts_default", "pfc_tau_critical", "pfc_mesh_create_p1", "pfc_mesh_create_p2",
     "pfc_mesh_create_csr", "pfc_mesh_query", "pfc_mesh_grid_side", "pfc_mesh_export_csr", "pfc_mesh_destroy", "pfc_spmv",
     "pfc_assemble_N", "pfc_load_psi3", "pfc_instance_footprint", "pfc_instance_create", "pfc_instance_destroy",
-    "pfc_solve", "pfc_solve_x", "pfc_last_inner_counts", "pfc_instance_launch_stats", "pfc_rosenbrock_run",
+    "pfc_solve", "pfc_solve_x", "pfc_last_inner_counts", "pfc_instance_launch_stats", "pfc_instance_config",
+    "pfc_rosenbrock_run",
     "pfc_rosenbrock_adaptive", "pfc_apply_AR", "pfc_apply_AR_x", "pfc_apply_pch", "pfc_stage_rhs",
     "pfc_batch_run", "pfc_server_create", "pfc_server_submit", "pfc_server_poll", "pfc_result_free",
     "pfc_server_drain", "pfc_server_clock", "pfc_server_destroy",
@@ -360,6 +362,14 @@ def pfc_instance_launch_stats(inst):
     a, b = C.c_longlong(), C.c_longlong()
     _check(_lib.pfc_instance_launch_stats(inst, C.byref(a), C.byref(b)), "pfc_instance_launch_stats")
     return a.value, b.value
+
+
+def pfc_instance_config(inst):
+    """The launch configuration of an instance served alone (dict)."""
+    v = [C.c_int() for _ in range(4)]
+    _check(_lib.pfc_instance_config(inst, *[C.byref(x) for x in v]), "pfc_instance_config")
+    return dict(team_size=v[0].value, rows_per_thread=v[1].value, pcg_steps_per_launch=v[2].value,
+                grid_columns=v[3].value)
 
 
 def pfc_rosenbrock_run(inst, n, state, r, psibar, tau, n_steps, init=PFC_INIT_CONSISTENT, replays=None, stream=None):

@@ -1,4 +1,6 @@
 """Shared test helpers: seeded problems on both sides (oracle on the CPU, HIP path on the GPU)."""
+import os
+
 import numpy as np
 
 import workloads as wl
@@ -45,3 +47,33 @@ def host(t):
 def rel(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def blockerr(a, b, blocks=3):
+    """Element-wise parity of a against the reference b: the largest, over the blocks (mu, psi,
+    omega of a block vector; blocks=1 for a vector over the nodes), of max|a - b| / max|b| taken
+    within the block.  Every entry counts, so a single wrong row (a halo or a wrap row) fails it."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    assert a.shape == b.shape, (a.shape, b.shape)
+    assert b.size % blocks == 0, (b.size, blocks)
+    worst = 0.0
+    for ab, bb in zip(np.split(a.ravel(), blocks), np.split(b.ravel(), blocks)):
+        if bb.size == 0:
+            continue
+        s = float(np.max(np.abs(bb)))
+        d = float(np.max(np.abs(ab - bb)))
+        if not np.isfinite(d):
+            return float("inf")
+        worst = max(worst, d / (s if s > 0 else 1.0))
+    _log_parity(worst)
+    return worst
+
+
+def _log_parity(value):
+    """With PFC_PARITY_LOG set to a file path, append the test's name and the measured error (the
+    margins of the parity bounds, read after a GPU run)."""
+    path = os.environ.get("PFC_PARITY_LOG")
+    if path:
+        with open(path, "a") as f:
+            f.write(f"{os.environ.get('PYTEST_CURRENT_TEST', '?')}\t{value:.3e}\n")

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from helpers import Problem, dev, host, rel
+from helpers import Problem, blockerr, dev, host, rel
 from oracle import pfc as opfc, solve as osolve
 
 pytestmark = pytest.mark.gpu
@@ -69,15 +69,16 @@ def test_batch_alone_equals_mix(pfc, prec):
             P.close()
 
 
-def _serve(pfc, meshes, reqs, prec, slots, budget):
+def _serve(pfc, meshes, reqs, prec, slots, budget, steps=2, rpt=0):
     import ctypes as C
-    so = pfc.pfc_server_opts(C.sizeof(pfc.pfc_server_opts), prec, budget, slots, 0, 0)
+    so = pfc.pfc_server_opts(C.sizeof(pfc.pfc_server_opts), prec, budget, slots, 0, rpt)
     srv = C.c_void_p()
     assert pfc._lib.pfc_server_create(C.byref(so), C.byref(srv)) == 0
     try:
         for rid, (mi, p, psi) in enumerate(reqs):
             a = np.ascontiguousarray(psi)
-            rc = pfc._lib.pfc_server_submit(srv, meshes[mi], p.r, p.psibar, p.tau, a.ctypes.data_as(pfc._dp), 2, rid)
+            rc = pfc._lib.pfc_server_submit(srv, meshes[mi], p.r, p.psibar, p.tau, a.ctypes.data_as(pfc._dp), steps,
+                                            rid)
             assert rc == 0, pfc.pfc_last_error()
         assert pfc._lib.pfc_server_drain(srv) == 0
         out = {}
@@ -163,7 +164,7 @@ def test_full_size_2d_512_stage_solve(pfc):
         x = dev(np.zeros(3 * n))
         s = info["schedule"]
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, m11, dev(b), x, replay=(s.cycles, s.inner))
-        assert rel(host(x), y_ref) <= 1e-10
+        assert blockerr(host(x), y_ref) <= 1e-10
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, m11, dev(b), x)
         y = host(x)
         res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, tau, m11, y)) / np.linalg.norm(b)
@@ -176,7 +177,7 @@ def test_full_size_2d_512_stage_solve(pfc):
         state = dev(np.concatenate([np.zeros(n), P.psi, np.zeros(n)]))
         st, gis = pfc.pfc_rosenbrock_run(inst, n, state, r, psibar, tau, 1, pfc.PFC_INIT_CONSISTENT, replays=reps)
         assert [g["outer_iters"] for g in gis] == [i["steps"] for i in oinf]
-        assert rel(host(state), x_ref) <= 1e-10
+        assert blockerr(host(state), x_ref) <= 1e-10
         state = dev(np.concatenate([np.zeros(n), P.psi, np.zeros(n)]))
         st, gis = pfc.pfc_rosenbrock_run(inst, n, state, r, psibar, tau, 1)
         assert st == pfc.PFC_OK and max(g["true_rel_res"] for g in gis) <= 1e-8
@@ -235,3 +236,41 @@ def test_single_slot_server_keeps_two_iterations(pfc):
             assert np.array_equal(state, alone[k]), k
     finally:
         P.close()
+
+
+def test_server_large_classes_mixed(pfc):
+    """A mixed-precision server with a 2D 512^2 and a 3D 48^3 request (the largest served classes) next to
+    small ones: every result equals, bit for bit, the same request run alone, and lands on the oracle's
+    float64 trajectory as closely as two runs whose stage solves stop at relative residual 1e-8 can."""
+    probs = [Problem(2, 512, 0.0, seed=31), Problem(3, 48, 0.0, seed=32), Problem(2, 16, 0.0, seed=33),
+             Problem(3, 4, 0.0, seed=34)]
+    prm = wl.draw_params(6, 900)
+    owners = [0, 2, 1, 3, 2, 3]
+    reqs = [(mi, prm[k], wl.psi0(probs[mi].n, prm[k].psibar, 0.01, seed=prm[k].seed)) for k, mi in enumerate(owners)]
+    steps = 1
+    try:
+        meshes = [P.gpu_mesh() for P in probs]
+        # served with one row per thread (fixed, so that the alone runs use the same teams)
+        print("served large classes: server run", flush=True)
+        out = _serve(pfc, meshes, reqs, 1, 8, 64 << 30, steps=steps, rpt=1)
+        assert sorted(out) == list(range(len(reqs)))
+        for k, (mi, p, psi) in enumerate(reqs):
+            P = probs[mi]
+            print(f"served large classes: request {k} ({P.mesh.dim}D, n = {P.n}) alone and oracle", flush=True)
+            inst = pfc.pfc_instance_create(meshes[mi], pfc.pfc_opts_default(precision=1, rows_per_thread=1,
+                                                                            pcg_steps_per_launch=1))
+            s = dev(np.concatenate([np.zeros(P.n), psi, np.zeros(P.n)]))
+            pfc.pfc_rosenbrock_run(inst, P.n, s, p.r, p.psibar, p.tau, steps)
+            alone = host(s)
+            pfc.pfc_instance_destroy(inst)
+            st, state, res, _ = out[k]
+            assert st >= 0 and max(res) <= 1e-8, (k, st, res)
+            assert np.array_equal(state, alone), k
+            x0 = opfc.consistent_init(P.mesh, P.M, P.K, p.r, psi)
+            xr, _ = osolve.rosenbrock_run(P.mesh, P.M, P.K, x0, p.r, p.tau, steps, tol=1e-8)
+            err = rel(state, xr)
+            print(f"served large classes: request {k} against the oracle {err:.2e}", flush=True)
+            assert err <= 1e-6, (k, err)
+    finally:
+        for P in probs:
+            P.close()

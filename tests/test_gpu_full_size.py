@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from helpers import Problem, dev, host, rel
+from helpers import Problem, blockerr, dev, host, rel
 from oracle import assembly, mobility as mob, pfc as opfc, precond, solve as osolve
 
 pytestmark = pytest.mark.gpu
@@ -88,7 +88,7 @@ def test_full_size_variant(pfc, name):
             z = dev(np.zeros(3 * n))
             got = pfc.pfc_apply_pch(inst, n, tau_s, dev(w), z, fixed_counts=inner.counts[0])
             assert list(got) == list(inner.counts[0])
-            assert rel(host(z), z_ref) <= 1e-12
+            assert blockerr(host(z), z_ref) <= 1e-12
         # the benchmark's entry point: one Rosenbrock step from consistent initial values
         state = dev(np.concatenate([np.zeros(n), P.psi, np.zeros(n)]))
         st, gis = pfc.pfc_rosenbrock_run(inst, n, state, r, psibar, tau, 1, pfc.PFC_INIT_CONSISTENT)
@@ -153,7 +153,7 @@ def test_full_size_batched_128_mixed(pfc):
             _, gi = pfc.pfc_rosenbrock_run(rep, n, s_rep, p.r, p.psibar, p.tau, 1, pfc.PFC_INIT_CONSISTENT,
                                            replays=reps)
             assert [g["outer_iters"] for g in gi] == [i["steps"] for i in oinf]
-            assert rel(host(s_rep), x_ref) <= 1e-10, k
+            assert blockerr(host(s_rep), x_ref) <= 1e-10, k
             sb = host(st[k])
             assert rel(sb, x_ref) <= 1e-6, k
             m0 = np.sum(P.M @ psi)

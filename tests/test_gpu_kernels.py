@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from helpers import Problem, dev, host, rel
+from helpers import Problem, blockerr, dev, host, rel
 from oracle import assembly, pfc as opfc, precond
 
 pytestmark = pytest.mark.gpu
@@ -40,9 +40,9 @@ def test_spmv_N_and_cubic_load(pfc, dim, N, jit):
         x = np.random.default_rng(1).normal(size=P.n)
         y = dev(np.zeros(P.n))
         pfc.pfc_spmv(m, pfc.PFC_OP_M, dev(x), y)
-        assert rel(host(y), P.M @ x) <= 1e-13
+        assert blockerr(host(y), P.M @ x, 1) <= 1e-13
         pfc.pfc_spmv(m, pfc.PFC_OP_K, dev(x), y)
-        assert rel(host(y), P.K @ x) <= 1e-12
+        assert blockerr(host(y), P.K @ x, 1) <= 1e-12
         Nref = assembly.N_matrix(P.mesh, P.psi)
         Nd = dev(np.zeros(P.M.nnz))
         pfc.pfc_assemble_N(m, dev(P.psi), Nd)
@@ -52,7 +52,7 @@ def test_spmv_N_and_cubic_load(pfc, dim, N, jit):
         assert np.abs(Nh - Nref.data).max() <= 1e-13 * np.abs(Nref.data).max()
         g = dev(np.zeros(P.n))
         pfc.pfc_load_psi3(m, dev(P.psi), g)
-        assert rel(host(g), assembly.load_psi3(P.mesh, P.psi)) <= 1e-13
+        assert blockerr(host(g), assembly.load_psi3(P.mesh, P.psi), 1) <= 1e-13
     finally:
         P.close()
 
@@ -70,7 +70,7 @@ def test_apply_AR_and_stage_rhs(pfc, dim, N, jit):
         N = assembly.N_matrix(P.mesh, P.psi)
         out = dev(np.zeros(3 * n))
         pfc.pfc_apply_AR(inst, n, dev(P.psi), r, tau, m11, dev(y), out)
-        assert rel(host(out), opfc.apply_AR(P.M, P.K, N, r, tau, m11, y)) <= 1e-13
+        assert blockerr(host(out), opfc.apply_AR(P.M, P.K, N, r, tau, m11, y)) <= 1e-13
         xk = np.concatenate([rng.normal(size=n), P.psi, rng.normal(size=n)])
         ys = rng.normal(size=(3, 3 * n)) * 0.1
         a = {(2, 1): opfc.ROS3PW_A[(2, 1)], (3, 1): opfc.ROS3PW_A[(3, 1)], (3, 2): opfc.ROS3PW_A[(3, 2)]}
@@ -80,7 +80,7 @@ def test_apply_AR_and_stage_rhs(pfc, dim, N, jit):
             bref = opfc.stage_rhs_R(P.mesh, P.M, P.K, r, tau, xi, [ys[j - 1][n:2 * n] for j in range(1, stage)], c)
             b = dev(np.zeros(3 * n))
             pfc.pfc_stage_rhs(inst, n, dev(xk), dev(ys.reshape(-1)), stage, r, tau, b)
-            assert rel(host(b), bref) <= 1e-12, stage
+            assert blockerr(host(b), bref) <= 1e-12, stage
     finally:
         if inst is not None:
             pfc.pfc_instance_destroy(inst)
@@ -101,7 +101,7 @@ def test_pch_apply_fixed_counts(pfc, dim, N, jit, tau_s):
         z = dev(np.zeros(3 * n))
         got = pfc.pfc_apply_pch(inst, n, tau_s, dev(v), z, fixed_counts=counts)
         assert list(got) == list(counts)
-        assert rel(host(z), z_ref) <= 1e-12
+        assert blockerr(host(z), z_ref) <= 1e-12
         # tolerance mode: same counts up to rounding near the threshold, same accuracy class
         got2 = pfc.pfc_apply_pch(inst, n, tau_s, dev(v), z)
         assert np.abs(np.array(got2) - np.array(counts)).max() <= 1
@@ -109,7 +109,7 @@ def test_pch_apply_fixed_counts(pfc, dim, N, jit, tau_s):
         P3 = precond.P3_dense(P.M, P.K, tau_s) if n <= 256 else None
         if P3 is not None:
             inner_ex = precond.InnerSolvers(P.M, P.K, tau_s, mode="exact")
-            assert rel(precond.pch_apply(inner_ex, v), np.linalg.solve(P3, v)) <= 1e-11
+            assert blockerr(precond.pch_apply(inner_ex, v), np.linalg.solve(P3, v)) <= 1e-11
     finally:
         if inst is not None:
             pfc.pfc_instance_destroy(inst)
@@ -138,7 +138,7 @@ def test_mesh_from_csr_equals_p1_assembly(pfc):
         x2 = dev(np.zeros(3 * n))
         pfc.pfc_solve(i1, n, dev(P.psi), r, -0.3, tau, m11, dev(b), x1)
         pfc.pfc_solve(i2, n, dev(P.psi), r, -0.3, tau, m11, dev(b), x2)
-        assert rel(host(x1), host(x2)) <= 1e-10
+        assert blockerr(host(x1), host(x2)) <= 1e-10
         # invalid CSR: a node pair of an element missing from the pattern
         rp_bad = P.M.indptr.copy()
         with pytest.raises(pfc.PFCError):

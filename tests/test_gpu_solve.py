@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from helpers import Problem, dev, host, rel
+from helpers import Problem, blockerr, dev, host, rel
 from oracle import assembly, pfc as opfc, reference, solve as osolve
 
 pytestmark = pytest.mark.gpu
@@ -45,7 +45,7 @@ def test_solve_replay_parity(pfc, dim, N, jit, tau, prec):
         x = dev(np.zeros(3 * n))
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
         assert gi["outer_iters"] == info["steps"]
-        assert rel(host(x), y_ref) <= 1e-10
+        assert blockerr(host(x), y_ref) <= 1e-10
         assert st == pfc.PFC_OK
     finally:
         if inst is not None:
@@ -68,7 +68,7 @@ def test_single_reduction_pcg_replay_parity(pfc, dim, N, jit, tau):
         s = info["schedule"]
         x = dev(np.zeros(3 * n))
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
-        assert rel(host(x), y_ref) <= 1e-10
+        assert blockerr(host(x), y_ref) <= 1e-10
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
         res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, tau, M11, host(x))) / np.linalg.norm(b)
         assert st == pfc.PFC_OK and res <= 1e-8
@@ -111,7 +111,7 @@ def test_solve_tolerance_mode(pfc, dim, N, jit, tau, prec):
         inst2 = pfc.pfc_instance_create(P.gpu_mesh(), opts)
         try:
             st2, _ = pfc.pfc_solve(inst2, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
-            assert rel(host(x), y_t) <= 1e-10 if prec == 0 else rel(host(x), y_t) <= 1e-8
+            assert blockerr(host(x), y_t) <= 1e-10 if prec == 0 else blockerr(host(x), y_t) <= 1e-8
         finally:
             pfc.pfc_instance_destroy(inst2)
     finally:
@@ -154,7 +154,7 @@ def test_fft_exact_agreement(pfc):
         inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(outer_tol=1e-12))
         x = dev(np.zeros(3 * n))
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, -0.3, tau, M11, dev(b), x)
-        assert rel(host(x), yf) <= 1e-10, gi
+        assert blockerr(host(x), yf) <= 1e-10, gi
     finally:
         if inst is not None:
             pfc.pfc_instance_destroy(inst)
@@ -175,7 +175,7 @@ def test_rosenbrock_run_replay_parity(pfc, dim, N, jit, tau):
         reps = [(i["schedule"].cycles, i["schedule"].inner) for i in infos]
         st, gi = pfc.pfc_rosenbrock_run(inst, n, state, r, psibar, tau, steps, pfc.PFC_INIT_CONSISTENT, replays=reps)
         assert [g["outer_iters"] for g in gi] == [i["steps"] for i in infos]
-        assert rel(host(state), x_ref) <= 1e-10
+        assert blockerr(host(state), x_ref) <= 1e-10
         # tolerance mode: conservation of int psi_h and closeness to the oracle trajectory
         state2 = dev(np.concatenate([np.zeros(n), P.psi, np.zeros(n)]))
         st2, gi2 = pfc.pfc_rosenbrock_run(inst, n, state2, r, psibar, tau, steps, pfc.PFC_INIT_CONSISTENT)
@@ -284,7 +284,7 @@ def test_extreme_parameters_and_status_codes(pfc):
         x = dev(np.zeros(3 * n))
         inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default())
         insts.append(inst)
-        # the paper accepts steps up to 18 with this preconditioner (Section 6); tau* = 12.26 here
+        # the paper accepts steps up to 18 with this preconditioner (Section 7); tau* = 12.26 here
         tau = 18.0
         assert tau >= pfc.pfc_tau_critical(r, psibar)
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
@@ -333,7 +333,7 @@ def test_schur_D_variant_parity(pfc, dim, N, jit, tau, prec):
         if prec == 0:
             s = info["schedule"]
             st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
-            assert rel(host(x), y_ref) <= 1e-10
+            assert blockerr(host(x), y_ref) <= 1e-10
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
         res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, tau, M11, host(x))) / np.linalg.norm(b)
         assert st == pfc.PFC_OK and res <= 1e-8
@@ -401,7 +401,7 @@ def test_gamma_literal_and_fixed_inner_counts(pfc, dim, N, jit, tau):
         insts.append(inst)
         s = info["schedule"]
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
-        assert gi["outer_iters"] == info["steps"] and rel(host(x), y_ref) <= 1e-10
+        assert gi["outer_iters"] == info["steps"] and blockerr(host(x), y_ref) <= 1e-10
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
         res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, tau, M11, host(x))) / np.linalg.norm(b)
         assert st == pfc.PFC_OK and res <= 1e-8
@@ -413,7 +413,7 @@ def test_gamma_literal_and_fixed_inner_counts(pfc, dim, N, jit, tau):
         st, gi = pfc.pfc_solve(inst2, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
         got = pfc.pfc_last_inner_counts(inst2)
         assert (got == np.array(fc)).all()
-        assert gi["outer_iters"] == info_f["steps"] and rel(host(x), y_f) <= 1e-10
+        assert gi["outer_iters"] == info_f["steps"] and blockerr(host(x), y_f) <= 1e-10
     finally:
         for i in insts:
             pfc.pfc_instance_destroy(i)
@@ -455,7 +455,7 @@ def test_two_pcg_iterations_per_launch(pfc, N, jit, tau):
         s = info["schedule"]
         x = dev(np.zeros(3 * n))
         st, gi = pfc.pfc_solve(insts[0], n, dev(P.psi), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
-        assert gi["outer_iters"] == info["steps"] and rel(host(x), y_ref) <= 1e-10
+        assert gi["outer_iters"] == info["steps"] and blockerr(host(x), y_ref) <= 1e-10
         # odd and even fixed counts, including 1
         fixed = [3, 1, 4, 5, 2]
         y_fix, info_f = osolve.solve_stage(P.M, P.K, Nm, r, tau, M11, b, tol=1e-8, inner_fixed=fixed, max_steps=6)
@@ -463,7 +463,7 @@ def test_two_pcg_iterations_per_launch(pfc, N, jit, tau):
         insts.append(inst)
         x = dev(np.zeros(3 * n))
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
-        assert gi["outer_iters"] == info_f["steps"] and rel(host(x), y_fix) <= 1e-10
+        assert gi["outer_iters"] == info_f["steps"] and blockerr(host(x), y_fix) <= 1e-10
     finally:
         for i in insts:
             pfc.pfc_instance_destroy(i)
@@ -472,9 +472,10 @@ def test_two_pcg_iterations_per_launch(pfc, N, jit, tau):
 
 def test_two_pcg_iterations_per_launch_large_team(pfc):
     """A 2D 600^2 grid: a team of 352 workgroups (Gram partials beyond the first 256 per thread group are
-    summed by the remainder loop) and a halo of 601 rows.  Two iterations per launch against one, both on
-    the GPU (the one-iteration path is tied to the oracle by the replay tests): the same counts, the same
-    solution to rounding, and the true residual of the tolerance."""
+    summed by the remainder loop) and a halo of 601 rows.  Both forms (two PCG iterations per launch and
+    one) replay the oracle's iteration record and reach its solution element by element; in tolerance
+    mode they take the same counts and reach the true residual of the tolerance, the two-iteration form
+    with fewer launches."""
     import workloads as wl
     mesh = wl.make_mesh(2, 600, jitter=0.2, seed=5)
     n = mesh.n
@@ -485,17 +486,26 @@ def test_two_pcg_iterations_per_launch_large_team(pfc):
         r, psibar, tau = -0.35, -0.3, 1.0
         psi = wl.psi0(n, psibar, 0.01, seed=5)
         b = np.random.default_rng(9).normal(size=3 * n)
+        M, K = assembly.mass_stiffness(mesh)
+        Nm = assembly.N_matrix(mesh, psi)
+        print("600^2: oracle stage solve", flush=True)
+        y_ref, info = osolve.solve_stage(M, K, Nm, r, tau, M11, b, tol=1e-8)
+        sch = info["schedule"]
         out = []
         for spl in (2, 1):
             inst = pfc.pfc_instance_create(h, pfc.pfc_opts_default(pcg_steps_per_launch=spl))
             insts.append(inst)
+            assert pfc.pfc_instance_config(inst)["pcg_steps_per_launch"] == spl
+            x = dev(np.zeros(3 * n))
+            print(f"600^2: {spl} PCG iteration(s) per launch, replay", flush=True)
+            st, gi = pfc.pfc_solve(inst, n, dev(psi), r, psibar, tau, M11, dev(b), x, replay=(sch.cycles, sch.inner))
+            assert gi["outer_iters"] == info["steps"] and blockerr(host(x), y_ref) <= 1e-10, spl
             x = dev(np.zeros(3 * n))
             st, gi = pfc.pfc_solve(inst, n, dev(psi), r, psibar, tau, M11, dev(b), x)
             assert st == pfc.PFC_OK and gi["true_rel_res"] <= 1e-8
             out.append((host(x), gi, pfc.pfc_last_inner_counts(inst), pfc.pfc_instance_launch_stats(inst)[0]))
         (x2, g2, c2, l2), (x1, g1, c1, l1) = out
         assert g2["outer_iters"] == g1["outer_iters"] and np.array_equal(c2, c1)
-        assert rel(x2, x1) <= 1e-10
         assert l2 < 0.8 * l1, (l2, l1)
     finally:
         for i in insts:

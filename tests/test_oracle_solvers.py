@@ -62,7 +62,7 @@ def test_unpreconditioned_gmres_agrees_with_dense_lu():
     y, info = krylov.fgmres(lambda v: A @ v, lambda v: v, b, tol=1e-11, restart=3 * mesh.n)
     yd = reference.dense_solve(A, b)
     assert np.linalg.norm(y - yd) <= 1e-8 * np.linalg.norm(yd)
-    # and the preconditioned one needs far fewer steps (Section 6, Fig. precon_no-precon)
+    # and the preconditioned one needs far fewer steps (Section 7, Fig. precon_no-precon)
     _, info_p = solve.solve_stage(M, K, assembly.N_matrix(mesh, psi), r, tau, 1.0, b, tol=1e-11)
     assert info_p["steps"] < info["steps"]
 

@@ -6,11 +6,11 @@ psi_0 and the per-instance parameter draws.  It computes nothing of the
 method itself (no integrals, no matrices, no solver steps), so both sides can
 take their inputs from here without sharing arithmetic.
 
-Workload shapes follow the paper's numerical studies (Section 6): periodic
+Workload shapes follow the paper's numerical studies (Section 7): periodic
 regular simplicial meshes, a constant mean density psibar plus small noise, a
 crystalline parameter regime (psibar^2 < -r/3, Lemma 3 and the remark after
 it).  The grid spacing is h = (2*pi/sqrt(3))/8, i.e. eight points per half
-lattice spacing d/2 with d = 4*pi/sqrt(3) (Section 6 uses d and h ~ d/10).
+lattice spacing d/2 with d = 4*pi/sqrt(3) (Section 7 uses d and h ~ d/10).
 """
 from __future__ import annotations
 
@@ -20,7 +20,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-# Lattice spacing of the single-mode approximation, d = 4*pi/sqrt(3) (Section 6).
+# Lattice spacing of the single-mode approximation, d = 4*pi/sqrt(3) (Section 7).
 LATTICE_D = 4.0 * math.pi / math.sqrt(3.0)
 # Grid spacing used for every synthetic workload: 64 cells span 8 half-lattice
 # spacings, L = 64*(2*pi/sqrt(3))/8.
