@@ -195,7 +195,7 @@ def bench_batched(args, torch, wl, pfc):
     n = mesh.n
     h = pfc.pfc_mesh_create_p1(2, n, mesh.elem_nodes, mesh.elem_coords)
     prm = wl.draw_params(count, 7000)
-    steps = args.steps if args.steps is not None else 1
+    steps = args.steps if args.steps is not None else 2
     dev = torch.device("cuda:0")
 
     def states():
@@ -207,13 +207,24 @@ def bench_batched(args, torch, wl, pfc):
         return out
 
     res = {}
-    for label, prec, shared in (("batched_mixed", 1, 1), ("batched_fp64", 0, 1)):
-        insts = [pfc.pfc_instance_create(h, pfc.pfc_opts_default(precision=prec, shared_ops=shared,
-                                                                 rows_per_thread=rpt))
-                 for _ in range(count)]
+    # launch configurations: the autotuner's choice for this batch (from the cache, or measured now), and
+    # the hand-picked one of earlier measurements (4 rows per thread, operators formed on the fly)
+    tuned = {prec: pfc.pfc_autotune(h, prec, count) for prec in (1, 0)}
+    runs = [("batched_mixed", 1, pfc.tuned_opts(tuned[1], precision=1)),
+            ("batched_fp64", 0, pfc.tuned_opts(tuned[0], precision=0))]
+    if not args.no_handpicked:
+        runs.append(("batched_mixed_handpicked", 1, pfc.pfc_opts_default(precision=1, shared_ops=1,
+                                                                         rows_per_thread=rpt)))
+    for label, prec, opts in runs:
+        insts = [pfc.pfc_instance_create(h, opts) for _ in range(count)]
         st = states()
         pfc.pfc_batch_run(insts, [n] * count, st, [p.r for p in prm], [p.psibar for p in prm],
                           [p.tau for p in prm], 0, pfc.PFC_INIT_CONSISTENT)
+        if args.warmup > 0:   # untimed steps from a copy of the states (the timed steps start from x_0)
+            warm = [x.clone() for x in st]
+            pfc.pfc_batch_run(insts, [n] * count, warm, [p.r for p in prm], [p.psibar for p in prm],
+                              [p.tau for p in prm], args.warmup, pfc.PFC_INIT_GIVEN)
+            del warm
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         code, infos = pfc.pfc_batch_run(insts, [n] * count, st, [p.r for p in prm], [p.psibar for p in prm],
@@ -227,7 +238,9 @@ def bench_batched(args, torch, wl, pfc):
         res[label] = dict(solves_per_s=3 * steps * count / dt, seconds=dt, status=pfc.pfc_status_str(code),
                           max_true_rel_res=resid, algorithmic_GBps=alg / dt / 1e9,
                           hbm_frac=alg / dt / 1e9 / HBM_PEAK_GBS)
-        if not args.no_precision_check:
+        res[label]["config"] = {k: getattr(opts, k) for k in ("rows_per_thread", "ticks_per_graph",
+                                                              "pcg_steps_per_launch", "grid_columns", "shared_ops")}
+        if label != "batched_mixed_handpicked" and not args.no_precision_check:
             # sampled instances against the oracle's float64 run of the same steps (not timed)
             res[label]["err_vs_oracle_fp64"] = sampled_oracle_errors(
                 mesh, [(k, prm[k], st[k].cpu().numpy()) for k in (0, count // 2, count - 1)], steps)
@@ -235,7 +248,8 @@ def bench_batched(args, torch, wl, pfc):
             pfc.pfc_instance_destroy(i)
     # plain float64 solver, one instance at a time, on a sample of the same instances
     sample = min(count, args.plain_sample)
-    inst = pfc.pfc_instance_create(h, pfc.pfc_opts_default())
+    plain_tuned = pfc.pfc_autotune(h, 0, 1)
+    inst = pfc.pfc_instance_create(h, pfc.tuned_opts(plain_tuned, precision=0))
     st = states()[:sample]
     for k in range(sample):
         p = prm[k]
@@ -247,14 +261,16 @@ def bench_batched(args, torch, wl, pfc):
         pfc.pfc_rosenbrock_run(inst, n, st[k], p.r, p.psibar, p.tau, steps, pfc.PFC_INIT_GIVEN)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    res["plain_fp64_sequential"] = dict(solves_per_s=3 * steps * sample / dt, seconds=dt, instances=sample)
+    res["plain_fp64_sequential"] = dict(solves_per_s=3 * steps * sample / dt, seconds=dt, instances=sample,
+                                        autotune=plain_tuned)
     pfc.pfc_instance_destroy(inst)
     pfc.pfc_mesh_destroy(h)
     out = {"metric": "PFC block solves/s @1e-8 rel residual", "value": res["batched_mixed"]["solves_per_s"],
-           "unit": "stage solves/s", "n_gpus": 1, "steps": steps, "warmup": 0, "higher_is_better": True,
+           "unit": "stage solves/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup, "higher_is_better": True,
            "dtype": "f64 outer / f32 inner", "data": "synthetic",
            "config": {"workload": f"pfc2d_128_batched{count}_mixed", "instances": count, "grid": N, "nodes": n,
-                      "rows_per_thread": rpt},
+                      "launch": res["batched_mixed"]["config"], "launch_chosen_by": "autotuner",
+                      "autotune": tuned[1]},
            "speedup_vs_plain_fp64": res["batched_mixed"]["solves_per_s"] / res["plain_fp64_sequential"]["solves_per_s"],
            "detail": res}
     print(json.dumps(out), flush=True)
@@ -276,8 +292,15 @@ def bench_served(args, torch, wl, pfc):
     def stream(rate):
         return wl.served_stream(nreq, rate, 4242)
 
-    def serve(prec, slots, rate, rpt, keep=()):
-        so = pfc.pfc_server_opts(C.sizeof(pfc.pfc_server_opts), prec, 96 << 30, slots, 0, rpt)
+    # the autotuner's rows per thread for each class alone and with many requests resident (the servers
+    # below take each request's choice from this table by the number of active requests)
+    tune_counts = sorted({1, max(1, args.slots // 2)})
+    tuned = {f"{d}D {N} {'mixed' if prec else 'fp64'} x{c}": pfc.pfc_autotune(hm, prec, c)
+             for (d, N), (_, hm) in zip(classes, meshes) for prec in (1, 0) for c in tune_counts
+             if prec == 1 or c == 1}
+
+    def serve(prec, slots, rate, rpt, keep=(), use_tuned=1):
+        so = pfc.pfc_server_opts(C.sizeof(pfc.pfc_server_opts), prec, 96 << 30, slots, 0, rpt, use_tuned)
         srv = C.c_void_p()
         assert pfc._lib.pfc_server_create(C.byref(so), C.byref(srv)) == 0
         reqs = stream(rate)
@@ -325,6 +348,8 @@ def bench_served(args, torch, wl, pfc):
     ours_bl, kept = serve(1, args.slots, 0.0, rpt, keep=set(sample.values()))
     base, _ = serve(0, 1, rate, 0)
     ours, _ = serve(1, args.slots, rate, rpt)
+    # the same backlogged stream with the load rule instead of the table (for comparison)
+    ours_rule, _ = serve(1, args.slots, 0.0, rpt, use_tuned=0)
     if not args.no_precision_check:
         reqs0 = stream(0.0)
         errs = {}
@@ -341,9 +366,11 @@ def bench_served(args, torch, wl, pfc):
            "data": "synthetic",
            "config": {"workload": "served_stream", "requests": nreq, "rosenbrock_steps": steps,
                       "classes": [f"{d}D {N}" for d, N in classes], "arrival_rate_hz": rate, "slots": args.slots,
-                      "rows_per_thread": rpt},
+                      "rows_per_thread": "autotuner table by class and load" if rpt == 0 else rpt,
+                      "autotune": {k: {f: v[f] for f in ("rows_per_thread", "ms_per_step", "ms_default", "from_cache")}
+                                   for k, v in tuned.items()}},
            "speedup_vs_plain_fp64_fifo": ours_bl["solves_per_s"] / base_bl["solves_per_s"],
-           "backlogged": {"mixed_continuous": ours_bl, "fp64_fifo": base_bl},
+           "backlogged": {"mixed_continuous": ours_bl, "fp64_fifo": base_bl, "mixed_continuous_load_rule": ours_rule},
            "poisson": {"mixed_continuous": ours, "fp64_fifo": base}}
     print(json.dumps(out), flush=True)
 
@@ -450,6 +477,11 @@ def main():
     ap.add_argument("--no-precision-check", action="store_true",
                     help="skip the untimed float64 comparison step of mixed-precision workloads (profiled runs)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1501_06852_amd", "tune_cache.json"),
+                    help="autotuning table to start from (JSON; missing entries are measured)")
+    ap.add_argument("--tune-save", default=None, help="write the autotuning table here afterwards")
+    ap.add_argument("--retune", action="store_true", help="start from an empty autotuning table")
+    ap.add_argument("--no-handpicked", action="store_true", help="batched: skip the hand-picked comparison run")
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--plain-sample", type=int, default=16)
     ap.add_argument("--requests", type=int, default=48)
@@ -469,6 +501,11 @@ def main():
 
     if args.workload == "copy_calibration":
         return bench_copy_calibration(torch)
+    if not args.retune and os.path.exists(args.tune_cache):
+        pfc.pfc_tune_load(args.tune_cache)
+    if args.tune_save:
+        import atexit
+        atexit.register(lambda: pfc.pfc_tune_save(args.tune_save))
     if args.workload == "batched":
         return bench_batched(args, torch, wl, pfc)
     if args.workload == "served":
@@ -492,8 +529,13 @@ def main():
     z = nnz / n
     model = var.get("model", 0)
     schur = var.get("schur_variant", 0)
-    opts = pfc.pfc_opts_default(precision=prec, max_run_steps=max(steps, args.warmup, 1), model=model,
-                                schur_variant=schur)
+    tuned = None
+    if not var:   # the launch configuration of the autotuner (the variants run the defaults)
+        tuned = pfc.pfc_autotune(h, prec, 1)
+        opts = pfc.tuned_opts(tuned, precision=prec, max_run_steps=max(steps, args.warmup, 1))
+    else:
+        opts = pfc.pfc_opts_default(precision=prec, max_run_steps=max(steps, args.warmup, 1), model=model,
+                                    schur_variant=schur)
     inst = pfc.pfc_instance_create(h, opts)
     if "smooth" in var:
         psi = wl.psi_smooth(mesh, psibar, var["smooth"][0], kmax=var["smooth"][1], seed=args.seed)
@@ -551,7 +593,9 @@ def main():
                    "element_degree": mesh.degree, "model": "PFC1" if model == 1 else "PFC2",
                    "schur": "S_D" if schur else "S_CH", "initial_state": "smooth" if "smooth" in var else "noise",
                    "columns": (f"computed from the row (periodic grid, side {gside})" if gside else "read from memory"),
-                   "pcg_steps_per_launch": pfc.pfc_instance_config(inst)["pcg_steps_per_launch"]},
+                   "pcg_steps_per_launch": pfc.pfc_instance_config(inst)["pcg_steps_per_launch"],
+                   "launch": pfc.pfc_instance_config(inst),
+                   "launch_chosen_by": "autotuner" if tuned else "defaults", "autotune": tuned},
         "status": pfc.pfc_status_str(st),
         "max_true_rel_res": max(res) if res else None,
         "outer_iters_mean": float(np.mean([i["outer_iters"] for i in infos])),

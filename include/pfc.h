@@ -86,7 +86,8 @@ typedef struct pfc_server pfc_server;
  *                 more bytes per iteration; useful when many instances share a mesh)
  *   rows_per_thread  rows of the mesh handled per thread in each phase (1..8; 0 means 1)
  *   max_run_steps capacity of per-stage info records of a Rosenbrock run (steps)
- *   ticks_per_graph  solver phases captured per replayed graph (0 = auto)
+ *   ticks_per_graph  solver phases captured per replayed graph (0: 64, or in
+ *                 pfc_batch_run the autotuning table's value for the batch)
  *   single_reduction 0: inner PCG in the standard form (two reductions, two
  *                 launches per iteration); 1: the Chronopoulos-Gear form of the
  *                 same iteration (one reduction, one launch per iteration;
@@ -407,6 +408,50 @@ int pfc_batch_run(pfc_instance* const* insts, int count, double* const* states,
                   const double* r, const double* psibar, const double* tau, int n_steps,
                   int init, pfc_solve_info* infos, void* stream);
 
+/* ---- autotuning -------------------------------------------------------------
+ * The launch configuration of the solver kernel (rows per thread, launches per
+ * captured graph, PCG iterations per launch of a lone instance, computed or
+ * read grid columns, stored or on-the-fly M + c K operators) is chosen by
+ * measurement: pfc_autotune times one Rosenbrock step of `count` instances of
+ * a mesh on synthetic states (psi = -0.3 + U[-0.01, 0.01] from a counter-based
+ * generator, consistent mu and omega, r = -0.35, tau = 0.5) for candidate
+ * configurations, coordinate descent from the defaults one knob at a time, and
+ * keeps the fastest in a process-wide table.  The table is keyed by (device
+ * architecture, dim, n, stored entries per row, precision, count); a lookup
+ * for `count` instances takes the entry with the largest tuned count <= count.
+ * pfc_batch_run takes its launches per graph from the table when the
+ * instances' ticks_per_graph is 0, and a server created with `tuned` takes
+ * each request's rows per thread from it.  The table is saved to and loaded
+ * from a JSON file: {"format": "pfc-tune-1", "entries": [{...}, ...]}. */
+typedef struct pfc_tune_entry {
+    int struct_size;
+    char arch[32];            /* device architecture, e.g. "gfx950" */
+    int dim, n, z, precision, count;                 /* key */
+    int rows_per_thread, ticks_per_graph, pcg_steps_per_launch, grid_columns, shared_ops;  /* choice */
+    double ms_per_step;       /* one Rosenbrock step of all `count` instances with the choice */
+    double ms_default;        /* the same with the default options */
+    int candidates;           /* configurations timed */
+    int from_cache;           /* 1: returned from the table, not measured by this call */
+} pfc_tune_entry;
+
+/* Tune (or, unless force, return the table's entry for exactly this count).
+ * mesh and precision as for an instance; count >= 1 instances per launch.
+ * Allocates and frees `count` instances per candidate; PFC_ERR_OOM if even
+ * the default configuration does not fit 80% of the free device memory.
+ * out: host record.  Synchronous on `stream`. */
+int pfc_autotune(pfc_mesh* mesh, int precision, int count, int force, pfc_tune_entry* out, void* stream);
+/* Table entry for `count` instances of a mesh with these sizes (arch: NULL
+ * for the current device's); PFC_ERR_STATE if the table has none.  Host only
+ * when arch is given. */
+int pfc_tune_lookup(const char* arch, int dim, int n, int z, int precision, int count, pfc_tune_entry* out);
+/* Merge the entries of a cache file into the table (an entry with the same
+ * key and count replaces the table's); PFC_ERR_ARG if the file cannot be read
+ * or is not such a cache. */
+int pfc_tune_load(const char* path);
+/* Write the whole table to `path` (atomically, through a temporary file). */
+int pfc_tune_save(const char* path);
+void pfc_tune_clear(void);
+
 /* ---- serving --------------------------------------------------------------
  * A server runs a library-owned thread that keeps a set of active requests
  * resident on the GPU and advances them together (continuous batching at the
@@ -424,6 +469,10 @@ int pfc_batch_run(pfc_instance* const* insts, int count, double* const* states,
  *               More rows per thread give each request fewer, longer
  *               workgroups: more throughput when many requests share the GPU,
  *               longer solves when few do.
+ *   tuned       1: with rows_per_thread 0, take each request's rows per thread
+ *               from the autotuning table (the entry for the request's mesh
+ *               and the number of active requests including it), and use the
+ *               rule above only where the table has no entry; 0: the rule.
  *   n_steps ... Rosenbrock steps per request (set per request) */
 typedef struct pfc_server_opts {
     int struct_size;
@@ -432,6 +481,7 @@ typedef struct pfc_server_opts {
     int max_slots;
     int ticks_per_graph;
     int rows_per_thread;
+    int tuned;
 } pfc_server_opts;
 
 typedef struct pfc_result {

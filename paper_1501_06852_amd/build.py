@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpfc.so")
-SOURCES = ["mesh.hip", "solver.hip", "server.hip"]
+SOURCES = ["mesh.hip", "solver.hip", "server.hip", "tune.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 arithmetic off for all device code

@@ -83,12 +83,18 @@ pfc_opts server_instance_opts(const pfc_server* S, int rpt) {
 }
 
 // Rows per thread of a request's instance.  Fixed by the server options, or
-// (0) chosen at admission from the load: one row per thread while the active
+// (0) taken from the autotuning table for the request's mesh and the number of
+// active requests including it (option `tuned`, where the table has an entry),
+// or else chosen at admission from the load: one row per thread while the active
 // requests and this one fit into one round of resident workgroups (the
 // shortest time per request), two once they do not (fewer, longer
 // workgroups: more throughput when the GPU is full).
 int choose_rpt(const pfc_server* S, const Request* q) {
   if (S->o.rows_per_thread > 0) return S->o.rows_per_thread;
+  if (S->o.tuned) {
+    const int t = tuned_rows_per_thread(q->mesh, S->o.precision, (int)S->active.size() + 1);
+    if (t > 0) return t;
+  }
   long long rows = q->mesh->n;
   for (const Request* a : S->active) rows += a->mesh->n;
   return rows > S->resident_rows ? 2 : 1;
@@ -289,7 +295,7 @@ extern "C" {
 int pfc_server_create(const pfc_server_opts* o, pfc_server** out) {
   if (!o || !out || o->struct_size != (int)sizeof(pfc_server_opts) || o->max_slots < 1 || o->hbm_budget == 0 ||
       (o->precision != PFC_FP64 && o->precision != PFC_MIXED) || o->ticks_per_graph < 0 || o->ticks_per_graph > 4096 ||
-      o->rows_per_thread < 0 || o->rows_per_thread > 8) {
+      o->rows_per_thread < 0 || o->rows_per_thread > 8 || (o->tuned != 0 && o->tuned != 1)) {
     set_error("pfc_server_create: invalid options");
     return PFC_ERR_ARG;
   }

@@ -1672,7 +1672,11 @@ int pfc_batch_run(pfc_instance* const* insts, int count, double* const* states, 
     int rc = prep_ops(insts[i], s);
     if (rc) return rc;
   }
-  const int ticks = insts[0]->ticks;
+  int ticks = insts[0]->ticks;
+  if (insts[0]->opts.ticks_per_graph == 0) {  // auto: the autotuning table's value for this batch, if any
+    const int tt = tuned_ticks(insts[0]->mesh, prec, count);
+    if (tt > 0) ticks = tt + (tt & 1);
+  }
   int rc = PFC_OK;
   auto one_pass = [&](int precision, int steps, int initm) -> int {
     Group g;

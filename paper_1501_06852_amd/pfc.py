@@ -76,7 +76,21 @@ class pfc_schedule(C.Structure):
 
 class pfc_server_opts(C.Structure):
     _fields_ = [("struct_size", C.c_int), ("precision", C.c_int), ("hbm_budget", C.c_size_t),
-                ("max_slots", C.c_int), ("ticks_per_graph", C.c_int), ("rows_per_thread", C.c_int)]
+                ("max_slots", C.c_int), ("ticks_per_graph", C.c_int), ("rows_per_thread", C.c_int),
+                ("tuned", C.c_int)]
+
+
+class pfc_tune_entry(C.Structure):
+    _fields_ = [("struct_size", C.c_int), ("arch", C.c_char * 32), ("dim", C.c_int), ("n", C.c_int), ("z", C.c_int),
+                ("precision", C.c_int), ("count", C.c_int), ("rows_per_thread", C.c_int),
+                ("ticks_per_graph", C.c_int), ("pcg_steps_per_launch", C.c_int), ("grid_columns", C.c_int),
+                ("shared_ops", C.c_int), ("ms_per_step", C.c_double), ("ms_default", C.c_double),
+                ("candidates", C.c_int), ("from_cache", C.c_int)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "struct_size"}
+        d["arch"] = self.arch.decode()
+        return d
 
 
 class pfc_result(C.Structure):
@@ -134,6 +148,11 @@ _sig("pfc_apply_pch", C.c_int, [_vp, C.c_double, _vp, _vp, _ip, _ip, _vp])
 _sig("pfc_stage_rhs", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.c_double, _vp, _vp])
 _sig("pfc_batch_run", C.c_int, [C.POINTER(_vp), C.c_int, C.POINTER(_vp), _dp, _dp, _dp, C.c_int, C.c_int,
                                 C.POINTER(pfc_solve_info), _vp])
+_sig("pfc_autotune", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.POINTER(pfc_tune_entry), _vp])
+_sig("pfc_tune_lookup", C.c_int, [C.c_char_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(pfc_tune_entry)])
+_sig("pfc_tune_load", C.c_int, [C.c_char_p])
+_sig("pfc_tune_save", C.c_int, [C.c_char_p])
+_sig("pfc_tune_clear", None, [])
 _sig("pfc_server_create", C.c_int, [C.POINTER(pfc_server_opts), C.POINTER(_vp)])
 _sig("pfc_server_submit", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, _dp, C.c_int, C.c_uint64])
 _sig("pfc_server_poll", C.c_int, [_vp, C.POINTER(pfc_result), C.c_int, _ip])
@@ -150,7 +169,8 @@ DECLARED = [
     "pfc_solve", "pfc_solve_x", "pfc_last_inner_counts", "pfc_instance_launch_stats", "pfc_instance_config",
     "pfc_rosenbrock_run",
     "pfc_rosenbrock_adaptive", "pfc_apply_AR", "pfc_apply_AR_x", "pfc_apply_pch", "pfc_stage_rhs",
-    "pfc_batch_run", "pfc_server_create", "pfc_server_submit", "pfc_server_poll", "pfc_result_free",
+    "pfc_batch_run", "pfc_autotune", "pfc_tune_lookup", "pfc_tune_load", "pfc_tune_save", "pfc_tune_clear",
+    "pfc_server_create", "pfc_server_submit", "pfc_server_poll", "pfc_result_free",
     "pfc_server_drain", "pfc_server_clock", "pfc_server_destroy",
 ]
 
@@ -362,6 +382,45 @@ def pfc_instance_launch_stats(inst):
     a, b = C.c_longlong(), C.c_longlong()
     _check(_lib.pfc_instance_launch_stats(inst, C.byref(a), C.byref(b)), "pfc_instance_launch_stats")
     return a.value, b.value
+
+
+def pfc_autotune(mesh, precision, count, force=False, stream=None):
+    """Tune (or take from the table) the launch configuration of `count` instances; returns a dict."""
+    e = pfc_tune_entry()
+    e.struct_size = C.sizeof(pfc_tune_entry)
+    _check(_lib.pfc_autotune(mesh, precision, count, 1 if force else 0, C.byref(e), _stream(stream)), "pfc_autotune")
+    return e.as_dict()
+
+
+def pfc_tune_lookup(dim, n, z, precision, count, arch=None):
+    """The table's entry (dict) for `count` instances, or None."""
+    e = pfc_tune_entry()
+    rc = _lib.pfc_tune_lookup(None if arch is None else arch.encode(), dim, n, z, precision, count, C.byref(e))
+    if rc == PFC_ERR_STATE:
+        return None
+    _check(rc, "pfc_tune_lookup")
+    return e.as_dict()
+
+
+def pfc_tune_load(path):
+    return _check(_lib.pfc_tune_load(os.fsencode(path)), "pfc_tune_load")
+
+
+def pfc_tune_save(path):
+    return _check(_lib.pfc_tune_save(os.fsencode(path)), "pfc_tune_save")
+
+
+def pfc_tune_clear():
+    _lib.pfc_tune_clear()
+
+
+def tuned_opts(entry, **kw):
+    """pfc_opts for an instance of a tuned batch: the entry's choice plus explicit overrides."""
+    base = dict(rows_per_thread=entry["rows_per_thread"], ticks_per_graph=entry["ticks_per_graph"],
+                pcg_steps_per_launch=entry["pcg_steps_per_launch"], grid_columns=entry["grid_columns"],
+                shared_ops=entry["shared_ops"])
+    base.update(kw)
+    return pfc_opts_default(**base)
 
 
 def pfc_instance_config(inst):

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from helpers import Problem, blockerr, dev, host, rel
+from helpers import Problem, blockerr, dev, entryerr, host, rel
 from oracle import assembly, mobility as mob, pfc as opfc, solve as osolve
 
 pytestmark = pytest.mark.gpu
@@ -95,7 +95,7 @@ def test_pfc1_solve_replay_and_tolerance(pfc, dim, N, jit, tau, km):
         x = dev(np.zeros(3 * n))
         st, gi = pfc.pfc_solve_x(inst, n, dev(x0), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
         assert gi["outer_iters"] == info["steps"]
-        assert blockerr(host(x), y_ref) <= 1e-10
+        assert entryerr(host(x), y_ref) <= 1e-10
         st, gi = pfc.pfc_solve_x(inst, n, dev(x0), r, psibar, tau, M11, dev(b), x)
         res = np.linalg.norm(b - mob.apply_AR1(P.M, P.K, N_, Kp, Fm, r, tau, M11, host(x))) / np.linalg.norm(b)
         assert st == pfc.PFC_OK and res <= 1e-8
@@ -129,7 +129,7 @@ def test_pfc1_rosenbrock_replay_parity(pfc, dim, N, jit, tau):
         reps = [(i["schedule"].cycles, i["schedule"].inner) for i in infos]
         st, gi = pfc.pfc_rosenbrock_run(inst, n, state, r, psibar, tau, steps, pfc.PFC_INIT_CONSISTENT, replays=reps)
         assert [g["outer_iters"] for g in gi] == [i["steps"] for i in infos]
-        assert blockerr(host(state), x_ref) <= 1e-10
+        assert entryerr(host(state), x_ref) <= 1e-10
         # tolerance mode stays on the oracle's trajectory and conserves int psi_h
         state2 = dev(np.concatenate([np.zeros(n), P.psi, np.zeros(n)]))
         st2, gi2 = pfc.pfc_rosenbrock_run(inst, n, state2, r, psibar, tau, steps, pfc.PFC_INIT_CONSISTENT)

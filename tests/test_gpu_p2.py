@@ -6,7 +6,7 @@ unchanged FGMRES / P_CH / PCG solver on the wider P2 pattern."""
 import numpy as np
 import pytest
 
-from helpers import Problem, blockerr, dev, host, rel
+from helpers import Problem, blockerr, dev, entryerr, host, rel
 from oracle import assembly, pfc as opfc, solve as osolve
 
 pytestmark = pytest.mark.gpu
@@ -92,7 +92,7 @@ def test_p2_solve_replay_and_tolerance(pfc, dim, N, jit, tau):
         x = dev(np.zeros(3 * n))
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
         assert gi["outer_iters"] == info["steps"]
-        assert blockerr(host(x), y_ref) <= 1e-10
+        assert entryerr(host(x), y_ref) <= 1e-10
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
         res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, N_, r, tau, M11, host(x))) / np.linalg.norm(b)
         assert st == pfc.PFC_OK and res <= 1e-8
@@ -124,7 +124,7 @@ def test_p2_rosenbrock_replay_parity(pfc, dim, N, jit, tau):
         reps = [(i["schedule"].cycles, i["schedule"].inner) for i in infos]
         st, gi = pfc.pfc_rosenbrock_run(inst, n, state, r, psibar, tau, steps, pfc.PFC_INIT_CONSISTENT, replays=reps)
         assert [g["outer_iters"] for g in gi] == [i["steps"] for i in infos]
-        assert blockerr(host(state), x_ref) <= 1e-10
+        assert entryerr(host(state), x_ref) <= 1e-10
     finally:
         if inst is not None:
             pfc.pfc_instance_destroy(inst)

@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from helpers import Problem, blockerr, dev, host, rel
+from helpers import Problem, blockerr, dev, entryerr, host, rel
 from oracle import assembly, pfc as opfc, reference, solve as osolve
 
 pytestmark = pytest.mark.gpu
@@ -45,7 +45,7 @@ def test_solve_replay_parity(pfc, dim, N, jit, tau, prec):
         x = dev(np.zeros(3 * n))
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
         assert gi["outer_iters"] == info["steps"]
-        assert blockerr(host(x), y_ref) <= 1e-10
+        assert entryerr(host(x), y_ref) <= 1e-10
         assert st == pfc.PFC_OK
     finally:
         if inst is not None:
@@ -68,7 +68,7 @@ def test_single_reduction_pcg_replay_parity(pfc, dim, N, jit, tau):
         s = info["schedule"]
         x = dev(np.zeros(3 * n))
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
-        assert blockerr(host(x), y_ref) <= 1e-10
+        assert entryerr(host(x), y_ref) <= 1e-10
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
         res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, tau, M11, host(x))) / np.linalg.norm(b)
         assert st == pfc.PFC_OK and res <= 1e-8
@@ -111,7 +111,7 @@ def test_solve_tolerance_mode(pfc, dim, N, jit, tau, prec):
         inst2 = pfc.pfc_instance_create(P.gpu_mesh(), opts)
         try:
             st2, _ = pfc.pfc_solve(inst2, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
-            assert blockerr(host(x), y_t) <= 1e-10 if prec == 0 else blockerr(host(x), y_t) <= 1e-8
+            assert rel(host(x), y_t) <= 1e-10 if prec == 0 else rel(host(x), y_t) <= 1e-8
         finally:
             pfc.pfc_instance_destroy(inst2)
     finally:
@@ -154,7 +154,7 @@ def test_fft_exact_agreement(pfc):
         inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(outer_tol=1e-12))
         x = dev(np.zeros(3 * n))
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, -0.3, tau, M11, dev(b), x)
-        assert blockerr(host(x), yf) <= 1e-10, gi
+        assert entryerr(host(x), yf) <= 1e-10, gi
     finally:
         if inst is not None:
             pfc.pfc_instance_destroy(inst)
@@ -175,7 +175,7 @@ def test_rosenbrock_run_replay_parity(pfc, dim, N, jit, tau):
         reps = [(i["schedule"].cycles, i["schedule"].inner) for i in infos]
         st, gi = pfc.pfc_rosenbrock_run(inst, n, state, r, psibar, tau, steps, pfc.PFC_INIT_CONSISTENT, replays=reps)
         assert [g["outer_iters"] for g in gi] == [i["steps"] for i in infos]
-        assert blockerr(host(state), x_ref) <= 1e-10
+        assert entryerr(host(state), x_ref) <= 1e-10
         # tolerance mode: conservation of int psi_h and closeness to the oracle trajectory
         state2 = dev(np.concatenate([np.zeros(n), P.psi, np.zeros(n)]))
         st2, gi2 = pfc.pfc_rosenbrock_run(inst, n, state2, r, psibar, tau, steps, pfc.PFC_INIT_CONSISTENT)
@@ -333,7 +333,7 @@ def test_schur_D_variant_parity(pfc, dim, N, jit, tau, prec):
         if prec == 0:
             s = info["schedule"]
             st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
-            assert blockerr(host(x), y_ref) <= 1e-10
+            assert entryerr(host(x), y_ref) <= 1e-10
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
         res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, tau, M11, host(x))) / np.linalg.norm(b)
         assert st == pfc.PFC_OK and res <= 1e-8
@@ -401,7 +401,7 @@ def test_gamma_literal_and_fixed_inner_counts(pfc, dim, N, jit, tau):
         insts.append(inst)
         s = info["schedule"]
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
-        assert gi["outer_iters"] == info["steps"] and blockerr(host(x), y_ref) <= 1e-10
+        assert gi["outer_iters"] == info["steps"] and entryerr(host(x), y_ref) <= 1e-10
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
         res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, tau, M11, host(x))) / np.linalg.norm(b)
         assert st == pfc.PFC_OK and res <= 1e-8
@@ -413,7 +413,7 @@ def test_gamma_literal_and_fixed_inner_counts(pfc, dim, N, jit, tau):
         st, gi = pfc.pfc_solve(inst2, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
         got = pfc.pfc_last_inner_counts(inst2)
         assert (got == np.array(fc)).all()
-        assert gi["outer_iters"] == info_f["steps"] and blockerr(host(x), y_f) <= 1e-10
+        assert gi["outer_iters"] == info_f["steps"] and entryerr(host(x), y_f) <= 1e-10
     finally:
         for i in insts:
             pfc.pfc_instance_destroy(i)
@@ -455,7 +455,7 @@ def test_two_pcg_iterations_per_launch(pfc, N, jit, tau):
         s = info["schedule"]
         x = dev(np.zeros(3 * n))
         st, gi = pfc.pfc_solve(insts[0], n, dev(P.psi), r, psibar, tau, M11, dev(b), x, replay=(s.cycles, s.inner))
-        assert gi["outer_iters"] == info["steps"] and blockerr(host(x), y_ref) <= 1e-10
+        assert gi["outer_iters"] == info["steps"] and entryerr(host(x), y_ref) <= 1e-10
         # odd and even fixed counts, including 1
         fixed = [3, 1, 4, 5, 2]
         y_fix, info_f = osolve.solve_stage(P.M, P.K, Nm, r, tau, M11, b, tol=1e-8, inner_fixed=fixed, max_steps=6)
@@ -463,7 +463,7 @@ def test_two_pcg_iterations_per_launch(pfc, N, jit, tau):
         insts.append(inst)
         x = dev(np.zeros(3 * n))
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
-        assert gi["outer_iters"] == info_f["steps"] and blockerr(host(x), y_fix) <= 1e-10
+        assert gi["outer_iters"] == info_f["steps"] and entryerr(host(x), y_fix) <= 1e-10
     finally:
         for i in insts:
             pfc.pfc_instance_destroy(i)
@@ -499,7 +499,7 @@ def test_two_pcg_iterations_per_launch_large_team(pfc):
             x = dev(np.zeros(3 * n))
             print(f"600^2: {spl} PCG iteration(s) per launch, replay", flush=True)
             st, gi = pfc.pfc_solve(inst, n, dev(psi), r, psibar, tau, M11, dev(b), x, replay=(sch.cycles, sch.inner))
-            assert gi["outer_iters"] == info["steps"] and blockerr(host(x), y_ref) <= 1e-10, spl
+            assert gi["outer_iters"] == info["steps"] and entryerr(host(x), y_ref) <= 1e-10, spl
             x = dev(np.zeros(3 * n))
             st, gi = pfc.pfc_solve(inst, n, dev(psi), r, psibar, tau, M11, dev(b), x)
             assert st == pfc.PFC_OK and gi["true_rel_res"] <= 1e-8

@@ -158,3 +158,36 @@ def test_fixed_inner_counts():
     # replaying the counts of an apply reproduces it exactly
     rep = precond.InnerSolvers(M, K, 0.5, replay_counts=[mixed.counts[0]])
     assert np.array_equal(precond.pch_apply(rep, v), z)
+
+
+def test_replay_sensitivity_by_block():
+    """How far a rounding-level change of the system moves each block of a replayed Rosenbrock run
+    (the scale the GPU replay parity is measured on).  The oracle replays its own iteration record
+    with M and K perturbed by one unit in the last place per entry (symmetric).  The psi block, about
+    1/1700 of mu in size here, then moves by more than 1e-9 of its own largest entry, over ten times
+    what the state moves against its largest entry: a rounding-level change moves the blocks by
+    similar absolute amounts.  A per-block relative bound of 1e-10 would fail implementations that
+    only sum in another order; the replay tests bound every entry against the state's largest entry
+    instead (and log the per-block figures)."""
+    import scipy.sparse as sp
+
+    def perturb(A, seed):
+        g = np.random.default_rng(seed)
+        U = sp.triu(A, 1).tocsr()
+        U.data *= 1.0 + 2.2e-16 * g.uniform(-1.0, 1.0, U.data.size)
+        d = A.diagonal() * (1.0 + 2.2e-16 * g.uniform(-1.0, 1.0, A.shape[0]))
+        return (U + U.T + sp.diags(d)).tocsr()
+
+    mesh = wl.make_mesh(3, 4, jitter=0.1, seed=9)
+    M, K = assembly.mass_stiffness(mesh)
+    psi = wl.psi0(mesh.n, -0.3, 0.05, seed=9)
+    r, tau, n = -0.35, 0.5, mesh.n
+    x0 = pfc.consistent_init(mesh, M, K, r, psi)
+    x1, infos = solve.rosenbrock_run(mesh, M, K, x0, r, tau, 2, tol=1e-8)
+    M2, K2 = perturb(M, 1), perturb(K, 2)
+    x2, _ = solve.rosenbrock_run(mesh, M2, K2, pfc.consistent_init(mesh, M2, K2, r, psi), r, tau, 2,
+                                 replays=[i["schedule"] for i in infos])
+    entry = np.max(np.abs(x2 - x1)) / np.max(np.abs(x1))
+    per_block = [np.max(np.abs(a - b)) / np.max(np.abs(b)) for a, b in zip(np.split(x2, 3), np.split(x1, 3))]
+    assert np.max(np.abs(x1[:n])) > 100 * np.max(np.abs(x1[n:2 * n]))
+    assert per_block[1] > 1e-9 and per_block[1] > 10 * entry, (per_block, entry)
