@@ -382,6 +382,27 @@ int pfc_apply_AR(pfc_instance* inst, const double* psi_k, double r, double tau, 
  * and F(mu_k), reassembled); the form PFC_MODEL_PFC1 instances require. */
 int pfc_apply_AR_x(pfc_instance* inst, const double* x_k, double r, double tau, double m11,
                    const double* y, double* out, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): out = A^R y as
+ * pfc_apply_AR, on a PFC2 mesh without an instance.  N(psi_k) is reassembled
+ * into a library-owned static device array of PFC_NOALLOC_MAX_ENTRIES float64
+ * values (32 MiB; each GPU the library runs on holds its own copy until the
+ * process ends) instead of an instance's memory; the call performs no device
+ * allocation or free.
+ *   mesh      any mesh whose stored pattern has at most PFC_NOALLOC_MAX_ENTRIES
+ *             entries (2D 512^2: 1.84M, 3D 64^3: 3.93M); a larger one returns
+ *             PFC_ERR_ARG before anything is enqueued
+ *   psi_k     device float64 [n]; y, out device float64 [3n]
+ * Unlike the other calls it only enqueues its two kernels on `stream` and
+ * returns (so it can be captured into a graph); the caller synchronises.
+ * The first call on a device resolves the array's address (no allocation);
+ * make it outside graph capture.  Every call on a GPU uses that GPU's one
+ * array: calls that overlap on one GPU (other streams, other host threads)
+ * race on it; calls on one stream are ordered and safe. */
+#define PFC_NOALLOC_MAX_ENTRIES (1 << 22)
+int pfc_apply_AR_noalloc(const pfc_mesh* mesh, const double* psi_k, double r, double tau, double m11,
+                         const double* y, double* out, void* stream);
+
 /* z = P_CH^{-1} v with parameter tau_s (the time step the preconditioner is
  * built for: tau/m11 for PFC2, M0 tau/m11 for PFC1; used as given): the five steps (1), (2), (3.1), (3.2), (4), (5) of Section 4.2 with
  * Jacobi-PCG inner solves.  fixed_counts: NULL (tolerance inner_tol) or host

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1209,6 +1210,37 @@ static int upload_schedules(pfc_instance* I, const pfc_schedule* sch, int count,
   return PFC_OK;
 }
 
+// Scratch of the allocation-free operator apply (pfc_apply_AR_noalloc): the
+// values of N(psi_k) on the mesh's stored pattern (PFC_NOALLOC_MAX_ENTRIES,
+// include/pfc.h).  Every GPU the library runs
+// on holds its own copy of this array, at its own address, until the process
+// ends; host code reaches it only through the address resolved per device
+// below (the array's name is a host-side stand-in, not a device address).
+#define PFC_NOALLOC_MAX_DEVICES 64
+static __device__ __align__(256) double scratch[PFC_NOALLOC_MAX_ENTRIES];
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[PFC_NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current device's scratch array, resolved once per
+// device (with that device current) and kept.
+static int scratch_address(double** out) {
+  int d = 0;
+  PFC_HIP(hipGetDevice(&d));
+  if (d < 0 || d >= PFC_NOALLOC_MAX_DEVICES) {
+    set_error("pfc_apply_AR_noalloc: device ordinal beyond the supported " + std::to_string(PFC_NOALLOC_MAX_DEVICES));
+    return PFC_ERR_ARG;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[d]) {
+    void* p = nullptr;
+    PFC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) { set_error("pfc_apply_AR_noalloc: no device address for the scratch array"); return PFC_ERR_HIP; }
+    g_scratch_dev[d] = (double*)p;
+  }
+  *out = g_scratch_dev[d];
+  return PFC_OK;
+}
+
 int run_single(pfc_instance* I, hipStream_t s, int job) {
   int rc = ensure_group(I);
   if (rc) return rc;
@@ -1587,6 +1619,35 @@ int pfc_apply_AR_x(pfc_instance* I, const double* x_k, double r, double tau, dou
                    void* stream) {
   if (!I || !x_k) { set_error("pfc_apply_AR_x: invalid arguments"); return PFC_ERR_ARG; }
   return apply_AR_impl(I, x_k + I->mesh->n, x_k, r, tau, m11, y, out, stream);
+}
+
+int pfc_apply_AR_noalloc(const pfc_mesh* m, const double* psi_k, double r, double tau, double m11, const double* y,
+                         double* out, void* stream) {
+  if (!m || !psi_k || !y || !out || !std::isfinite(r) || !std::isfinite(tau) || !std::isfinite(m11)) {
+    set_error("pfc_apply_AR_noalloc: invalid arguments");
+    return PFC_ERR_ARG;
+  }
+  if (m->nnz_sell > PFC_NOALLOC_MAX_ENTRIES) {
+    set_error("pfc_apply_AR_noalloc: the mesh stores " + std::to_string(m->nnz_sell) +
+              " matrix entries, more than the scratch buffer's " + std::to_string(PFC_NOALLOC_MAX_ENTRIES));
+    return PFC_ERR_ARG;
+  }
+  double* N = nullptr;
+  int rc = scratch_address(&N);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  InstDev h;
+  std::memset(&h, 0, sizeof(h));
+  h.m = m->dev;
+  h.n = m->n;
+  h.model = PFC_MODEL_PFC2;
+  h.r = r; h.tau = tau; h.m11 = m11;
+  h.N = N;
+  const int nb = slice_blocks(m->n_slices);
+  hipLaunchKernelGGL(k_assemble_N_sell, dim3(nb), dim3(PFC_WG), 0, s, h, psi_k);
+  hipLaunchKernelGGL(k_apply_AR, dim3(nb), dim3(PFC_WG), 0, s, h, y, out);
+  PFC_HIP(hipGetLastError());
+  return PFC_OK;
 }
 
 int pfc_apply_pch(pfc_instance* I, double tau_s, const double* v, double* z, const int* fixed_counts, int* counts_out,

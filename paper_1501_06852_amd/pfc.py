@@ -144,6 +144,7 @@ _sig("pfc_rosenbrock_adaptive", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_
                                           _vp])
 _sig("pfc_apply_AR", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, _vp, _vp, _vp])
 _sig("pfc_apply_AR_x", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, _vp, _vp, _vp])
+_sig("pfc_apply_AR_noalloc", C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double, _vp, _vp, _vp])
 _sig("pfc_apply_pch", C.c_int, [_vp, C.c_double, _vp, _vp, _ip, _ip, _vp])
 _sig("pfc_stage_rhs", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.c_double, _vp, _vp])
 _sig("pfc_batch_run", C.c_int, [C.POINTER(_vp), C.c_int, C.POINTER(_vp), _dp, _dp, _dp, C.c_int, C.c_int,
@@ -168,7 +169,7 @@ DECLARED = [
     "pfc_assemble_N", "pfc_load_psi3", "pfc_instance_footprint", "pfc_instance_create", "pfc_instance_destroy",
     "pfc_solve", "pfc_solve_x", "pfc_last_inner_counts", "pfc_instance_launch_stats", "pfc_instance_config",
     "pfc_rosenbrock_run",
-    "pfc_rosenbrock_adaptive", "pfc_apply_AR", "pfc_apply_AR_x", "pfc_apply_pch", "pfc_stage_rhs",
+    "pfc_rosenbrock_adaptive", "pfc_apply_AR", "pfc_apply_AR_x", "pfc_apply_AR_noalloc", "pfc_apply_pch", "pfc_stage_rhs",
     "pfc_batch_run", "pfc_autotune", "pfc_tune_lookup", "pfc_tune_load", "pfc_tune_save", "pfc_tune_clear",
     "pfc_server_create", "pfc_server_submit", "pfc_server_poll", "pfc_result_free",
     "pfc_server_drain", "pfc_server_clock", "pfc_server_destroy",
@@ -473,6 +474,12 @@ def pfc_apply_AR(inst, n, psi_k, r, tau, m11, y, out, stream=None):
 def pfc_apply_AR_x(inst, n, x_k, r, tau, m11, y, out, stream=None):
     return _check(_lib.pfc_apply_AR_x(inst, _dev(x_k, 3 * n, "x_k"), r, tau, m11, _dev(y, 3 * n, "y"),
                                       _dev(out, 3 * n, "out"), _stream(stream)), "pfc_apply_AR_x")
+
+
+def pfc_apply_AR_noalloc(mesh, n, psi_k, r, tau, m11, y, out, stream=None):
+    """Enqueues only (the C call returns without waiting); synchronise before reading `out`."""
+    return _check(_lib.pfc_apply_AR_noalloc(mesh, _dev(psi_k, n, "psi_k"), r, tau, m11, _dev(y, 3 * n, "y"),
+                                            _dev(out, 3 * n, "out"), _stream(stream)), "pfc_apply_AR_noalloc")
 
 
 def pfc_apply_pch(inst, n, tau_s, v, z, fixed_counts=None, stream=None):
