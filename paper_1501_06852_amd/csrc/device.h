@@ -747,53 +747,6 @@ __device__ __forceinline__ void block_row(const InstDev& I, const PatView<L>& pv
   });
 }
 
-template <typename T, int L, bool MOB>
-__device__ __forceinline__ Red3 ph_aspmv(const InstDev& I, const State& S, const Team& tm) {
-  const int n = I.n;
-  const PatView<L> pv = p1_pat<L>(I, tm);
-  const long long n3 = 3LL * n;
-  double* Zj = I.Z + (long long)S.j * n3;
-  const T* x2 = (const T*)I.x2;
-  const double* V0 = I.V;
-  double a0 = 0.0, a1 = 0.0;
-  PFC_SLICES(I, tm) {
-    const int i = sl * 64 + tm.lane;
-    double w0, w1, w2;
-    block_row<L, MOB>(I, pv, sl, tm.lane, I.tau_s, I.m11_s,
-              [&](int j, double& mu, double& ps, double& om) { mu = Zj[j]; ps = Zj[n + j]; om = (double)x2[j]; },
-              w0, w1, w2);
-    if (i < n) {
-      vst(I.W + i, w0); vst(I.W + n + i, w1); vst(I.W + 2 * n + i, w2);
-      vst(Zj + 2 * n + i, (double)x2[i]);
-      a0 += w0 * V0[i] + w1 * V0[n + i] + w2 * V0[2 * n + i];
-      a1 += w0 * w0 + w1 * w1 + w2 * w2;
-    }
-  }
-  return red3(a0, a1);
-}
-
-__device__ __forceinline__ Red3 ph_mgs(const InstDev& I, const State& S, const Team& tm, bool last) {
-  const int n = I.n;
-  const long long n3 = 3LL * n;
-  const int ip = last ? S.j : S.mgs_i - 1;
-  const double* vp = I.V + (long long)ip * n3;
-  const double* vi = I.V + (long long)(last ? 0 : S.mgs_i) * n3;
-  const double h = S.hprev;
-  double a0 = 0.0;
-  PFC_SLICES(I, tm) {
-    const int i = sl * 64 + tm.lane;
-    if (i < n) {
-      for (int blk = 0; blk < 3; ++blk) {
-        const long long o = (long long)blk * n + i;
-        const double w = I.W[o] - h * vp[o];
-        vst(I.W + o, w);
-        a0 += last ? w * w : w * vi[o];
-      }
-    }
-  }
-  return red3(a0, 0.0);
-}
-
 __device__ __forceinline__ Red3 ph_update_x(const InstDev& I, const State& S, const Team& tm, const double* y) {
   const int n = I.n;
   const long long n3 = 3LL * n;
@@ -1340,6 +1293,159 @@ __device__ __forceinline__ void ss_gram(const double* part, int size, const doub
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
   }
+}
+
+
+// ---- orthogonalisation of an Arnoldi step (one reduction) ----------------------
+// Modified Gram-Schmidt against v_0..v_j computes h_i = (w - sum_{k<i} h_k v_k,
+// v_i) one after the other, which needs j + 1 reductions.  Expanding the inner
+// product gives h_i = c_i - sum_{k<i} (v_i, v_k) h_k with c_i = (w, v_i): h
+// solves (I + L) h = c, L the strictly lower part of the basis' Gram matrix.
+// This equals modified Gram-Schmidt in exact arithmetic for any basis
+// (Swirydowicz, Langou, Ananthan, Yang, Thomas, "Low synchronization
+// Gram-Schmidt and GMRES algorithms", 2020).  The launch that forms w = A z_j
+// therefore also sums c_0..c_j, row j of L ((v_j, v_k), k < j) and (w, w); the
+// transition solves for h; the next launch applies w -= sum_i h_i v_i in the
+// order of modified Gram-Schmidt and sums (w, w) for h_{j+1,j}.
+// Slots of the 64 sums: c_k -> k, (v_j, v_k) -> 32 + k, (w, w) -> 32 + j.
+#define PFC_GS_NV 64
+__shared__ double pfc_gsred[PFC_WAVES * PFC_GS_NV];
+
+// Sums of 16 values over the 64 lanes of a wave by recursive halving (as
+// ss_wave_sums32 for 32): the total of value idx ends in the four lanes of a
+// quad, idx = 8 [l >= 32] + 4 [row odd] + 2 [l mod 16 >= 8] + [l mod 8 >= 4].
+__device__ __forceinline__ double gs_wave_sums16(const double* v, int lane) {
+  double w8[8], w4[4], w2[2];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) w8[k] = ss_swap<false>(v[k], v[k + 8], lane >= 32);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w4[k] = ss_swap<true>(w8[k], w8[k + 4], (lane >> 4) & 1);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) w2[k] = ss_dppx<0x140>(w4[k], w4[k + 2], (lane & 15) >= 8);  // row_mirror
+  double w1 = ss_dppx<0x141>(w2[0], w2[1], (lane & 7) >= 4);                                // row_half_mirror
+  w1 += dpp_f64<0x4e, 0xf>(w1);                                                             // quad_perm [2,3,0,1]
+  return w1 + dpp_f64<0xb1, 0xf>(w1);                                                       // quad_perm [1,0,3,2]
+}
+__device__ __forceinline__ int gs_wave_sums16_index(int lane) {
+  return (lane >= 32 ? 8 : 0) + (((lane >> 4) & 1) ? 4 : 0) + ((lane & 15) >= 8 ? 2 : 0) + ((lane & 7) >= 4 ? 1 : 0);
+}
+
+// w = A_s z_j (the block SpMV of A^R on the scaled system) and the Gram sums
+// of the orthogonalisation; the workgroup's 64 sums go to gout[rank * 64 + s].
+template <typename T, int L, bool MOB>
+__device__ __forceinline__ void ph_aspmv(const InstDev& I, const State& S, const Team& tm, double* gout) {
+  const int n = I.n;
+  const PatView<L> pv = p1_pat<L>(I, tm);
+  const long long n3 = 3LL * n;
+  double* Zj = I.Z + (long long)S.j * n3;
+  const T* x2 = (const T*)I.x2;
+  PFC_SLICES(I, tm) {
+    const int i = sl * 64 + tm.lane;
+    double w0, w1, w2;
+    block_row<L, MOB>(I, pv, sl, tm.lane, I.tau_s, I.m11_s,
+              [&](int j, double& mu, double& ps, double& om) { mu = Zj[j]; ps = Zj[n + j]; om = (double)x2[j]; },
+              w0, w1, w2);
+    if (i < n) {
+      vst(I.W + i, w0); vst(I.W + n + i, w1); vst(I.W + 2 * n + i, w2);
+      vst(Zj + 2 * n + i, (double)x2[i]);
+    }
+  }
+  // the sums, eight basis vectors at a time; a thread reads back only the rows of
+  // w it stored itself
+  const int j = S.j;
+  const double* Vj = I.V + (long long)j * n3;
+  const int lane = tm.lane, wave = tm.wave;
+  for (int b = 0; b * 8 <= j; ++b) {
+    double v16[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v16[q] = 0.0;
+    PFC_SLICES(I, tm) {
+      const int i = sl * 64 + lane;
+      if (i < n) {
+        double w[3], vj[3];
+#pragma unroll
+        for (int blk = 0; blk < 3; ++blk) { w[blk] = I.W[blk * n + i]; vj[blk] = gld(Vj + blk * n + i); }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int k = 8 * b + q;
+          if (k < j) {
+            const double* Vk = I.V + (long long)k * n3;
+            double c = 0.0, l = 0.0;
+#pragma unroll
+            for (int blk = 0; blk < 3; ++blk) {
+              const double vk = gld(Vk + blk * n + i);
+              c += w[blk] * vk;
+              l += vj[blk] * vk;
+            }
+            v16[q] += c;
+            v16[8 + q] += l;
+          } else if (k == j) {
+            v16[q] += w[0] * vj[0] + w[1] * vj[1] + w[2] * vj[2];
+            v16[8 + q] += w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+          }
+        }
+      }
+    }
+    const double tot = gs_wave_sums16(v16, lane);
+    const int idx = gs_wave_sums16_index(lane);
+    if ((lane & 3) == 0) pfc_gsred[wave * PFC_GS_NV + (idx < 8 ? 8 * b + idx : 32 + 8 * b + idx - 8)] = tot;
+  }
+  __syncthreads();
+  const int tid = threadIdx.x;
+  if (tid < PFC_GS_NV) {
+    const int k = tid & 31;
+    double t = 0.0;
+    if (k <= j) {
+#pragma unroll
+      for (int w = 0; w < PFC_WAVES; ++w) t += pfc_gsred[w * PFC_GS_NV + tid];
+    }
+    vst(gout + (long long)tm.rank * PFC_GS_NV + tid, t);
+  }
+}
+
+// Sum of the orthogonalisation's Gram partials of a team ([size][64], fixed
+// order) into g[0..63] (LDS): thread t sums value t mod 64 over the ranks
+// t / 64, t / 64 + 16, ...; the first 64 threads add the 16 group sums.  The
+// basis' stored Gram rows L (the Hist record) come to Ls[32 * 32] in the same
+// round trip.  Every thread of the workgroup calls this.
+static_assert(PFC_WG == PFC_MAXM * PFC_MAXM, "gs_gather loads the stored Gram rows one entry per thread");
+__device__ __forceinline__ void gs_gather(const double* part, int size, const double* Lg, double* g, double* Ls) {
+  const int tid = threadIdx.x, v = tid & 63, grp = tid >> 6;
+  const double lv = Lg[tid];  // PFC_WG = PFC_MAXM * PFC_MAXM entries, one per thread
+  double s = 0.0;
+  for (int k = grp; k < size; k += PFC_WAVES) s += part[(long long)k * PFC_GS_NV + v];
+  pfc_gsred[grp * PFC_GS_NV + v] = s;
+  Ls[tid] = lv;
+  __syncthreads();
+  if (tid < PFC_GS_NV) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < PFC_WAVES; ++w) t += pfc_gsred[w * PFC_GS_NV + tid];
+    g[tid] = t;
+  }
+  __syncthreads();
+}
+
+// w -= sum_{i <= j} h_i v_i in the order of modified Gram-Schmidt; partial (w, w)
+__device__ __forceinline__ Red3 ph_gs_update(const InstDev& I, const State& S, const Team& tm, const double* h) {
+  const int n = I.n;
+  const long long n3 = 3LL * n;
+  const int j = S.j;
+  double a0 = 0.0;
+  PFC_SLICES(I, tm) {
+    const int i = sl * 64 + tm.lane;
+    if (i < n) {
+#pragma unroll
+      for (int blk = 0; blk < 3; ++blk) {
+        const long long o = (long long)blk * n + i;
+        double w = I.W[o];
+        for (int k = 0; k <= j; ++k) w -= h[k] * I.V[(long long)k * n3 + o];
+        vst(I.W + o, w);
+        a0 += w * w;
+      }
+    }
+  }
+  return red3(a0, 0.0);
 }
 
 }  // namespace pfc

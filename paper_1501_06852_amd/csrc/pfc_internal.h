@@ -35,9 +35,8 @@ enum {
   PH_PCG_SETUP,   // right-hand side of inner solve `kind`, r = rhs, x = 0
   PH_PCG_A,       // p = D^{-1} r + beta p_old, q = C p, partial (p, q)
   PH_PCG_B,       // x += alpha p, r -= alpha q, partials (r, r), (r, D^{-1} r)
-  PH_ASPMV,       // w = A_s z_j, partials (w, v_0), (w, w)
-  PH_MGS,         // w -= h_{i-1} v_{i-1}, partial (w, v_i)
-  PH_MGS_LAST,    // w -= h_j v_j, partial (w, w)
+  PH_ASPMV,       // w = A_s z_j; Gram partials (w, v_i) i <= j, (v_j, v_k) k < j, (w, w)
+  PH_GS_UPDATE,   // w -= sum_i h_i v_i (modified Gram-Schmidt coefficients), partial (w, w)
   PH_UPDATE_X,    // x += Z y
   PH_TRUE_RES,    // r = b - A^R x, partials ||r||^2, ||r_s||^2; W = r_s
   PH_PCH_OUT,     // z_out = P_CH^{-1} v (preconditioner-only job)
@@ -123,10 +122,10 @@ struct State {
   int job;
   int step, stage;          // Rosenbrock position
   int kind, it, pcur, pad0; // inner PCG
-  int j, mgs_i, cycle, total, apply, kcols;
+  int j, cycle, total, apply, kcols;
   int status, cur;
   double rho, bb, alpha, beta_cg;
-  double vscale, bnorm, bnorm_s, est_thresh, w0, hprev, est, rel;
+  double vscale, bnorm, bnorm_s, est_thresh, w0, est, rel;
 };
 
 // Single-buffered FGMRES history of the current cycle.  Every entry is
@@ -138,6 +137,7 @@ struct Hist {
   double gpre[PFC_MAXM + 1];
   double gfin[PFC_MAXM];
   double R[PFC_MAXM][PFC_MAXM];   // R[l][c], l <= c
+  double L[PFC_MAXM][PFC_MAXM];   // L[i][k] = (v_i, v_k), k < i (the Arnoldi basis' strictly lower Gram)
   int inner_max[PFC_NSTEPS_P];
   int applies;
   long long inner_total;
@@ -189,6 +189,7 @@ struct InstDev {
   void *r_, *pA, *pB, *q, *y0, *y1, *zt, *x1, *x2;
   void *rB, *wB, *sA, *sB;      // extra buffers of the single-reduction PCG
   double* part;                 // [2][team_size][4] partial sums
+  double* gpart;                // [2][team_size][64] Gram partial sums of the orthogonalisation
   double* sbas;                 // s-step basis [2][5][n] (p, Tp, T^2 p, u, Tu), or null
   double* spart;                // s-step Gram partial sums [2][team_size][32], or null
   State* st;                    // [2]

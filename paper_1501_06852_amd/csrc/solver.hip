@@ -30,7 +30,7 @@ namespace pfc {
 __device__ __forceinline__ bool phase_partials(int ph) {
   switch (ph) {
     case PH_SOLVE_INIT: case PH_RB_RHS: case PH_PCG_SETUP: case PH_PCG_A: case PH_PCG_B:
-    case PH_ASPMV: case PH_MGS: case PH_MGS_LAST: case PH_TRUE_RES: case PH_CG_INIT: case PH_CG_ITER:
+    case PH_GS_UPDATE: case PH_TRUE_RES: case PH_CG_INIT: case PH_CG_ITER:
       return true;
     default:
       return false;
@@ -281,6 +281,24 @@ __device__ void scg_transition(State& S, const InstDev& I, bool wr, const double
   S.pcur = 0;
 }
 
+// After w = A_s z_j and its Gram sums g (slots as in ph_aspmv; Ls: the rows of
+// L stored by earlier steps of the cycle): h solves (I + L) h = c by forward
+// substitution, which is modified Gram-Schmidt's sequence of coefficients.
+__device__ void gs_coefficients(State& S, const InstDev& I, bool wr, const double* g, const double* Ls, double* h) {
+  const int j = S.j;
+  for (int i = 0; i <= j; ++i) {
+    double s = g[i];
+    for (int k = 0; k < i; ++k) s -= (i == j ? g[32 + k] : Ls[i * PFC_MAXM + k]) * h[k];
+    h[i] = s;
+  }
+  if (wr) {
+    for (int k = 0; k < j; ++k) I.hist->L[j][k] = g[32 + k];
+    for (int i = 0; i <= j; ++i) I.hist->hcol[i] = h[i];
+  }
+  S.w0 = sqrt(g[32 + j]);
+  S.phase = PH_GS_UPDATE;
+}
+
 __device__ void transition(State& S, const InstDev& I, bool wr, Red3 red, double* ybuf, double* col, bool ss) {
   switch (S.phase) {
     case PH_START:
@@ -351,20 +369,7 @@ __device__ void transition(State& S, const InstDev& I, bool wr, Red3 red, double
       if (done) pcg_done(S, I, wr);
       else { S.beta_cg = rzn / S.rho; S.rho = rzn; S.phase = PH_PCG_A; }
     } break;
-    case PH_ASPMV:
-      S.w0 = sqrt(red.b);
-      S.hprev = red.a;
-      if (wr) I.hist->hcol[0] = red.a;
-      if (S.j == 0) S.phase = PH_MGS_LAST;
-      else { S.mgs_i = 1; S.phase = PH_MGS; }
-      break;
-    case PH_MGS:
-      S.hprev = red.a;
-      if (wr) I.hist->hcol[S.mgs_i] = red.a;
-      if (S.mgs_i == S.j) S.phase = PH_MGS_LAST;
-      else { S.mgs_i += 1; S.phase = PH_MGS; }
-      break;
-    case PH_MGS_LAST:
+    case PH_GS_UPDATE:
       givens(S, I, wr, red.a, ybuf, col);
       break;
     case PH_UPDATE_X:
@@ -455,6 +460,9 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   __shared__ Red3 lds4[PFC_WAVES];
   __shared__ double ybuf[PFC_MAXM];
   __shared__ double gcol[PFC_MAXM + 1];
+  __shared__ double hbuf[PFC_MAXM];          // Gram-Schmidt coefficients of the current Arnoldi step
+  __shared__ double gs_g[PFC_GS_NV];         // Gram sums of the step (after PH_ASPMV)
+  __shared__ double gs_L[PFC_MAXM * PFC_MAXM];
   // two PCG iterations per launch: float64 launches that serve one instance on a periodic grid
   constexpr bool SS = SINGLE && COLS == PFC_COL_GRID && std::is_same<T, double>::value;
   __shared__ double ss_g[SS ? 32 : 1];
@@ -525,6 +533,9 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     if (writer && tid < NS) ((int*)st_out)[tid] = ((const int*)&S)[tid];
     return;
   }
+  // Gram partials of an orthogonalisation (the previous launch formed w = A_s z_j)
+  if (S.phase == PH_ASPMV)
+    gs_gather(I.gpart + (long long)parity * te.size * PFC_GS_NV, te.size, &I.hist->L[0][0], gs_g, gs_L);
   bool scg = false;
   SsPre ssp;
   if constexpr (SS) {
@@ -553,7 +564,8 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
 #pragma unroll
         for (int w = 0; w < PFC_WAVES; ++w) { red.a += lds4[w].a; red.b += lds4[w].b; red.c += lds4[w].c; }
       }
-      if (!cg_iter_continues(S, I, red)) transition(S, I, writer, red, ybuf, gcol, SS && I.sstep);
+      if (S.phase == PH_ASPMV) gs_coefficients(S, I, writer, gs_g, gs_L, hbuf);
+      else if (!cg_iter_continues(S, I, red)) transition(S, I, writer, red, ybuf, gcol, SS && I.sstep);
     }
   }
   if constexpr (SS) {
@@ -588,11 +600,12 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
       break;
     case PH_PCG_A: acc = pcg_phase<T, COLS, PH_PCG_A>(I, S, tm, sd); break;
     case PH_PCG_B: acc = pcg_phase<T, COLS, PH_PCG_B>(I, S, tm, sd); break;
-    case PH_ASPMV:
-      acc = I.model == PFC_MODEL_PFC1 ? ph_aspmv<T, COLS, true>(I, S, tm) : ph_aspmv<T, COLS, false>(I, S, tm);
-      break;
-    case PH_MGS: acc = ph_mgs(I, S, tm, false); break;
-    case PH_MGS_LAST: acc = ph_mgs(I, S, tm, true); break;
+    case PH_ASPMV: {
+      double* gout = I.gpart + (long long)(1 - parity) * te.size * PFC_GS_NV;
+      if (I.model == PFC_MODEL_PFC1) ph_aspmv<T, COLS, true>(I, S, tm, gout);
+      else ph_aspmv<T, COLS, false>(I, S, tm, gout);
+    } break;
+    case PH_GS_UPDATE: acc = ph_gs_update(I, S, tm, hbuf); break;
     case PH_UPDATE_X: acc = ph_update_x(I, S, tm, ybuf); break;
     case PH_TRUE_RES:
       acc = I.model == PFC_MODEL_PFC1 ? ph_true_res<COLS, true>(I, S, tm) : ph_true_res<COLS, false>(I, S, tm);
@@ -877,6 +890,7 @@ size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int t
   h.xbak = (double*)take(n3 * 8);
   h.errpart = (double*)take((size_t)m->n_slices * 2 * 8);
   h.part = (double*)take(2 * (size_t)team_size * 4 * sizeof(double));
+  h.gpart = (double*)take(2 * (size_t)team_size * PFC_GS_NV * sizeof(double));
   h.sH = sstep_halo(m, o, team_size);
   h.sstep = h.sH > 0;
   h.sbas = h.sstep ? (double*)take(10 * n * 8) : nullptr;
