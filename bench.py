@@ -292,12 +292,12 @@ def bench_served(args, torch, wl, pfc):
     def stream(rate):
         return wl.served_stream(nreq, rate, 4242)
 
-    # the autotuner's rows per thread for each class alone and with many requests resident (the servers
-    # below take each request's choice from this table by the number of active requests)
-    tune_counts = sorted({1, max(1, args.slots // 2)})
-    tuned = {f"{d}D {N} {'mixed' if prec else 'fp64'} x{c}": pfc.pfc_autotune(hm, prec, c)
-             for (d, N), (_, hm) in zip(classes, meshes) for prec in (1, 0) for c in tune_counts
-             if prec == 1 or c == 1}
+    # the autotuner's rows per thread for batches mixing the six classes, at a moderate and at the full
+    # load (the tuned servers below give each request the choice for the number of requests then active;
+    # below the smallest tuned count they use the load rule)
+    hmeshes = [hm for _, hm in meshes]
+    tuned = {f"{'mixed' if prec else 'fp64'} mix x{c}": pfc.pfc_autotune_mix(hmeshes, prec, c)
+             for prec in (1, 0) for c in sorted({8, args.slots})}
 
     def serve(prec, slots, rate, rpt, keep=(), use_tuned=1):
         so = pfc.pfc_server_opts(C.sizeof(pfc.pfc_server_opts), prec, 96 << 30, slots, 0, rpt, use_tuned)
@@ -343,7 +343,7 @@ def bench_served(args, torch, wl, pfc):
     for k, (_, c, _) in enumerate(stream(0.0)):
         if c not in sample and meshes[c][0].n <= 32768:
             sample[c] = k
-    base_bl, _ = serve(0, 1, 0.0, 0)
+    base_bl, _ = serve(0, 1, 0.0, 0)   # a single slot: every request alone (tuned table entries apply from 8)
     rate = 0.8 * nreq / base_bl["wall_s"]
     ours_bl, kept = serve(1, args.slots, 0.0, rpt, keep=set(sample.values()))
     base, _ = serve(0, 1, rate, 0)
@@ -366,7 +366,8 @@ def bench_served(args, torch, wl, pfc):
            "data": "synthetic",
            "config": {"workload": "served_stream", "requests": nreq, "rosenbrock_steps": steps,
                       "classes": [f"{d}D {N}" for d, N in classes], "arrival_rate_hz": rate, "slots": args.slots,
-                      "rows_per_thread": "autotuner table by class and load" if rpt == 0 else rpt,
+                      "rows_per_thread": "autotuner (mixed-batch table entry for the active count)" if rpt == 0
+                      else rpt,
                       "autotune": {k: {f: v[f] for f in ("rows_per_thread", "ms_per_step", "ms_default", "from_cache")}
                                    for k, v in tuned.items()}},
            "speedup_vs_plain_fp64_fifo": ours_bl["solves_per_s"] / base_bl["solves_per_s"],

@@ -442,7 +442,7 @@ int pfc_batch_run(pfc_instance* const* insts, int count, double* const* states,
  * for `count` instances takes the entry with the largest tuned count <= count.
  * pfc_batch_run takes its launches per graph from the table when the
  * instances' ticks_per_graph is 0, and a server created with `tuned` takes
- * each request's rows per thread from it.  The table is saved to and loaded
+ * each request's rows per thread from its mixed-batch entries.  The table is saved to and loaded
  * from a JSON file: {"format": "pfc-tune-1", "entries": [{...}, ...]}. */
 typedef struct pfc_tune_entry {
     int struct_size;
@@ -461,6 +461,13 @@ typedef struct pfc_tune_entry {
  * the default configuration does not fit 80% of the free device memory.
  * out: host record.  Synchronous on `stream`. */
 int pfc_autotune(pfc_mesh* mesh, int precision, int count, int force, pfc_tune_entry* out, void* stream);
+/* The same for batches that mix several meshes (the server's case): `count`
+ * instances dealt round robin over meshes[0..n_meshes-1], only rows per thread
+ * searched (the other knobs keep their defaults).  The entry's key has
+ * dim = n = z = 0 ("a mix"), whatever the meshes; tuning another mix replaces
+ * it. */
+int pfc_autotune_mix(pfc_mesh* const* meshes, int n_meshes, int precision, int count, int force, pfc_tune_entry* out,
+                     void* stream);
 /* Table entry for `count` instances of a mesh with these sizes (arch: NULL
  * for the current device's); PFC_ERR_STATE if the table has none.  Host only
  * when arch is given. */
@@ -491,9 +498,9 @@ void pfc_tune_clear(void);
  *               workgroups: more throughput when many requests share the GPU,
  *               longer solves when few do.
  *   tuned       1: with rows_per_thread 0, take each request's rows per thread
- *               from the autotuning table (the entry for the request's mesh
- *               and the number of active requests including it), and use the
- *               rule above only where the table has no entry; 0: the rule.
+ *               from the autotuning table's mixed-batch entry (pfc_autotune_mix)
+ *               for the number of active requests including it, and use the
+ *               rule above only where the table has no such entry; 0: the rule.
  *   n_steps ... Rosenbrock steps per request (set per request) */
 typedef struct pfc_server_opts {
     int struct_size;

@@ -83,16 +83,16 @@ pfc_opts server_instance_opts(const pfc_server* S, int rpt) {
 }
 
 // Rows per thread of a request's instance.  Fixed by the server options, or
-// (0) taken from the autotuning table for the request's mesh and the number of
-// active requests including it (option `tuned`, where the table has an entry),
-// or else chosen at admission from the load: one row per thread while the active
+// (0) taken from the autotuning table's entry for mixed batches of the number
+// of active requests including this one (option `tuned`, where the table has
+// such an entry), or else chosen at admission from the load: one row per thread while the active
 // requests and this one fit into one round of resident workgroups (the
 // shortest time per request), two once they do not (fewer, longer
 // workgroups: more throughput when the GPU is full).
 int choose_rpt(const pfc_server* S, const Request* q) {
   if (S->o.rows_per_thread > 0) return S->o.rows_per_thread;
   if (S->o.tuned) {
-    const int t = tuned_rows_per_thread(q->mesh, S->o.precision, (int)S->active.size() + 1);
+    const int t = tuned_mix_rows_per_thread(S->o.precision, (int)S->active.size() + 1);
     if (t > 0) return t;
   }
   long long rows = q->mesh->n;

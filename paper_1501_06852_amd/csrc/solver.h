@@ -33,10 +33,10 @@ int team_size_for(int n_slices, int rows_per_thread);
 void set_params(InstDev& h, double r, double tau, double m11);
 int set_mobility_mean(pfc_instance* I, const double* psi, hipStream_t s);
 int prep_ops_public(pfc_instance* I, hipStream_t s);
-// autotuning table (tune.hip): launches per graph and rows per thread for
-// `count` instances of a mesh, 0 where the table has no entry
+// autotuning table (tune.hip), 0 where it has no entry: launches per graph for
+// `count` instances of a mesh; rows per thread for `count` instances of a mix
 int tuned_ticks(const pfc_mesh* m, int precision, int count);
-int tuned_rows_per_thread(const pfc_mesh* m, int precision, int count);
+int tuned_mix_rows_per_thread(int precision, int count);
 
 }  // namespace pfc
 

@@ -10,8 +10,12 @@
 // defaults, one knob at a time) and keeps the fastest in a process-wide table
 // keyed by (device architecture, dim, n, entries per row, precision, count).
 // The table is read from and written to a JSON file.  pfc_batch_run takes its
-// launches per graph from the table, and a server created with `tuned` takes
-// each request's rows per thread from it.
+// launches per graph from the table.  pfc_autotune_mix tunes one rows-per-thread
+// value for batches that mix several meshes (key dim = n = z = 0): a server
+// created with `tuned` gives every request it admits the value for the number
+// of requests then active, since a launch lasts as long as its slowest
+// workgroup and per-mesh choices that differ would leave some workgroups far
+// longer than the rest.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -168,7 +172,8 @@ struct Candidate {
 // Milliseconds of one Rosenbrock step of `count` instances with candidate c
 // (best of two timed steps after a consistent initialisation and a warm-up
 // step), or a negative status.
-double time_candidate(pfc_mesh* m, int precision, int count, const Candidate& c, hipStream_t s, int* status) {
+double time_candidate(pfc_mesh* const* ms, int n_meshes, int precision, int count, const Candidate& c, hipStream_t s,
+                      int* status) {
   *status = PFC_OK;
   pfc_opts o;
   pfc_opts_default(&o);
@@ -181,20 +186,26 @@ double time_candidate(pfc_mesh* m, int precision, int count, const Candidate& c,
   o.max_run_steps = 4;
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) { *status = PFC_ERR_HIP; return -1; }
-  const size_t fp = pfc_instance_footprint(m, &o);
-  if (fp == 0) { *status = PFC_ERR_ARG; return -1; }
-  if ((double)fp * count > 0.8 * (double)free_b) { *status = PFC_ERR_OOM; return -1; }
+  double need = 0.0;
+  for (int k = 0; k < count; ++k) {
+    const size_t fp = pfc_instance_footprint(ms[k % n_meshes], &o);
+    if (fp == 0) { *status = PFC_ERR_ARG; return -1; }
+    need += (double)fp;
+  }
+  if (need > 0.8 * (double)free_b) { *status = PFC_ERR_OOM; return -1; }
   std::vector<pfc_instance*> insts(count, nullptr);
   std::vector<double*> states(count, nullptr);
   std::vector<double> r(count, -0.35), pb(count, -0.3), tau(count, 0.5);
-  const int n = m->n;
   int rc = PFC_OK;
   double best = 1e300;
-  std::vector<double> h((size_t)3 * n, 0.0);
+  std::vector<double> h;
   for (int k = 0; k < count && !rc; ++k) {
+    pfc_mesh* m = ms[k % n_meshes];
+    const int n = m->n;
     rc = pfc_instance_create(m, &o, &insts[k]);
     if (rc) break;
     if (hipMalloc((void**)&states[k], sizeof(double) * 3 * (size_t)n) != hipSuccess) { rc = PFC_ERR_OOM; break; }
+    h.assign((size_t)3 * n, 0.0);
     for (int i = 0; i < n; ++i) h[(size_t)n + i] = -0.3 + 0.01 * (2.0 * splitmix_u01((uint64_t)k * n + i) - 1.0);
     if (hipMemcpy(states[k], h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice) != hipSuccess) rc = PFC_ERR_HIP;
   }
@@ -217,6 +228,66 @@ double time_candidate(pfc_mesh* m, int precision, int count, const Candidate& c,
   return best;
 }
 
+// Coordinate descent from the defaults over the launch knobs for `count`
+// instances on the meshes ms (round robin); the result, key fields from e, goes
+// into the table and to out.
+int tune_search(pfc_mesh* const* ms, int n_meshes, int precision, int count, hipStream_t s, pfc_tune_entry e,
+                pfc_tune_entry* out) {
+  bool grid = true;
+  for (int k = 0; k < n_meshes; ++k) grid = grid && ms[k]->dev.gN > 0 && ms[k]->uniform_width >= 1;
+  const bool mix = n_meshes > 1;
+  // defaults: one row per thread, 64 launches per graph, two PCG iterations per
+  // launch where they apply, computed columns on grids, stored operators
+  Candidate best{1, 64, 2, 1, 0};
+  std::vector<std::pair<Candidate, double>> seen;
+  int status = PFC_OK;
+  auto measure = [&](const Candidate& c) -> double {
+    for (const auto& x : seen)
+      if (x.first == c) return x.second;
+    int st = PFC_OK;
+    const double t = time_candidate(ms, n_meshes, precision, count, c, s, &st);
+    if (st == PFC_ERR_OOM) { seen.push_back({c, 1e300}); return 1e300; }  // does not fit: never chosen
+    if (st < 0) { status = st; return 1e300; }
+    seen.push_back({c, t});
+    return t;
+  };
+  double tbest = measure(best);
+  if (status) return status;
+  if (tbest >= 1e299) { set_error("pfc_autotune: the instances do not fit the free device memory"); return PFC_ERR_OOM; }
+  e.ms_default = tbest;
+  auto axis = [&](auto set, const std::vector<int>& values) {
+    for (int v : values) {
+      Candidate c = best;
+      set(c, v);
+      const double t = measure(c);
+      if (status) return;
+      if (t < tbest) { tbest = t; best = c; }
+    }
+  };
+  axis([](Candidate& c, int v) { c.rpt = v; }, {1, 2, 4, 8});
+  if (!mix) {  // a mix is tuned for the server, whose instances keep the other defaults
+    if (!status && grid) axis([](Candidate& c, int v) { c.grid = v; }, {1, 0});
+    if (!status && count > 1) axis([](Candidate& c, int v) { c.shared = v; }, {0, 1});
+    if (!status && count == 1) axis([](Candidate& c, int v) { c.pcg = v; }, {2, 1});
+    if (!status) axis([](Candidate& c, int v) { c.ticks = v; }, {32, 64, 128});
+  }
+  if (status) return status;
+  e.rows_per_thread = best.rpt;
+  e.ticks_per_graph = best.ticks;
+  e.pcg_steps_per_launch = best.pcg;
+  e.grid_columns = best.grid;
+  e.shared_ops = best.shared;
+  e.ms_per_step = tbest;
+  e.candidates = (int)seen.size();
+  e.from_cache = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    put_entry(e);
+  }
+  *out = e;
+  return PFC_OK;
+}
+
 }  // namespace
 
 // launches per graph the table holds for a batch of these instances (0: none)
@@ -228,12 +299,13 @@ int tuned_ticks(const pfc_mesh* m, int precision, int count) {
   return e ? e->ticks_per_graph : 0;
 }
 
-// rows per thread the table holds for `count` instances of this mesh (0: none)
-int tuned_rows_per_thread(const pfc_mesh* m, int precision, int count) {
+// rows per thread the table holds for `count` instances of a mix of meshes, as
+// tuned by pfc_autotune_mix (0: none)
+int tuned_mix_rows_per_thread(int precision, int count) {
   char arch[32];
   if (current_arch(arch, sizeof(arch))) { (void)hipGetLastError(); return 0; }
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  const pfc_tune_entry* e = find_entry(arch, m->dim, m->n, mesh_z(m), precision, count);
+  const pfc_tune_entry* e = find_entry(arch, 0, 0, 0, precision, count);
   return e ? e->rows_per_thread : 0;
 }
 
@@ -315,56 +387,32 @@ int pfc_autotune(pfc_mesh* m, int precision, int count, int force, pfc_tune_entr
         return PFC_OK;
       }
   }
-  hipStream_t s = (hipStream_t)stream;
-  const bool grid = m->dev.gN > 0 && m->uniform_width >= 1;
-  // defaults: one row per thread, 64 launches per graph, two PCG iterations per
-  // launch where they apply, computed columns on grids, stored operators
-  Candidate best{1, 64, 2, 1, 0};
-  std::vector<std::pair<Candidate, double>> seen;
-  int status = PFC_OK;
-  auto measure = [&](const Candidate& c) -> double {
-    for (const auto& x : seen)
-      if (x.first == c) return x.second;
-    int st = PFC_OK;
-    const double ms = time_candidate(m, precision, count, c, s, &st);
-    if (st == PFC_ERR_OOM) { seen.push_back({c, 1e300}); return 1e300; }  // does not fit: never chosen
-    if (st < 0) { status = st; return 1e300; }
-    seen.push_back({c, ms});
-    return ms;
-  };
-  double tbest = measure(best);
-  if (status) return status;
-  if (tbest >= 1e299) { set_error("pfc_autotune: the instances do not fit the free device memory"); return PFC_ERR_OOM; }
-  e.ms_default = tbest;
-  auto axis = [&](auto set, const std::vector<int>& values) {
-    for (int v : values) {
-      Candidate c = best;
-      set(c, v);
-      const double t = measure(c);
-      if (status) return;
-      if (t < tbest) { tbest = t; best = c; }
-    }
-  };
-  axis([](Candidate& c, int v) { c.rpt = v; }, {1, 2, 4, 8});
-  if (!status && grid) axis([](Candidate& c, int v) { c.grid = v; }, {1, 0});
-  if (!status && count > 1) axis([](Candidate& c, int v) { c.shared = v; }, {0, 1});
-  if (!status && count == 1) axis([](Candidate& c, int v) { c.pcg = v; }, {2, 1});
-  if (!status) axis([](Candidate& c, int v) { c.ticks = v; }, {32, 64, 128});
-  if (status) return status;
-  e.rows_per_thread = best.rpt;
-  e.ticks_per_graph = best.ticks;
-  e.pcg_steps_per_launch = best.pcg;
-  e.grid_columns = best.grid;
-  e.shared_ops = best.shared;
-  e.ms_per_step = tbest;
-  e.candidates = (int)seen.size();
-  e.from_cache = 0;
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    put_entry(e);
+  return tune_search(&m, 1, precision, count, (hipStream_t)stream, e, out);
+}
+
+int pfc_autotune_mix(pfc_mesh* const* meshes, int n_meshes, int precision, int count, int force, pfc_tune_entry* out,
+                     void* stream) {
+  if (!meshes || n_meshes < 1 || !out || count < 1 || (precision != PFC_FP64 && precision != PFC_MIXED)) {
+    set_error("pfc_autotune_mix: invalid arguments");
+    return PFC_ERR_ARG;
   }
-  *out = e;
-  return PFC_OK;
+  for (int k = 0; k < n_meshes; ++k)
+    if (!meshes[k]) { set_error("pfc_autotune_mix: null mesh"); return PFC_ERR_ARG; }
+  pfc_tune_entry e;
+  std::memset(&e, 0, sizeof(e));
+  e.struct_size = (int)sizeof(pfc_tune_entry);
+  if (int rc = current_arch(e.arch, sizeof(e.arch))) return rc;
+  e.dim = 0; e.n = 0; e.z = 0; e.precision = precision; e.count = count;  // the mix key
+  if (!force) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const pfc_tune_entry& x : g_table)
+      if (same_key(x, e.arch, 0, 0, 0, precision) && x.count == count) {
+        *out = x;
+        out->from_cache = 1;
+        return PFC_OK;
+      }
+  }
+  return tune_search(meshes, n_meshes, precision, count, (hipStream_t)stream, e, out);
 }
 
 }  // extern "C"

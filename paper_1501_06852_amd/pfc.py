@@ -150,6 +150,7 @@ _sig("pfc_stage_rhs", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.c_double, 
 _sig("pfc_batch_run", C.c_int, [C.POINTER(_vp), C.c_int, C.POINTER(_vp), _dp, _dp, _dp, C.c_int, C.c_int,
                                 C.POINTER(pfc_solve_info), _vp])
 _sig("pfc_autotune", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.POINTER(pfc_tune_entry), _vp])
+_sig("pfc_autotune_mix", C.c_int, [C.POINTER(_vp), C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(pfc_tune_entry), _vp])
 _sig("pfc_tune_lookup", C.c_int, [C.c_char_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(pfc_tune_entry)])
 _sig("pfc_tune_load", C.c_int, [C.c_char_p])
 _sig("pfc_tune_save", C.c_int, [C.c_char_p])
@@ -170,7 +171,7 @@ DECLARED = [
     "pfc_solve", "pfc_solve_x", "pfc_last_inner_counts", "pfc_instance_launch_stats", "pfc_instance_config",
     "pfc_rosenbrock_run",
     "pfc_rosenbrock_adaptive", "pfc_apply_AR", "pfc_apply_AR_x", "pfc_apply_AR_noalloc", "pfc_apply_pch", "pfc_stage_rhs",
-    "pfc_batch_run", "pfc_autotune", "pfc_tune_lookup", "pfc_tune_load", "pfc_tune_save", "pfc_tune_clear",
+    "pfc_batch_run", "pfc_autotune", "pfc_autotune_mix", "pfc_tune_lookup", "pfc_tune_load", "pfc_tune_save", "pfc_tune_clear",
     "pfc_server_create", "pfc_server_submit", "pfc_server_poll", "pfc_result_free",
     "pfc_server_drain", "pfc_server_clock", "pfc_server_destroy",
 ]
@@ -390,6 +391,16 @@ def pfc_autotune(mesh, precision, count, force=False, stream=None):
     e = pfc_tune_entry()
     e.struct_size = C.sizeof(pfc_tune_entry)
     _check(_lib.pfc_autotune(mesh, precision, count, 1 if force else 0, C.byref(e), _stream(stream)), "pfc_autotune")
+    return e.as_dict()
+
+
+def pfc_autotune_mix(meshes, precision, count, force=False, stream=None):
+    """Tune the rows per thread of batches mixing the given meshes (the server's table entry); returns a dict."""
+    e = pfc_tune_entry()
+    e.struct_size = C.sizeof(pfc_tune_entry)
+    arr = (_vp * len(meshes))(*[m.value if isinstance(m, _vp) else m for m in meshes])
+    _check(_lib.pfc_autotune_mix(arr, len(meshes), precision, count, 1 if force else 0, C.byref(e), _stream(stream)),
+           "pfc_autotune_mix")
     return e.as_dict()
 
 
