@@ -455,17 +455,30 @@ def bench_adaptive(args, torch, wl, pfc, roofline):
 
 
 def bench_copy_calibration(torch):
-    """Plain device copy of 1 GiB (float64), three times: the reference kernel whose
-    FETCH_SIZE / WRITE_SIZE counter readings calibrate the solver kernel's."""
-    n = 1 << 27
-    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
-    y = torch.empty_like(x)
-    torch.cuda.synchronize()
-    for _ in range(3):
-        y.copy_(x)
-    torch.cuda.synchronize()
-    print(json.dumps({"workload": "copy_calibration", "bytes_read_per_copy": 8 * n, "bytes_written_per_copy": 8 * n,
-                      "copies": 3}), flush=True)
+    """Plain device copies (torch's copy kernel, float64): a 1 GiB copy three times, the reference
+    kernel whose FETCH_SIZE / WRITE_SIZE counter readings calibrate the solver kernel's, and the
+    streaming rates of the two ceilings the roofline discussion uses: arrays far larger than the
+    256 MB MALL (1 GiB, read + write), and a 32 MiB working set that stays MALL-resident (copied
+    over and over).  Rates count the bytes read plus the bytes written."""
+    out = {"workload": "copy_calibration"}
+    for label, nbytes, reps in (("hbm_1GiB", 1 << 30, 20), ("mall_32MiB", 32 << 20, 400)):
+        n = nbytes // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[label] = {"bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes, "copies": reps,
+                      "us_per_copy": ms * 1e3, "GBps": 2 * nbytes / (ms * 1e-3) / 1e9}
+        del x, y
+    print(json.dumps(out), flush=True)
 
 
 def main():

@@ -136,10 +136,13 @@ typedef struct pfc_server pfc_server;
  *                 reduction of their D-weighted Gram matrix, halo rows staged
  *                 in LDS): same iterates and the same stopping decisions as the
  *                 standard iteration in exact arithmetic, and the same count
- *                 of iterations.  It applies to float64 instances with
- *                 single_reduction = 1 on 2D periodic grid meshes with
- *                 grid_columns = 1 and rows_per_thread <= 1, in launches that
- *                 serve the instance alone; elsewhere, and with 1, one
+ *                 of iterations.  It applies in launches that serve the
+ *                 instance alone, to single_reduction = 1 instances with
+ *                 grid_columns = 1 and rows_per_thread <= 1 that are either
+ *                 float64 on a 2D periodic grid mesh (a workgroup's rows are
+ *                 a range of rows) or PFC_MIXED on a 3D periodic grid mesh of
+ *                 side 64 (a workgroup's rows are a block of 4 x 4 grid lines,
+ *                 the inner iterations in float32); elsewhere, and with 1, one
  *                 iteration per launch.  Results then differ from a launch
  *                 that serves the instance together with others by rounding
  *                 (1 gives the same bits alone and in a batch). */

@@ -1296,6 +1296,253 @@ __device__ __forceinline__ void ss_gram(const double* part, int size, const doub
 }
 
 
+// ---- two Jacobi-PCG iterations per launch on 3D periodic grids of side 64 -------
+// The s-step iteration of ph_scg with a workgroup's rows a block of the grid
+// instead of a range of rows: whole x-lines (64 rows, one SELL slice each) at
+// y0..y0+3, z0..z0+3, 1024 rows; rank r has y0 = 4 (r mod 16), z0 = 4 (r / 16).
+// The two-step frame is the 8 x 8 lines y0-2..y0+5, z0-2..z0+5, the one-step
+// frame the 6 x 6 lines y0-1..y0+4, z0-1..z0+4 (periodic in every direction),
+// so a row's neighbour in a frame follows from the entry's direction
+// (MeshDev::gdir).  Frame positions: q = x + 64 (ly + 8 lz) in the two-step
+// frame (4 passes of the workgroup), q1 = x + 64 (ly1 + 6 lz1) in the one-step
+// frame (3 passes, the third partial).  New p and u are formed on the frames,
+// T p on the one-step frame, and a last pass gives thread t the own row
+// x = t mod 64, y0 + (t / 64) mod 4, z0 + t / 256 for T u, T^2 p, the stores and
+// the Gram products.  T is the inner precision (float in PFC_MIXED); the Gram
+// sums and the coefficients stay float64.
+#define PFC_S3_N 64
+__device__ __forceinline__ int s3_wrap(int v) { return v & (PFC_S3_N - 1); }
+struct S3Geo {
+  int y0, z0;
+};
+__device__ __forceinline__ S3Geo s3_geo(int rank) { return S3Geo{(rank & 15) * 4, (rank >> 4) * 4}; }
+__device__ __forceinline__ int s3_row(const S3Geo& G, int x, int yl, int zl) {
+  return x + PFC_S3_N * (s3_wrap(G.y0 + yl) + PFC_S3_N * s3_wrap(G.z0 + zl));
+}
+// row class (grid_class) of the row at block coordinates (x, yl, zl)
+__device__ __forceinline__ int s3_class(const S3Geo& G, int x, int yl, int zl) {
+  return grid_edge(x, PFC_S3_N) + 3 * grid_edge(s3_wrap(G.y0 + yl), PFC_S3_N) + 9 * grid_edge(s3_wrap(G.z0 + zl), PFC_S3_N);
+}
+// offset of an entry's neighbour within a frame of f lines per direction:
+// (x + dx) mod 64 - x is applied separately
+__device__ __forceinline__ int s3_dline(int code, int f) { return PFC_S3_N * ((code / 3) % 3 - 1 + f * (code / 9 - 1)); }
+__device__ __forceinline__ int s3_nx(int x, int code) { return s3_wrap(x + code % 3 - 1); }
+
+template <typename T>
+struct S3Pre {
+  T bv[PFC_SS_NA][5];
+};
+// the current basis on the two-step frame, issued before the reductions
+template <typename T>
+__device__ __forceinline__ void s3_load(const InstDev& I, const State& S, int rank, S3Pre<T>& P) {
+  const long long nn = I.n;
+  const int tid = threadIdx.x;
+  const S3Geo G = s3_geo(rank);
+  const T* bin = (const T*)I.sbas + (long long)S.cur * 5 * nn;
+#pragma unroll
+  for (int c = 0; c < PFC_SS_NA; ++c) {
+    const int q = tid + c * PFC_WG;
+    const int g = s3_row(G, q & 63, ((q >> 6) & 7) - 2, (q >> 9) - 2);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) P.bv[c][k] = gld(bin + k * nn + g);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void ph_scg3(const InstDev& I, const State& S, const Team& tm, const double* coef, bool init,
+                                        double* spart_out, S3Pre<T>& P) {
+  constexpr int W15 = 15;
+  const int n = I.n, tid = threadIdx.x;
+  const long long nn = n;
+  const S3Geo G = s3_geo(tm.rank);
+  PcgOps<T> o = pcg_ops<T>(I, S.kind);
+  const PatView<PFC_COL_GRID> pv = op_pat<PFC_COL_GRID>(I, o, tm);
+  T* bout = (T*)I.sbas + (long long)S.cur * 5 * nn;
+  const T* bold = (const T*)I.sbas + (long long)(S.cur ^ 1) * 5 * nn;
+  const unsigned char* gdir = I.m.gdir;
+  T* sp = (T*)pfc_ss;          // new p on the two-step frame [4096]
+  T* su = sp + 4096;           // new u on the one-step frame [2304]
+  T* stp = su + 2304;          // T p on the one-step frame [2304]
+  T* sb = stp + 2304;          // right-hand side on the two-step frame (first launch of a solve) [4096]
+  static_assert(12800 * sizeof(T) <= sizeof(pfc_ss), "the frames of ph_scg3 exceed the s-step LDS");
+  // own row of this thread
+  const int ox = tid & 63, oyl = (tid >> 6) & 3, ozl = tid >> 8;
+  const int og = s3_row(G, ox, oyl, ozl);
+  if (init) {
+    // the solve's right-hand side b on the two-step frame and u_0 = p_0 = D^{-1} b;
+    // as ph_scg: b = t - s (A v) by solve kind
+    const long long n3 = 3 * nn;
+    const double* Vj = I.V + (long long)S.j * n3;
+    const int kind = S.kind;
+    const T* A = (kind == KIND_Y1 || kind == KIND_X2) ? o.Kv : (kind == KIND_Y0 ? nullptr : o.Mv);
+    const T* v = kind == KIND_Y1 ? (const T*)I.y0 : kind == KIND_Z ? (const T*)I.y1 : kind == KIND_X1 ? (const T*)I.zt
+                                                                                                      : (const T*)I.x1;
+    const double* t = kind == KIND_Y0 ? I.W : (kind == KIND_Y1 ? Vj + nn : (kind == KIND_X2 ? Vj + 2 * nn : nullptr));
+    const double ts = kind == KIND_Y0 ? S.vscale : 1.0, sa = kind == KIND_Y1 ? I.tau_p : 1.0;
+#pragma unroll
+    for (int c = 0; c < PFC_SS_NA; ++c) {
+      const int q = tid + c * PFC_WG;
+      const int g = s3_row(G, q & 63, ((q >> 6) & 7) - 2, (q >> 9) - 2);
+      const int base = (g >> 6) * 64 * W15 + (g & 63);
+      T d = T(0);
+      if (A) {
+#pragma unroll 5
+        for (int k = 0; k < W15; ++k) {
+          const long long e = (long long)base + k * 64;
+          d += gld(A + e) * gld(v + pv.at(e, g));
+        }
+      }
+      const double tt = t ? gld(t + g) * ts : 0.0;
+      const double b = !A ? tt : (t ? tt - sa * (double)d : (double)d);
+      P.bv[c][0] = gld(o.dinv + g);
+      P.bv[c][1] = T(b);
+      sb[q] = T(b);
+    }
+  } else if (S.pcur) {  // the solve ends within these two iterations: x only, on the own row
+    const T xo = gld(o.x + og);
+    const double p = gld(bold + og), tp = gld(bold + nn + og), u = gld(bold + 3 * nn + og);
+    vst(o.x + og, T((double)xo + (coef[0] * p + coef[1] * tp + coef[3] * u)));
+    return;
+  }
+  // new p on the two-step frame, new u on the one-step frame
+#pragma unroll
+  for (int c = 0; c < PFC_SS_NA; ++c) {
+    const int q = tid + c * PFC_WG;
+    const T* b = P.bv[c];
+    T pn, un;
+    if (init) {
+      pn = b[0] * b[1];
+      un = pn;
+    } else {
+      pn = T(coef[5] * b[0] + coef[6] * b[1] + coef[7] * b[2] + coef[8] * b[3] + coef[9] * b[4]);
+      un = T(coef[10] * b[0] + coef[11] * b[1] + coef[12] * b[2] + coef[13] * b[3] + coef[14] * b[4]);
+    }
+    sp[q] = pn;
+    const int ly = (q >> 6) & 7, lz = q >> 9;
+    if (ly >= 1 && ly < 7 && lz >= 1 && lz < 7) su[(q & 63) + 64 * ((ly - 1) + 6 * (lz - 1))] = un;
+  }
+  // operator rows of the one-step frame, in flight across the barrier
+  T av[2][W15], dv[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int q1 = tid + c * PFC_WG, t1 = q1 >> 6;
+    const int g = s3_row(G, q1 & 63, t1 % 6 - 1, t1 / 6 - 1);
+    const int base = (g >> 6) * 64 * W15 + (g & 63);
+#pragma unroll
+    for (int k = 0; k < W15; ++k) av[c][k] = opval_g(o, (long long)base + k * 64);
+    dv[c] = gld(o.dinv + g);
+  }
+  lds_barrier();
+  // T p on the one-step frame
+  auto tprow = [&](int q1, const T* a, T di) {
+    const int x = q1 & 63, t1 = q1 >> 6, yl = t1 % 6 - 1, zl = t1 / 6 - 1;
+    const unsigned char* gd = gdir + s3_class(G, x, yl, zl) * PFC_GRID_W;
+    const int rb = PFC_S3_N * ((yl + 2) + 8 * (zl + 2));
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < W15; ++k) {
+      const int code = gd[k];
+      acc += a[k] * sp[s3_nx(x, code) + rb + s3_dline(code, 8)];
+    }
+    stp[q1] = di * acc;
+  };
+#pragma unroll
+  for (int c = 0; c < 2; ++c) tprow(tid + c * PFC_WG, av[c], dv[c]);
+  if (tid + 2 * PFC_WG < 2304) {  // the third pass: 256 rows
+    const int q1 = tid + 2 * PFC_WG, t1 = q1 >> 6;
+    const int g = s3_row(G, q1 & 63, t1 % 6 - 1, t1 / 6 - 1);
+    const int base = (g >> 6) * 64 * W15 + (g & 63);
+    T a3[W15];
+#pragma unroll
+    for (int k = 0; k < W15; ++k) a3[k] = opval_g(o, (long long)base + k * 64);
+    tprow(q1, a3, gld(o.dinv + g));
+  }
+  // the own row's operator row (a cache hit: the frame passes read it)
+  T ao[W15];
+  const int obase = (og >> 6) * 64 * W15 + (og & 63);
+#pragma unroll
+  for (int k = 0; k < W15; ++k) ao[k] = opval_g(o, (long long)obase + k * 64);
+  const T odi = gld(o.dinv + og);
+  lds_barrier();
+  // own row: T u, T^2 p, the stores and the Gram products
+  const unsigned char* gd = gdir + s3_class(G, ox, oyl, ozl) * PFC_GRID_W;
+  const int rb1 = PFC_S3_N * ((oyl + 1) + 6 * (ozl + 1));
+  T au = T(0), att = T(0), dg = T(0);
+#pragma unroll
+  for (int k = 0; k < W15; ++k) {
+    const int code = gd[k];
+    const int i1 = s3_nx(ox, code) + rb1 + s3_dline(code, 6);
+    au += ao[k] * su[i1];
+    att += ao[k] * stp[i1];
+    dg += code == 13 ? ao[k] : T(0);
+  }
+  const int o2 = ox + PFC_S3_N * ((oyl + 2) + 8 * (ozl + 2)), o1 = ox + rb1;
+  const T pn = sp[o2], un = su[o1], tpo = stp[o1], tuo = odi * au, ttp = odi * att;
+  double bbo = 0.0;
+  if (init) {
+    const double bo = (double)sb[o2];
+    bbo = bo * bo;
+    vst(o.x + og, T(0));
+    const long long n3 = 3 * nn;
+    if (S.kind == KIND_Y0) {  // the Arnoldi vector v_j = w / ||w||
+      double* Vw = I.V + (long long)S.j * n3;
+      vst(Vw + og, gld(I.W + og) * S.vscale);
+      vst(Vw + nn + og, gld(I.W + nn + og) * S.vscale);
+      vst(Vw + 2 * nn + og, gld(I.W + 2 * nn + og) * S.vscale);
+    } else if (S.kind == KIND_X2) {  // (4): z_j = (y0 + (y1 - x1) / delta, x1, x2)
+      double* Zj = I.Z + (long long)S.j * n3;
+      const double y0i = (double)gld((const T*)I.y0 + og), y1i = (double)gld((const T*)I.y1 + og);
+      const double x1i = (double)gld((const T*)I.x1 + og);
+      vst(Zj + og, y0i + (y1i - x1i) / I.delta);
+      vst(Zj + nn + og, x1i);
+    }
+  } else {
+    const T xo = gld(o.x + og);
+    const double p = gld(bold + og), tp = gld(bold + nn + og), u = gld(bold + 3 * nn + og);
+    vst(o.x + og, T((double)xo + (coef[0] * p + coef[1] * tp + coef[3] * u)));
+  }
+  vst(bout + og, pn);
+  vst(bout + nn + og, tpo);
+  vst(bout + 2 * nn + og, ttp);
+  vst(bout + 3 * nn + og, un);
+  vst(bout + 4 * nn + og, tuo);
+  double gp[PFC_SS_NG];
+  {
+    const double dgo = (double)dg;
+    const double v[5] = {(double)pn, (double)tpo, (double)ttp, (double)un, (double)tuo};
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      const double di = dgo * v[i];
+#pragma unroll
+      for (int j = i; j < 5; ++j) gp[ss_tri(i, j, 5)] = di * v[j];
+    }
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+      const double di = dgo * dgo * v[i];
+#pragma unroll
+      for (int j = i; j < 5; ++j) gp[15 + ss_tri(i - 1, j - 1, 4)] = di * v[j];
+    }
+  }
+  gp[25] = bbo;
+  // workgroup sums as ph_scg: each wave by recursive halving, then over the waves
+  const int lane = tid & 63, wave = tid >> 6;
+  {
+    double v32[32];
+#pragma unroll
+    for (int m = 0; m < 32; ++m) v32[m] = m < PFC_SS_NG ? gp[m] : 0.0;
+    const double tot = ss_wave_sums32(v32, lane);
+    const int idx = ss_wave_sums32_index(lane);
+    if ((lane & 1) == 0) pfc_ssred[wave * 32 + idx] = tot;
+  }
+  lds_barrier();
+  if (tid < PFC_SS_NG) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < PFC_WAVES; ++w) t += pfc_ssred[w * 32 + tid];
+    vst(spart_out + (long long)tm.rank * 32 + tid, t);
+  }
+}
+
 // ---- orthogonalisation of an Arnoldi step (one reduction) ----------------------
 // Modified Gram-Schmidt against v_0..v_j computes h_i = (w - sum_{k<i} h_k v_k,
 // v_i) one after the other, which needs j + 1 reductions.  Expanding the inner

@@ -256,6 +256,41 @@ static int slot_of(const pfc_mesh* m, int row, int col) {
 // (grid_class) have the same column offsets j - i.  The offsets of a class are
 // read off its first row; every row, that one included, is then checked entry
 // by entry against grid_col.
+// Direction of every entry of a grid mesh's rows (for sweeps over blocks of the
+// grid): per row class and entry, the step (dx, dy, dz) from the row to the
+// column with each component in -1..1 (periodic), read off the class's first
+// row and checked on every row.  False if some entry is farther than one step.
+static bool detect_grid_dirs(const pfc_mesh* m, int w, int N, std::vector<unsigned char>& gdir) {
+  const int n = m->n, dim = m->dim;
+  const float inv = 1.0f / (float)N;
+  gdir.assign((size_t)PFC_GRID_CLASSES * PFC_GRID_W, 13);  // 13: no step
+  std::vector<char> have(PFC_GRID_CLASSES, 0);
+  auto coord = [&](int v, int c) { return c == 0 ? v % N : (c == 1 ? (v / N) % N : v / (N * N)); };
+  auto step = [&](int a, int b) {  // b - a on the circle of N, or 9 when farther than one step
+    int d = b - a;
+    if (d > N / 2) d -= N;
+    if (d < -(N / 2)) d += N;
+    return (d >= -1 && d <= 1) ? d : 9;
+  };
+  for (int i = 0; i < n; ++i) {
+    const int cls = grid_class(i, N, inv);
+    const int* col = m->col_idx.data() + m->row_ptr[i];
+    for (int k = 0; k < w; ++k) {
+      int code = 0, mul = 1;
+      for (int c = 0; c < 3; ++c, mul *= 3) {
+        const int d = c < dim ? step(coord(i, c), coord(col[k], c)) : 0;
+        if (d == 9) return false;
+        code += (d + 1) * mul;
+      }
+      unsigned char& g = gdir[(size_t)cls * PFC_GRID_W + k];
+      if (!have[cls]) g = (unsigned char)code;
+      else if (g != code) return false;
+    }
+    have[cls] = 1;
+  }
+  return true;
+}
+
 static bool detect_grid(const pfc_mesh* m, int w, int& gN, std::vector<int>& glin) {
   const int n = m->n, dim = m->dim;
   const int N = (int)std::llround(std::pow((double)n, 1.0 / dim));
@@ -384,6 +419,10 @@ static int finish_layout(pfc_mesh* m, const int32_t* en, const std::vector<int>&
   d.gInv = gN ? 1.0f / (float)gN : 0.0f;
   std::memset(d.glin, 0, sizeof(d.glin));
   if (gN) std::memcpy(d.glin, glin.data(), sizeof(d.glin));
+  std::vector<unsigned char> gdir;
+  d.gdir_ok = gN && detect_grid_dirs(m, m->uniform_width, gN, gdir) ? 1 : 0;
+  std::memset(d.gdir, 13, sizeof(d.gdir));
+  if (d.gdir_ok) std::memcpy(d.gdir, gdir.data(), sizeof(d.gdir));
   d.nd_el_ptr = m->d_nd_el_ptr; d.nd_el = m->d_nd_el; d.elem_nodes = m->d_elem_nodes; d.elem_vol = m->d_vol;
   return PFC_OK;
 }

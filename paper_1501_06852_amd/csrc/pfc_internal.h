@@ -88,6 +88,10 @@ struct MeshDev {
   int gN;                 // periodic grid side N (grid_col), or 0
   float gInv;             // float(1 / N)
   int glin[PFC_GRID_CLASSES * PFC_GRID_W];  // column offset of each entry per row class (grid_col)
+  // direction of each entry per row class: (dx + 1) + 3 (dy + 1) + 9 (dz + 1), the
+  // column's grid step from its row (periodic, each component in -1..1); valid if gdir_ok
+  unsigned char gdir[PFC_GRID_CLASSES * PFC_GRID_W];
+  int gdir_ok;
   const double* p2_M2;    // P2 reference tables (divided by |T|): M2[a][b],
   const double* p2_D;     //   D[i][j][a][b] = int d_i phi_a d_j phi_b (i, j barycentric),
   const double* p2_C4;    //   C4[a][b][c][d] = int phi_a phi_b phi_c phi_d
@@ -159,7 +163,8 @@ struct InstDev {
   int sd_iters, model;          // model: PFC_MODEL_PFC2 / PFC_MODEL_PFC1
   int grid_cols, gamma_mode;    // grid_columns and gamma_mode options
   int inner_fixed[5], pad_if;   // fixed inner iteration counts (0: to inner_tol)
-  int sstep, sH;                // two PCG iterations per launch allowed; halo rows (N + 1)
+  int sstep, sH;                // two PCG iterations per launch: 0 no, 1 row ranges of a 2D grid (halo sH = N + 1
+                                // rows), 2 blocks of a 3D grid of side 64
   double outer_tol, inner_tol, ci_tol;
   // job parameters; tau_p = m0 tau_s is the preconditioner's time step
   // rs: factor of block row 1 in the system FGMRES works on (1/m11 for

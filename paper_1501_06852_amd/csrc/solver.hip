@@ -465,8 +465,11 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   __shared__ double gs_L[PFC_MAXM * PFC_MAXM];
   // two PCG iterations per launch: float64 launches that serve one instance on a periodic grid
   constexpr bool SS = SINGLE && COLS == PFC_COL_GRID && std::is_same<T, double>::value;
-  __shared__ double ss_g[SS ? 32 : 1];
-  __shared__ double ss_coef[SS ? 16 : 1];
+  // and float launches of one instance on a 3D periodic grid of side 64 (blocks of the grid)
+  constexpr bool SS3 = SINGLE && COLS == PFC_COL_GRID && std::is_same<T, float>::value;
+  constexpr bool SSX = SS || SS3;
+  __shared__ double ss_g[SSX ? 32 : 1];
+  __shared__ double ss_coef[SSX ? 16 : 1];
   PFC_STAMP(t_entry);
   const int tid = threadIdx.x;
   TeamEntry te;
@@ -538,14 +541,17 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     gs_gather(I.gpart + (long long)parity * te.size * PFC_GS_NV, te.size, &I.hist->L[0][0], gs_g, gs_L);
   bool scg = false;
   SsPre ssp;
-  if constexpr (SS) {
+  S3Pre<float> s3p;
+  if constexpr (SSX) {
     // launches after a two-iteration launch, or after the set-up that formed the first basis
     scg = S.phase == PH_SCG_ITER || (S.phase == PH_PCG_SETUP && I.sstep && scg_kind(S.kind));
     if (scg && !(S.phase == PH_SCG_ITER && S.pcur)) {
       const double* gpart = I.spart + (long long)S.cur * te.size * 32;
       double pl[PFC_SS_GL];
       ss_gram_load(gpart, te.size, pl);
-      ss_load(I, S, ss_rows(I, te.rank, te.size), ssp);  // in flight during the reduction and the transition
+      // in flight during the reduction and the transition
+      if constexpr (SS) ss_load(I, S, ss_rows(I, te.rank, te.size), ssp);
+      else s3_load<float>(I, S, te.rank, s3p);
       ss_gram(gpart, te.size, pl, ss_g);
 #ifdef PFC_TICK_TIMING
       if (tid == 0) pfc_sst[4] = wall_clock64();
@@ -554,7 +560,7 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   }
   if (tid == 0) {
     if (scg) {
-      if constexpr (SS) scg_transition(S, I, writer, ss_g, ss_coef);
+      if constexpr (SSX) scg_transition(S, I, writer, ss_g, ss_coef);
 #ifdef PFC_TICK_TIMING
       if constexpr (SS) pfc_sst[5] = wall_clock64();
 #endif
@@ -568,7 +574,7 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
       else if (!cg_iter_continues(S, I, red)) transition(S, I, writer, red, ybuf, gcol, SS && I.sstep);
     }
   }
-  if constexpr (SS) {
+  if constexpr (SSX) {
     if (scg) lds_barrier();  // the basis loads issued in the prologue stay in flight
     else __syncthreads();
   } else {
@@ -588,11 +594,14 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     case PH_RB_UPDATE: acc = ph_rb_update(I, tm); break;
     // the mass solves of the consistent initial values run in float64 in every precision
     case PH_PCG_SETUP:
-      if constexpr (SS) {
+      if constexpr (SSX) {
         if (I.sstep && scg_kind(S.kind)) {  // set-up and first basis of a two-iteration solve
           fused = true;
-          ph_scg<COLS>(I, S, tm, ss_coef, true, I.spart + (long long)S.cur * te.size * 32, ss_rows(I, te.rank, te.size),
-                       ssp);
+          if constexpr (SS)
+            ph_scg<COLS>(I, S, tm, ss_coef, true, I.spart + (long long)S.cur * te.size * 32,
+                         ss_rows(I, te.rank, te.size), ssp);
+          else
+            ph_scg3<float>(I, S, tm, ss_coef, true, I.spart + (long long)S.cur * te.size * 32, s3p);
           break;
         }
       }
@@ -617,6 +626,8 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
       if constexpr (SS)
         ph_scg<COLS>(I, S, tm, ss_coef, false, I.spart + (long long)S.cur * te.size * 32, ss_rows(I, te.rank, te.size),
                      ssp);
+      else if constexpr (SS3)
+        ph_scg3<float>(I, S, tm, ss_coef, false, I.spart + (long long)S.cur * te.size * 32, s3p);
       break;
     default: break;
   }
@@ -848,6 +859,16 @@ static int sstep_halo(const pfc_mesh* m, const pfc_opts& o, int team_size) {
   return H;
 }
 
+// Two PCG iterations per launch on blocks of a 3D grid (ph_scg3): float
+// (mixed-precision) single-reduction instances on periodic grids of side 64 with
+// computed columns and entry directions, one row per thread (a team of 256
+// workgroups of 4 x 4 x-lines).
+static bool sstep_block3(const pfc_mesh* m, const pfc_opts& o, int team_size) {
+  const MeshDev& d = m->dev;
+  return o.pcg_steps_per_launch == 2 && o.precision == PFC_MIXED && o.single_reduction == 1 && o.grid_columns == 1 &&
+         d.dim == 3 && d.gN == PFC_S3_N && d.uw == 15 && d.gdir_ok && team_size == 256 && d.n_slices == 4096;
+}
+
 // Carve the instance arena.  With base == nullptr only the size is computed.
 size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int team_size) {
   size_t off = 0;
@@ -892,7 +913,7 @@ size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int t
   h.part = (double*)take(2 * (size_t)team_size * 4 * sizeof(double));
   h.gpart = (double*)take(2 * (size_t)team_size * PFC_GS_NV * sizeof(double));
   h.sH = sstep_halo(m, o, team_size);
-  h.sstep = h.sH > 0;
+  h.sstep = h.sH > 0 ? 1 : (sstep_block3(m, o, team_size) ? 2 : 0);
   h.sbas = h.sstep ? (double*)take(10 * n * 8) : nullptr;
   h.spart = h.sstep ? (double*)take(2 * (size_t)team_size * 32 * sizeof(double)) : nullptr;
   h.st = (State*)take(2 * sizeof(State));

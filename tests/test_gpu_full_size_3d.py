@@ -85,6 +85,7 @@ def test_c3_stage_solve_fp64_replay_and_mixed_tolerance(pfc, c3):
         # the benchmark's mixed-precision instance
         imp = pfc.pfc_instance_create(mesh, pfc.pfc_opts_default(precision=1))
         insts.append(imp)
+        assert pfc.pfc_instance_config(imp)["pcg_steps_per_launch"] == 2   # blocks of the grid
         st, gi = pfc.pfc_solve(imp, n, dev(P.psi), R, PSIBAR, TAU, M11, dev(c3["b"]), x)
         ymp = host(x)
         resmp = _residual(c3, ymp)
@@ -132,6 +133,48 @@ def test_c3_rosenbrock_step_fp64_replay_and_mixed(pfc, c3):
         bnd = sum(abs(m) for m in opfc.ROS3PW_M) * opfc.ROS3PW_GAMMA * np.sqrt(n) * 1e-8
         bmax = max(np.linalg.norm(c3["b"]), 1.0)
         assert abs(np.sum(P.M @ s[n:2 * n]) - np.sum(P.M @ P.psi)) <= 10 * bnd * bmax
+    finally:
+        for i in insts:
+            pfc.pfc_instance_destroy(i)
+
+
+def test_c3_two_pcg_iterations_per_launch_blocks(pfc, c3):
+    """The mixed instance's inner PCG runs two iterations per launch on blocks of the grid (4 x 4 x-lines
+    per workgroup, one- and two-step frames in LDS).  With the oracle's inner counts fixed, odd ones
+    included (a launch that ends after the first of its two iterations), one P_CH apply in that form
+    reaches the oracle's float64 apply as closely as the one-iteration float32 form does (both differ
+    from it by float32 rounding of the inner solves), and the form takes fewer launches."""
+    from oracle import precond
+    P = c3["P"]
+    n = P.n
+    tau_s = TAU / M11
+    w = np.random.default_rng(3).normal(size=3 * n)
+    inner = precond.InnerSolvers(P.M, P.K, tau_s, mode="pcg", tol=1e-3)
+    z_ref = precond.pch_apply(inner, w)
+    counts = list(inner.counts[0])
+    out = {}
+    insts = []
+    try:
+        mesh = P.gpu_mesh()
+        for spl in (2, 1):
+            inst = pfc.pfc_instance_create(mesh, pfc.pfc_opts_default(precision=1, pcg_steps_per_launch=spl))
+            insts.append(inst)
+            assert pfc.pfc_instance_config(inst)["pcg_steps_per_launch"] == spl
+            for fixed in (counts, [3, 1, 4, 5, 2]):
+                ref = z_ref if fixed is counts else precond.pch_apply(
+                    precond.InnerSolvers(P.M, P.K, tau_s, mode="pcg", fixed_counts=fixed), w)
+                z = dev(np.zeros(3 * n))
+                print(f"3D 64^3: P_CH apply, {spl} PCG iteration(s) per launch, counts {fixed}", flush=True)
+                got = pfc.pfc_apply_pch(inst, n, tau_s, dev(w), z, fixed_counts=fixed)
+                assert list(got) == list(fixed)
+                out[(spl, tuple(fixed))] = (rel(host(z), ref), pfc.pfc_instance_launch_stats(inst)[0])
+        for fixed in (counts, [3, 1, 4, 5, 2]):
+            (e2, l2), (e1, l1) = out[(2, tuple(fixed))], out[(1, tuple(fixed))]
+            print(f"3D 64^3: counts {fixed}: error against the oracle {e2:.2e} (two per launch) "
+                  f"{e1:.2e} (one per launch); launches {l2} / {l1}", flush=True)
+            assert e2 <= max(1e-5, 3.0 * e1), (e2, e1)
+            if sum(fixed) >= 20:
+                assert l2 < 0.8 * l1, (l2, l1)
     finally:
         for i in insts:
             pfc.pfc_instance_destroy(i)
