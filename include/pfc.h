@@ -12,7 +12,10 @@
  *     m11 = 1/gamma for Rosenbrock stages and m11 = 1 for the linearised Euler
  *     system (eq. systemmatrix);
  *   - right-preconditioned flexible GMRES(restart) with modified Gram-Schmidt
- *     (Section 4 and the solver settings of Section 7);
+ *     (Section 4 and the solver settings of Section 7), its coefficients for
+ *     Arnoldi step j taken from one reduction (the lower-triangular system
+ *     (I + L) h = V^T w, L the strictly lower Gram matrix of the basis, which
+ *     equals modified Gram-Schmidt in exact arithmetic);
  *   - the preconditioner P_CH = P(S_CH) of eq. preconditioner_S with
  *     S_CH = (M + sqrt(delta) K) M^{-1} (M + sqrt(delta) K), delta = sqrt(tau),
  *     applied in five steps with Jacobi-PCG inner solves (Section 4.2,
