@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # was taken on: when their digest differs, `traffic` is reported as null.
 TRAFFIC = {
     # workload: (sha256 of the kernel sources, bytes per launch, algorithmic bytes per launch of the same run)
-    "pfc2d_512_fp64": ("b024f9995be3e40259003c58458c2c3ae1cb61e377efba39eb20a191389fe2dc", 37899747.0, 65684139.0),
-    "pfc3d_64_mixed": ("b024f9995be3e40259003c58458c2c3ae1cb61e377efba39eb20a191389fe2dc", 30396108.0, 37670502.0),
+    "pfc2d_512_fp64": ("9d291b9d1a3157b0a8f9a8409ab70c26403d511b91a5f4edc91288af4b900148", 42997952.0, 78820966.0),
+    "pfc3d_64_mixed": ("9d291b9d1a3157b0a8f9a8409ab70c26403d511b91a5f4edc91288af4b900148", 41698443.0, 71753338.0),
 }
 
 
