@@ -87,6 +87,22 @@ VARIANTS = {
 }
 
 
+# The paper's own numbers for this path, quoted as context only: a machine the tables do not name, a time
+# discretisation they do not single out (implicit Euler or the Rosenbrock scheme, Section 7), h = pi/4,
+# about 66,000 DOFs; P_CH with PCG inner solves as in Table inner_solvers, times per linear solve averaged
+# over 20 time steps.
+PAPER_CONTEXT = {
+    2: {"source": "Table direct_iterative_solvers (tau = 0.1, P1) and Table timestep_change (P2, tau = 1.0), 2D",
+        "p1_tau0.1": {"seconds_per_solve": 1.65, "outer_iterations": 14},
+        "p2_tau1.0": {"seconds_per_solve": 4.53, "outer_iterations": 19},
+        "hardware": "not stated (sequential AMDiS/MTL4 runs)", "dofs": "about 66,000"},
+    3: {"source": "Table direct_iterative_solvers (tau = 0.1, P1) and Table timestep_change (P2, tau = 1.0), 3D",
+        "p1_tau0.1": {"seconds_per_solve": 3.36, "outer_iterations": 18},
+        "p2_tau1.0": {"seconds_per_solve": 14.29, "outer_iterations": 24},
+        "hardware": "not stated (sequential AMDiS/MTL4 runs)", "dofs": "about 66,000"},
+}
+
+
 def run_cpu_baseline(dim, N, jitter, r, psibar, tau, seed, repeats=3):
     """The oracle as it stands: one Rosenbrock step (three stage solves) of the same workload, timed
     `repeats` times from the same state, median.  The oracle's work is scipy sparse products and numpy
@@ -286,6 +302,7 @@ def bench_served(args, torch, wl, pfc):
         m = wl.make_mesh(dim, N)
         meshes.append((m, pfc.pfc_mesh_create_p1(dim, m.n, m.elem_nodes, m.elem_coords)))
     nreq = args.requests
+    warm = int(np.ceil(0.05 * nreq))
     steps = args.req_steps
     rpt = 0 if args.rows_per_thread is None else args.rows_per_thread   # 0: chosen per request by load
 
@@ -325,7 +342,8 @@ def bench_served(args, torch, wl, pfc):
                 break
             for k in range(got.value):
                 r = buf[k]
-                lat.append(r.t_done - arrive[r.req_id])
+                if r.req_id >= warm:   # the first 5% of the stream warm the server up
+                    lat.append(r.t_done - arrive[r.req_id])
                 worst = max([worst] + [r.infos[i].true_rel_res for i in range(r.n_stages)])
                 if r.req_id in keep:
                     nn = meshes[reqs[r.req_id][1]][0].n
@@ -335,7 +353,7 @@ def bench_served(args, torch, wl, pfc):
         lat = np.array(lat)
         return dict(solves_per_s=3 * steps * nreq / (t_end - t_base), wall_s=t_end - t_base,
                     p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
-                    max_true_rel_res=worst), kept
+                    latency_requests=int(lat.size), max_true_rel_res=worst), kept
 
     # capacity of the plain server (backlogged), then both at 0.8 of that rate
     # the first request of each of the three smallest classes is checked against the oracle
@@ -364,7 +382,8 @@ def bench_served(args, torch, wl, pfc):
     out = {"metric": "PFC block solves/s @1e-8 rel residual; p50/p99 served latency", "value": ours_bl["solves_per_s"],
            "unit": "stage solves/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64 outer / f32 inner",
            "data": "synthetic",
-           "config": {"workload": "served_stream", "requests": nreq, "rosenbrock_steps": steps,
+           "config": {"workload": "served_stream", "requests": nreq, "warmup_requests_excluded_from_latency": warm,
+                      "rosenbrock_steps": steps,
                       "classes": [f"{d}D {N}" for d, N in classes], "arrival_rate_hz": rate, "slots": args.slots,
                       "rows_per_thread": "autotuner (mixed-batch table entry for the active count)" if rpt == 0
                       else rpt,
@@ -498,7 +517,7 @@ def main():
     ap.add_argument("--no-handpicked", action="store_true", help="batched: skip the hand-picked comparison run")
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--plain-sample", type=int, default=16)
-    ap.add_argument("--requests", type=int, default=48)
+    ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--req-steps", type=int, default=5)
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--rows-per-thread", type=int, default=None,
@@ -623,6 +642,7 @@ def main():
                      "algorithmic_bytes": alg, "algorithmic_bytes_per_launch": alg / max(1, launches),
                      "avg_launch_period_us": period_s * 1e6, "kernel_sources_sha256": kernel_source_digest()},
     }
+    out["paper_context"] = PAPER_CONTEXT[dim]
     if not args.no_precision_check:
         # accuracy against the float64 oracle at the final state (not timed); a mixed-precision
         # workload also reports the float64 GPU solve of the same system for comparison
