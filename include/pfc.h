@@ -141,11 +141,13 @@ typedef struct pfc_server pfc_server;
  *                 standard iteration in exact arithmetic, and the same count
  *                 of iterations.  It applies in launches that serve the
  *                 instance alone, to single_reduction = 1 instances with
- *                 grid_columns = 1 and rows_per_thread <= 1 that are either
- *                 float64 on a 2D periodic grid mesh (a workgroup's rows are
- *                 a range of rows) or PFC_MIXED on a 3D periodic grid mesh of
- *                 side 64 (a workgroup's rows are a block of 4 x 4 grid lines,
- *                 the inner iterations in float32); elsewhere, and with 1, one
+ *                 grid_columns = 1 and rows_per_thread <= 1 on 2D periodic
+ *                 grid meshes of side a multiple of 64 (either precision; a
+ *                 workgroup's rows are a block of 64 x 16 grid points), other
+ *                 2D periodic grid meshes in float64 (a workgroup's rows are a
+ *                 range of rows) and 3D periodic grid meshes of side 64 in
+ *                 PFC_MIXED (a block of 4 x 4 grid lines); in PFC_MIXED the
+ *                 inner iterations run in float32.  Elsewhere, and with 1, one
  *                 iteration per launch.  Results then differ from a launch
  *                 that serves the instance together with others by rounding
  *                 (1 gives the same bits alone and in a batch). */

@@ -1026,11 +1026,11 @@ struct SsPre {
   double bv[PFC_SS_NA][5];
   double xo;
 };
-__device__ __forceinline__ void ss_load(const InstDev& I, const State& S, const SsRows& w, SsPre& P) {
+__device__ __forceinline__ void ss_load(const InstDev& I, const State& S, const SsRows& w, SsPre& P, int par) {
   const int n = I.n;
   const long long nn = n;
   const int tid = threadIdx.x;
-  const double* bin = I.sbas + (long long)S.cur * 5 * nn;  // the basis of the previous launch
+  const double* bin = I.sbas + (long long)par * 5 * nn;  // the basis of the previous launch
 #pragma unroll
   for (int c = 0; c < PFC_SS_NA; ++c) {
     const int g = ss_wrap(w.lo - 2 * w.H + min(tid + c * PFC_WG, w.L2 - 1), n);
@@ -1041,15 +1041,16 @@ __device__ __forceinline__ void ss_load(const InstDev& I, const State& S, const 
 }
 
 // coef: x increment [0..4], new p [5..9], new u [10..14] over B; S.pcur: x only.
+// par: the launch's parity (reads basis [par], writes basis [1 - par]).
 template <int L>
 __device__ __forceinline__ void ph_scg(const InstDev& I, const State& S, const Team& tm, const double* coef, bool init,
-                                       double* spart_out, const SsRows& w, SsPre& P) {
+                                       double* spart_out, const SsRows& w, SsPre& P, int par) {
   const int n = I.n, H = w.H, R = w.R, L1 = w.L1, L2 = w.L2, lo = w.lo;
   PcgOps<double> o = pcg_ops<double>(I, S.kind);
   const PatView<L> pv = op_pat<L>(I, o, tm);
   const int tid = threadIdx.x;
   const long long nn = n;
-  double* bout = I.sbas + (long long)S.cur * 5 * nn;
+  double* bout = I.sbas + (long long)(1 - par) * 5 * nn;
   double bbo = 0.0;  // ||b||^2 over the own rows (first launch of a solve)
   if (init) {
     // the solve's right-hand side b (the set-up of the inner solve, on the own
@@ -1254,18 +1255,18 @@ __device__ __forceinline__ void ph_scg(const InstDev& I, const State& S, const T
   PFC_SS_STAMP(3);
 }
 
-// Sum of the Gram partials of a team ([size][32], fixed order) into g[0..24].
-// Issued before the basis loads (the memory counters complete in order, so the
-// reduction then waits for these loads only); teams of more than 256 add the rest.
+// Sum of the Gram partials of a team ([size][32], fixed order) into g[0..25]:
+// the first 8 x 32 partials come from loads issued in the launch's prologue,
+// before its phase is known, with the state loads (unconditional loads at
+// clamped positions, masked in the sum; from fallback[0] where part is null,
+// values then unused); teams of more than 256 add the rest here.
 #define PFC_SS_GL 8
-__device__ __forceinline__ void ss_gram_load(const double* part, int size, double* pl) {
+__device__ __forceinline__ void ss_gram_prefetch(const double* part, const double* fallback, int size, double* pl) {
   const int tid = threadIdx.x, v = tid & 31, grp = tid >> 5;
-  // unconditional loads at clamped positions (straight-line code keeps the wait
-  // for them separate from the later loads), masked afterwards
 #pragma unroll
   for (int c = 0; c < PFC_SS_GL; ++c) {
     const int k = min(grp + 32 * c, size - 1);
-    pl[c] = gld(part + (long long)k * 32 + min(v, PFC_SS_NG - 1));
+    pl[c] = gld(part ? part + (long long)k * 32 + min(v, PFC_SS_NG - 1) : fallback);
   }
 }
 __device__ __forceinline__ void ss_gram(const double* part, int size, const double* pl, double* g) {
@@ -1334,11 +1335,11 @@ struct S3Pre {
 };
 // the current basis on the two-step frame, issued before the reductions
 template <typename T>
-__device__ __forceinline__ void s3_load(const InstDev& I, const State& S, int rank, S3Pre<T>& P) {
+__device__ __forceinline__ void s3_load(const InstDev& I, const State& S, int rank, S3Pre<T>& P, int par) {
   const long long nn = I.n;
   const int tid = threadIdx.x;
   const S3Geo G = s3_geo(rank);
-  const T* bin = (const T*)I.sbas + (long long)S.cur * 5 * nn;
+  const T* bin = (const T*)I.sbas + (long long)par * 5 * nn;
 #pragma unroll
   for (int c = 0; c < PFC_SS_NA; ++c) {
     const int q = tid + c * PFC_WG;
@@ -1350,15 +1351,15 @@ __device__ __forceinline__ void s3_load(const InstDev& I, const State& S, int ra
 
 template <typename T>
 __device__ __forceinline__ void ph_scg3(const InstDev& I, const State& S, const Team& tm, const double* coef, bool init,
-                                        double* spart_out, S3Pre<T>& P) {
+                                        double* spart_out, S3Pre<T>& P, int par) {
   constexpr int W15 = 15;
   const int n = I.n, tid = threadIdx.x;
   const long long nn = n;
   const S3Geo G = s3_geo(tm.rank);
   PcgOps<T> o = pcg_ops<T>(I, S.kind);
   const PatView<PFC_COL_GRID> pv = op_pat<PFC_COL_GRID>(I, o, tm);
-  T* bout = (T*)I.sbas + (long long)S.cur * 5 * nn;
-  const T* bold = (const T*)I.sbas + (long long)(S.cur ^ 1) * 5 * nn;
+  T* bout = (T*)I.sbas + (long long)(1 - par) * 5 * nn;
+  const T* bold = (const T*)I.sbas + (long long)par * 5 * nn;
   const unsigned char* gdir = I.m.gdir;
   T* sp = (T*)pfc_ss;          // new p on the two-step frame [4096]
   T* su = sp + 4096;           // new u on the one-step frame [2304]
@@ -1477,6 +1478,247 @@ __device__ __forceinline__ void ph_scg3(const InstDev& I, const State& S, const 
     dg += code == 13 ? ao[k] : T(0);
   }
   const int o2 = ox + PFC_S3_N * ((oyl + 2) + 8 * (ozl + 2)), o1 = ox + rb1;
+  const T pn = sp[o2], un = su[o1], tpo = stp[o1], tuo = odi * au, ttp = odi * att;
+  double bbo = 0.0;
+  if (init) {
+    const double bo = (double)sb[o2];
+    bbo = bo * bo;
+    vst(o.x + og, T(0));
+    const long long n3 = 3 * nn;
+    if (S.kind == KIND_Y0) {  // the Arnoldi vector v_j = w / ||w||
+      double* Vw = I.V + (long long)S.j * n3;
+      vst(Vw + og, gld(I.W + og) * S.vscale);
+      vst(Vw + nn + og, gld(I.W + nn + og) * S.vscale);
+      vst(Vw + 2 * nn + og, gld(I.W + 2 * nn + og) * S.vscale);
+    } else if (S.kind == KIND_X2) {  // (4): z_j = (y0 + (y1 - x1) / delta, x1, x2)
+      double* Zj = I.Z + (long long)S.j * n3;
+      const double y0i = (double)gld((const T*)I.y0 + og), y1i = (double)gld((const T*)I.y1 + og);
+      const double x1i = (double)gld((const T*)I.x1 + og);
+      vst(Zj + og, y0i + (y1i - x1i) / I.delta);
+      vst(Zj + nn + og, x1i);
+    }
+  } else {
+    const T xo = gld(o.x + og);
+    const double p = gld(bold + og), tp = gld(bold + nn + og), u = gld(bold + 3 * nn + og);
+    vst(o.x + og, T((double)xo + (coef[0] * p + coef[1] * tp + coef[3] * u)));
+  }
+  vst(bout + og, pn);
+  vst(bout + nn + og, tpo);
+  vst(bout + 2 * nn + og, ttp);
+  vst(bout + 3 * nn + og, un);
+  vst(bout + 4 * nn + og, tuo);
+  double gp[PFC_SS_NG];
+  {
+    const double dgo = (double)dg;
+    const double v[5] = {(double)pn, (double)tpo, (double)ttp, (double)un, (double)tuo};
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      const double di = dgo * v[i];
+#pragma unroll
+      for (int j = i; j < 5; ++j) gp[ss_tri(i, j, 5)] = di * v[j];
+    }
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+      const double di = dgo * dgo * v[i];
+#pragma unroll
+      for (int j = i; j < 5; ++j) gp[15 + ss_tri(i - 1, j - 1, 4)] = di * v[j];
+    }
+  }
+  gp[25] = bbo;
+  // workgroup sums as ph_scg: each wave by recursive halving, then over the waves
+  const int lane = tid & 63, wave = tid >> 6;
+  {
+    double v32[32];
+#pragma unroll
+    for (int m = 0; m < 32; ++m) v32[m] = m < PFC_SS_NG ? gp[m] : 0.0;
+    const double tot = ss_wave_sums32(v32, lane);
+    const int idx = ss_wave_sums32_index(lane);
+    if ((lane & 1) == 0) pfc_ssred[wave * 32 + idx] = tot;
+  }
+  lds_barrier();
+  if (tid < PFC_SS_NG) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < PFC_WAVES; ++w) t += pfc_ssred[w * 32 + tid];
+    vst(spart_out + (long long)tm.rank * 32 + tid, t);
+  }
+}
+
+// ---- two Jacobi-PCG iterations per launch on blocks of 2D periodic grids -------
+// The iteration of ph_scg3 on a 2D grid of side N, a multiple of 64: rank r
+// owns the block of 64 x 16 rows x0 .. x0 + 63, y0 .. y0 + 15 with
+// x0 = 64 (r mod N/64), y0 = 16 (r div N/64).  The two-step frame is the
+// 68 x 20 rows x0 - 2 .. x0 + 65, y0 - 2 .. y0 + 17, the one-step frame the
+// 66 x 18 rows x0 - 1 .. x0 + 64, y0 - 1 .. y0 + 16 (periodic), so a row's
+// neighbour in a frame is the row's frame position plus the entry's direction
+// (MeshDev::gdir).  Against a range of whole grid lines per workgroup (ph_scg)
+// the frames hold 1360 and 1188 rows instead of 3076 and 2050 at N = 512: the
+// basis is read, and p and T p are formed, on fewer rows.  Thread t's own row
+// is x0 + t mod 64, y0 + t / 64, so a wave's own rows are one SELL slice.
+#define PFC_B2_W2 68
+#define PFC_B2_N2 (PFC_B2_W2 * 20)  // two-step frame
+#define PFC_B2_W1 66
+#define PFC_B2_N1 (PFC_B2_W1 * 18)  // one-step frame
+struct B2Geo {
+  int x0, y0, N;
+};
+__device__ __forceinline__ B2Geo b2_geo(int rank, int N) {
+  const int bx = N >> 6;
+  return B2Geo{(rank % bx) * 64, (rank / bx) * 16, N};
+}
+__device__ __forceinline__ int b2_wrap(int v, int N) { return v < 0 ? v + N : (v >= N ? v - N : v); }
+// row at block coordinates (fx, fy), -2 <= fx < 66, -2 <= fy < 18
+__device__ __forceinline__ int b2_row(const B2Geo& G, int fx, int fy) {
+  return b2_wrap(G.x0 + fx, G.N) + G.N * b2_wrap(G.y0 + fy, G.N);
+}
+__device__ __forceinline__ int b2_class(const B2Geo& G, int fx, int fy) {
+  return grid_edge(b2_wrap(G.x0 + fx, G.N), G.N) + 3 * grid_edge(b2_wrap(G.y0 + fy, G.N), G.N);
+}
+// frame offset of an entry's direction code in a frame of width w
+__device__ __forceinline__ int b2_doff(int code, int w) { return code % 3 - 1 + w * ((code / 3) % 3 - 1); }
+
+template <typename T>
+struct B2Pre {
+  T bv[2][5];
+};
+// the current basis on the two-step frame (the second pass covers 336
+// positions; the others load a clamped position), issued before the reductions
+template <typename T>
+__device__ __forceinline__ void b2_load(const InstDev& I, int rank, B2Pre<T>& P, int par) {
+  const long long nn = I.n;
+  const int tid = threadIdx.x;
+  const B2Geo G = b2_geo(rank, I.m.gN);
+  const T* bin = (const T*)I.sbas + (long long)par * 5 * nn;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int q = min(tid + c * PFC_WG, PFC_B2_N2 - 1);
+    const int g = b2_row(G, q % PFC_B2_W2 - 2, q / PFC_B2_W2 - 2);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) P.bv[c][k] = gld(bin + k * nn + g);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void ph_scg2b(const InstDev& I, const State& S, const Team& tm, const double* coef, bool init,
+                                         double* spart_out, B2Pre<T>& P, int par) {
+  constexpr int W7 = 7;
+  const int n = I.n, tid = threadIdx.x;
+  const long long nn = n;
+  const B2Geo G = b2_geo(tm.rank, I.m.gN);
+  PcgOps<T> o = pcg_ops<T>(I, S.kind);
+  const PatView<PFC_COL_GRID> pv = op_pat<PFC_COL_GRID>(I, o, tm);
+  T* bout = (T*)I.sbas + (long long)(1 - par) * 5 * nn;
+  const T* bold = (const T*)I.sbas + (long long)par * 5 * nn;
+  const unsigned char* gdir = I.m.gdir;
+  T* sp = (T*)pfc_ss;          // new p on the two-step frame
+  T* su = sp + PFC_B2_N2;      // new u on the one-step frame
+  T* stp = su + PFC_B2_N1;     // T p on the one-step frame
+  T* sb = stp + PFC_B2_N1;     // right-hand side on the two-step frame (first launch of a solve)
+  static_assert((2 * PFC_B2_N2 + 2 * PFC_B2_N1) * sizeof(double) <= sizeof(pfc_ss),
+                "the frames of ph_scg2b exceed the s-step LDS");
+  const int ox = tid & 63, oy = tid >> 6;
+  const int og = b2_row(G, ox, oy);
+  if (init) {
+    // the solve's right-hand side b on the two-step frame and u_0 = p_0 = D^{-1} b;
+    // as ph_scg: b = t - s (A v) by solve kind
+    const long long n3 = 3 * nn;
+    const double* Vj = I.V + (long long)S.j * n3;
+    const int kind = S.kind;
+    const T* A = (kind == KIND_Y1 || kind == KIND_X2) ? o.Kv : (kind == KIND_Y0 ? nullptr : o.Mv);
+    const T* v = kind == KIND_Y1 ? (const T*)I.y0 : kind == KIND_Z ? (const T*)I.y1 : kind == KIND_X1 ? (const T*)I.zt
+                                                                                                      : (const T*)I.x1;
+    const double* t = kind == KIND_Y0 ? I.W : (kind == KIND_Y1 ? Vj + nn : (kind == KIND_X2 ? Vj + 2 * nn : nullptr));
+    const double ts = kind == KIND_Y0 ? S.vscale : 1.0, sa = kind == KIND_Y1 ? I.tau_p : 1.0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int q = tid + c * PFC_WG, qc = min(q, PFC_B2_N2 - 1);
+      const int g = b2_row(G, qc % PFC_B2_W2 - 2, qc / PFC_B2_W2 - 2);
+      const int base = (g >> 6) * 64 * W7 + (g & 63);
+      T d = T(0);
+      if (A) {
+#pragma unroll
+        for (int k = 0; k < W7; ++k) {
+          const long long e = (long long)base + k * 64;
+          d += gld(A + e) * gld(v + pv.at(e, g));
+        }
+      }
+      const double tt = t ? gld(t + g) * ts : 0.0;
+      const double b = !A ? tt : (t ? tt - sa * (double)d : (double)d);
+      P.bv[c][0] = gld(o.dinv + g);
+      P.bv[c][1] = T(b);
+      if (q < PFC_B2_N2) sb[q] = T(b);
+    }
+  } else if (S.pcur) {  // the solve ends within these two iterations: x only, on the own row
+    const T xo = gld(o.x + og);
+    const double p = gld(bold + og), tp = gld(bold + nn + og), u = gld(bold + 3 * nn + og);
+    vst(o.x + og, T((double)xo + (coef[0] * p + coef[1] * tp + coef[3] * u)));
+    return;
+  }
+  // new p on the two-step frame, new u on the one-step frame
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int q = tid + c * PFC_WG;
+    if (q < PFC_B2_N2) {
+      const T* b = P.bv[c];
+      T pn, un;
+      if (init) {
+        pn = b[0] * b[1];
+        un = pn;
+      } else {
+        pn = T(coef[5] * b[0] + coef[6] * b[1] + coef[7] * b[2] + coef[8] * b[3] + coef[9] * b[4]);
+        un = T(coef[10] * b[0] + coef[11] * b[1] + coef[12] * b[2] + coef[13] * b[3] + coef[14] * b[4]);
+      }
+      sp[q] = pn;
+      const int fx = q % PFC_B2_W2 - 2, fy = q / PFC_B2_W2 - 2;
+      if (fx >= -1 && fx < 65 && fy >= -1 && fy < 17) su[(fx + 1) + PFC_B2_W1 * (fy + 1)] = un;
+    }
+  }
+  // operator rows of the one-step frame (the second pass covers 164 rows), in
+  // flight across the barrier
+  T av[2][W7], dv[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int q1 = min(tid + c * PFC_WG, PFC_B2_N1 - 1);
+    const int g = b2_row(G, q1 % PFC_B2_W1 - 1, q1 / PFC_B2_W1 - 1);
+    const int base = (g >> 6) * 64 * W7 + (g & 63);
+#pragma unroll
+    for (int k = 0; k < W7; ++k) av[c][k] = opval_g(o, (long long)base + k * 64);
+    dv[c] = gld(o.dinv + g);
+  }
+  lds_barrier();
+  // T p on the one-step frame
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int q1 = tid + c * PFC_WG;
+    if (q1 < PFC_B2_N1) {
+      const int fx = q1 % PFC_B2_W1 - 1, fy = q1 / PFC_B2_W1 - 1;
+      const unsigned char* gd = gdir + b2_class(G, fx, fy) * PFC_GRID_W;
+      const int q2 = (fx + 2) + PFC_B2_W2 * (fy + 2);
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < W7; ++k) acc += av[c][k] * sp[q2 + b2_doff(gd[k], PFC_B2_W2)];
+      stp[q1] = dv[c] * acc;
+    }
+  }
+  // the own row's operator row (a cache hit: the frame pass read it)
+  T ao[W7];
+  const int obase = (og >> 6) * 64 * W7 + (og & 63);
+#pragma unroll
+  for (int k = 0; k < W7; ++k) ao[k] = opval_g(o, (long long)obase + k * 64);
+  const T odi = gld(o.dinv + og);
+  lds_barrier();
+  // own row: T u, T^2 p, the stores and the Gram products
+  const unsigned char* gd = gdir + b2_class(G, ox, oy) * PFC_GRID_W;
+  const int o1 = (ox + 1) + PFC_B2_W1 * (oy + 1), o2 = (ox + 2) + PFC_B2_W2 * (oy + 2);
+  T au = T(0), att = T(0), dg = T(0);
+#pragma unroll
+  for (int k = 0; k < W7; ++k) {
+    const int code = gd[k];
+    const int i1 = o1 + b2_doff(code, PFC_B2_W1);
+    au += ao[k] * su[i1];
+    att += ao[k] * stp[i1];
+    dg += code == 13 ? ao[k] : T(0);
+  }
   const T pn = sp[o2], un = su[o1], tpo = stp[o1], tuo = odi * au, ttp = odi * att;
   double bbo = 0.0;
   if (init) {

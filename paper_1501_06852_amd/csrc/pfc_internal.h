@@ -164,7 +164,7 @@ struct InstDev {
   int grid_cols, gamma_mode;    // grid_columns and gamma_mode options
   int inner_fixed[5], pad_if;   // fixed inner iteration counts (0: to inner_tol)
   int sstep, sH;                // two PCG iterations per launch: 0 no, 1 row ranges of a 2D grid (halo sH = N + 1
-                                // rows), 2 blocks of a 3D grid of side 64
+                                // rows), 2 blocks of a 3D grid of side 64, 3 blocks of a 2D grid (side 64 k)
   double outer_tol, inner_tol, ci_tol;
   // job parameters; tau_p = m0 tau_s is the preconditioner's time step
   // rs: factor of block row 1 in the system FGMRES works on (1/m11 for
@@ -195,6 +195,8 @@ struct InstDev {
   void *rB, *wB, *sA, *sB;      // extra buffers of the single-reduction PCG
   double* part;                 // [2][team_size][4] partial sums
   double* gpart;                // [2][team_size][64] Gram partial sums of the orthogonalisation
+  // s-step double buffers, indexed by the launch's parity: a launch reads the
+  // previous launch's basis and Gram partials from [parity], writes to [1 - parity]
   double* sbas;                 // s-step basis [2][5][n] (p, Tp, T^2 p, u, Tu), or null
   double* spart;                // s-step Gram partial sums [2][team_size][32], or null
   State* st;                    // [2]

@@ -234,7 +234,6 @@ __device__ void scg_transition(State& S, const InstDev& I, bool wr, const double
   if (S.phase == PH_SCG_ITER && S.pcur) { pcg_done(S, I, wr); return; }
   const bool first = (S.phase == PH_PCG_SETUP);  // that launch formed the solve's first basis
   S.phase = PH_SCG_ITER;
-  S.cur ^= 1;
   // entries (i <= j) of G = B^T D B and of H = B'^T D^2 B' (basis indices 1..4)
   auto G = [&](int i, int j) { return g[ss_tri(i, j, 5)]; };
   auto Hq = [&](int i, int j) { return g[15 + ss_tri(i - 1, j - 1, 4)]; };
@@ -450,11 +449,11 @@ __device__ __forceinline__ Red3 pcg_phase(const InstDev& I, const State& S, cons
 // (uniform slice width, at most PFC_WAVES slices per workgroup); PFC_COL_GRID
 // computes them from the row (periodic grid meshes).  The host picks the
 // variant that the launch's meshes allow.
-template <typename T, bool SINGLE, int COLS>
+template <typename T, bool SINGLE, int COLS, bool B2>
 __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ teams, const InstDev* __restrict__ insts,
                                                  const State* st_in_arg, State* st_out_arg, const double* part_in_arg,
                                                  double* part_out_arg, int parity, const int* __restrict__ col_arg,
-                                                 int uw_arg, int nsl_arg) {
+                                                 int uw_arg, int nsl_arg, const double* gram_in_arg) {
   __shared__ State S;
   __shared__ InstDev sI;
   __shared__ Red3 lds4[PFC_WAVES];
@@ -463,11 +462,13 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   __shared__ double hbuf[PFC_MAXM];          // Gram-Schmidt coefficients of the current Arnoldi step
   __shared__ double gs_g[PFC_GS_NV];         // Gram sums of the step (after PH_ASPMV)
   __shared__ double gs_L[PFC_MAXM * PFC_MAXM];
-  // two PCG iterations per launch: float64 launches that serve one instance on a periodic grid
-  constexpr bool SS = SINGLE && COLS == PFC_COL_GRID && std::is_same<T, double>::value;
-  // and float launches of one instance on a 3D periodic grid of side 64 (blocks of the grid)
-  constexpr bool SS3 = SINGLE && COLS == PFC_COL_GRID && std::is_same<T, float>::value;
-  constexpr bool SSX = SS || SS3;
+  // two PCG iterations per launch in launches that serve one instance on a
+  // periodic grid: blocks of a 2D grid (B2, either precision), else row ranges
+  // of a 2D grid in float64 and blocks of a 3D grid of side 64 in float
+  constexpr bool SB2 = B2 && SINGLE && COLS == PFC_COL_GRID;
+  constexpr bool SS = SINGLE && COLS == PFC_COL_GRID && std::is_same<T, double>::value && !B2;
+  constexpr bool SS3 = SINGLE && COLS == PFC_COL_GRID && std::is_same<T, float>::value && !B2;
+  constexpr bool SSX = SS || SS3 || SB2;
   __shared__ double ss_g[SSX ? 32 : 1];
   __shared__ double ss_coef[SSX ? 16 : 1];
   PFC_STAMP(t_entry);
@@ -490,10 +491,17 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     part_in = gI->part + (long long)parity * te.size * 4;
     part_out = gI->part + (long long)(1 - parity) * te.size * 4;
   }
-  // one round trip: partial sums of the previous launch, the state record and
-  // the instance descriptor, loaded by different threads at the same time
+  // one round trip: the state record and the instance descriptor (a word per
+  // thread, every thread loading at a clamped position), the partial sums of
+  // the previous launch and, in single-instance launches of two-iteration
+  // solves, the previous launch's Gram partials (gram_in_arg; a launch that
+  // runs another phase leaves them unused).  Every load is issued before the
+  // first of them is waited for.
   constexpr int NS = (int)(sizeof(State) / 4), ND = (int)(sizeof(InstDev) / 4);
   static_assert(NS <= 64 && ND <= PFC_WG - 64, "state / descriptor too large for the staging threads");
+  const int word = tid < 64 ? ((const int*)st_in)[min(tid, NS - 1)] : ((const int*)gI)[min(tid - 64, ND - 1)];
+  double gpl[SSX ? PFC_SS_GL : 1];
+  if constexpr (SSX) ss_gram_prefetch(gram_in_arg, part_in, te.size, gpl);
   // columns of this workgroup's slices: positions [lo, lo + len) of the SELL
   // pattern, issued first and written to LDS once everything has arrived
   int lo = 0, len = 0;
@@ -510,10 +518,13 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
       if (idx < len) cv[q] = te.col[lo + idx];
     }
   }
-  Red3 pre = red3(0.0, 0.0, 0.0);
-  for (int k = tid; k < te.size; k += PFC_WG) { pre.a += part_in[4 * k]; pre.b += part_in[4 * k + 1]; pre.c += part_in[4 * k + 2]; }
-  if (tid < NS) ((int*)&S)[tid] = ((const int*)st_in)[tid];
-  else if (tid >= 64 && tid < 64 + ND) ((int*)&sI)[tid - 64] = ((const int*)gI)[tid - 64];
+  Red3 pre = red3(0.0, 0.0, 0.0), pre2 = red3(0.0, 0.0, 0.0);
+  if (tid < te.size) { pre.a = part_in[4 * tid]; pre.b = part_in[4 * tid + 1]; pre.c = part_in[4 * tid + 2]; }
+  for (int k = tid + PFC_WG; k < te.size; k += PFC_WG) {  // teams of more than PFC_WG workgroups
+    pre2.a += part_in[4 * k]; pre2.b += part_in[4 * k + 1]; pre2.c += part_in[4 * k + 2];
+  }
+  if (tid < NS) ((int*)&S)[tid] = word;
+  else if (tid >= 64 && tid < 64 + ND) ((int*)&sI)[tid - 64] = word;
   if (COLS == PFC_COL_LDS) {
 #pragma unroll
     for (int q = 0; q < PFC_LCOL_W; ++q) {
@@ -521,6 +532,9 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
       if (idx < len) pfc_lcol[idx] = cv[q];
     }
   }
+  pre.a += pre2.a;
+  pre.b += pre2.b;
+  pre.c += pre2.c;
   pre.a = wave_sum(pre.a);
   pre.b = wave_sum(pre.b);
   pre.c = wave_sum(pre.c);
@@ -542,17 +556,16 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   bool scg = false;
   SsPre ssp;
   S3Pre<float> s3p;
+  B2Pre<T> b2p;
   if constexpr (SSX) {
     // launches after a two-iteration launch, or after the set-up that formed the first basis
     scg = S.phase == PH_SCG_ITER || (S.phase == PH_PCG_SETUP && I.sstep && scg_kind(S.kind));
     if (scg && !(S.phase == PH_SCG_ITER && S.pcur)) {
-      const double* gpart = I.spart + (long long)S.cur * te.size * 32;
-      double pl[PFC_SS_GL];
-      ss_gram_load(gpart, te.size, pl);
       // in flight during the reduction and the transition
-      if constexpr (SS) ss_load(I, S, ss_rows(I, te.rank, te.size), ssp);
-      else s3_load<float>(I, S, te.rank, s3p);
-      ss_gram(gpart, te.size, pl, ss_g);
+      if constexpr (SB2) b2_load<T>(I, te.rank, b2p, parity);
+      else if constexpr (SS) ss_load(I, S, ss_rows(I, te.rank, te.size), ssp, parity);
+      else s3_load<float>(I, S, te.rank, s3p, parity);
+      ss_gram(gram_in_arg, te.size, gpl, ss_g);
 #ifdef PFC_TICK_TIMING
       if (tid == 0) pfc_sst[4] = wall_clock64();
 #endif
@@ -597,11 +610,10 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
       if constexpr (SSX) {
         if (I.sstep && scg_kind(S.kind)) {  // set-up and first basis of a two-iteration solve
           fused = true;
-          if constexpr (SS)
-            ph_scg<COLS>(I, S, tm, ss_coef, true, I.spart + (long long)S.cur * te.size * 32,
-                         ss_rows(I, te.rank, te.size), ssp);
-          else
-            ph_scg3<float>(I, S, tm, ss_coef, true, I.spart + (long long)S.cur * te.size * 32, s3p);
+          double* gout = I.spart + (long long)(1 - parity) * te.size * 32;
+          if constexpr (SB2) ph_scg2b<T>(I, S, tm, ss_coef, true, gout, b2p, parity);
+          else if constexpr (SS) ph_scg<COLS>(I, S, tm, ss_coef, true, gout, ss_rows(I, te.rank, te.size), ssp, parity);
+          else ph_scg3<float>(I, S, tm, ss_coef, true, gout, s3p, parity);
           break;
         }
       }
@@ -623,11 +635,12 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     case PH_CG_INIT: acc = pcg_phase<T, COLS, PH_CG_INIT>(I, S, tm, sd); break;
     case PH_CG_ITER: acc = pcg_phase<T, COLS, PH_CG_ITER>(I, S, tm, sd); break;
     case PH_SCG_ITER:
-      if constexpr (SS)
-        ph_scg<COLS>(I, S, tm, ss_coef, false, I.spart + (long long)S.cur * te.size * 32, ss_rows(I, te.rank, te.size),
-                     ssp);
-      else if constexpr (SS3)
-        ph_scg3<float>(I, S, tm, ss_coef, false, I.spart + (long long)S.cur * te.size * 32, s3p);
+      if constexpr (SSX) {
+        double* gout = I.spart + (long long)(1 - parity) * te.size * 32;
+        if constexpr (SB2) ph_scg2b<T>(I, S, tm, ss_coef, false, gout, b2p, parity);
+        else if constexpr (SS) ph_scg<COLS>(I, S, tm, ss_coef, false, gout, ss_rows(I, te.rank, te.size), ssp, parity);
+        else ph_scg3<float>(I, S, tm, ss_coef, false, gout, s3p, parity);
+      }
       break;
     default: break;
   }
@@ -869,6 +882,17 @@ static bool sstep_block3(const pfc_mesh* m, const pfc_opts& o, int team_size) {
          d.dim == 3 && d.gN == PFC_S3_N && d.uw == 15 && d.gdir_ok && team_size == 256 && d.n_slices == 4096;
 }
 
+// Two PCG iterations per launch on blocks of a 2D grid (ph_scg2b): single-
+// reduction instances (either precision) on periodic grids whose side is a
+// multiple of 64, with computed columns and entry directions, one row per
+// thread (a team of N^2 / 1024 workgroups of 64 x 16 rows).
+static bool sstep_block2(const pfc_mesh* m, const pfc_opts& o, int team_size) {
+  const MeshDev& d = m->dev;
+  return o.pcg_steps_per_launch == 2 && o.single_reduction == 1 && o.grid_columns == 1 && d.dim == 2 &&
+         d.gN >= 64 && d.gN % 64 == 0 && d.uw == 7 && d.gdir_ok && d.n_slices % PFC_WAVES == 0 &&
+         team_size == d.n_slices / PFC_WAVES;
+}
+
 // Carve the instance arena.  With base == nullptr only the size is computed.
 size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int team_size) {
   size_t off = 0;
@@ -913,7 +937,7 @@ size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int t
   h.part = (double*)take(2 * (size_t)team_size * 4 * sizeof(double));
   h.gpart = (double*)take(2 * (size_t)team_size * PFC_GS_NV * sizeof(double));
   h.sH = sstep_halo(m, o, team_size);
-  h.sstep = h.sH > 0 ? 1 : (sstep_block3(m, o, team_size) ? 2 : 0);
+  h.sstep = sstep_block2(m, o, team_size) ? 3 : (h.sH > 0 ? 1 : (sstep_block3(m, o, team_size) ? 2 : 0));
   h.sbas = h.sstep ? (double*)take(10 * n * 8) : nullptr;
   h.spart = h.sstep ? (double*)take(2 * (size_t)team_size * 32 * sizeof(double)) : nullptr;
   h.st = (State*)take(2 * sizeof(State));
@@ -1023,22 +1047,28 @@ int Group::build(hipStream_t capture, int precision, int ticks) {
     State* sout = nullptr;
     double* pin = nullptr;
     double* pout = nullptr;
+    const double* gin = nullptr;
     if (count == 1) {
       sin = h_descs[0].st + par;
       sout = h_descs[0].st + (1 - par);
       pin = h_descs[0].part + (size_t)par * n_wg * 4;
       pout = h_descs[0].part + (size_t)(1 - par) * n_wg * 4;
+      if (h_descs[0].spart) gin = h_descs[0].spart + (size_t)par * n_wg * 32;
     }
-#define PFC_TICK(TT, SG, LD)                                                                                    \
-  hipLaunchKernelGGL((k_tick<TT, SG, LD>), dim3(n_wg), dim3(PFC_WG), 0, capture, d_teams, d_descs, sin, sout, pin, pout, \
-                     par, pcol, puw, pnsl)
-#define PFC_TICK_COLS(TT, SG)                                      \
-  switch (cols) {                                                  \
-    case PFC_COL_GRID: PFC_TICK(TT, SG, PFC_COL_GRID); break;        \
-    case PFC_COL_LDS: PFC_TICK(TT, SG, PFC_COL_LDS); break;          \
-    default: PFC_TICK(TT, SG, PFC_COL_MEM); break;                   \
+#define PFC_TICK(TT, SG, LD, BB)                                                                              \
+  hipLaunchKernelGGL((k_tick<TT, SG, LD, BB>), dim3(n_wg), dim3(PFC_WG), 0, capture, d_teams, d_descs, sin, sout, pin, \
+                     pout, par, pcol, puw, pnsl, gin)
+#define PFC_TICK_COLS(TT, SG)                                                  \
+  switch (cols) {                                                              \
+    case PFC_COL_GRID:                                                         \
+      if (b2) { PFC_TICK(TT, true, PFC_COL_GRID, true); }                      \
+      else { PFC_TICK(TT, SG, PFC_COL_GRID, false); }                          \
+      break;                                                                   \
+    case PFC_COL_LDS: PFC_TICK(TT, SG, PFC_COL_LDS, false); break;             \
+    default: PFC_TICK(TT, SG, PFC_COL_MEM, false); break;                      \
   }
     const bool sg = (count == 1);
+    const bool b2 = sg && h_descs[0].sstep == 3;  // blocks of a 2D grid (ph_scg2b)
     if (precision == PFC_MIXED) {
       if (sg) { PFC_TICK_COLS(float, true); } else { PFC_TICK_COLS(float, false); }
     } else {

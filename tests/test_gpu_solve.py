@@ -422,8 +422,11 @@ def test_gamma_literal_and_fixed_inner_counts(pfc, dim, N, jit, tau):
 
 # 2D float64 periodic grids: one workgroup smaller than a slice (3^2), one workgroup (16^2, 24^2), several
 # workgroups with a ragged last one (72^2: six workgroups of 896 rows, the last 704), and the halo of
-# N + 1 rows wrapping round the grid in every case
-@pytest.mark.parametrize("N,jit,tau", [(3, 0.2, 0.5), (16, 0.2, 0.1), (24, 0.2, 1.0), (72, 0.2, 1.0)])
+# N + 1 rows wrapping round the grid in every case (ranges of rows); sides that are multiples of 64 take
+# blocks of 64 x 16 rows whose frames wrap round the grid in both directions (64^2: one block column of
+# four blocks; 128^2: 2 x 8 blocks)
+@pytest.mark.parametrize("N,jit,tau", [(3, 0.2, 0.5), (16, 0.2, 0.1), (24, 0.2, 1.0), (72, 0.2, 1.0),
+                                       (64, 0.2, 1.0), (128, 0.2, 0.5)])
 def test_two_pcg_iterations_per_launch(pfc, N, jit, tau):
     """The s-step form (two PCG iterations per launch) against one iteration per launch and the oracle:
     the same inner iteration counts and Arnoldi steps, the same solution to rounding, odd fixed counts
@@ -464,6 +467,52 @@ def test_two_pcg_iterations_per_launch(pfc, N, jit, tau):
         x = dev(np.zeros(3 * n))
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
         assert gi["outer_iters"] == info_f["steps"] and entryerr(host(x), y_fix) <= 1e-10
+    finally:
+        for i in insts:
+            pfc.pfc_instance_destroy(i)
+        P.close()
+
+
+@pytest.mark.parametrize("N", [64, 128])
+def test_two_pcg_iterations_per_launch_2d_blocks_mixed(pfc, N):
+    """Mixed precision (float32 inner PCG) on 2D grids of side a multiple of 64 runs two PCG iterations per
+    launch on blocks of 64 x 16 rows.  With the oracle's inner counts fixed, odd ones included, one P_CH
+    apply in that form reaches the oracle's float64 apply as closely as the one-iteration float32 form
+    (both differ from it by float32 rounding of the inner solves), with fewer launches; a tolerance-mode
+    stage solve reaches the true residual of the tolerance (the oracle's operator) with the same outer
+    iteration count as the one-iteration form."""
+    from oracle import precond
+    P = Problem(2, N, 0.2, seed=13)
+    n = P.n
+    tau, r, psibar = 0.5, -0.35, -0.3
+    tau_s = tau / M11
+    w = np.random.default_rng(5).normal(size=3 * n)
+    insts = []
+    out = {}
+    try:
+        _, b = _stage1(P, r, tau)
+        Nm = assembly.N_matrix(P.mesh, P.psi)
+        for spl in (2, 1):
+            inst = pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(precision=1, pcg_steps_per_launch=spl))
+            insts.append(inst)
+            assert pfc.pfc_instance_config(inst)["pcg_steps_per_launch"] == spl
+            for fixed in ([3, 1, 4, 5, 2], [25, 21, 17, 23, 19]):
+                ref = precond.pch_apply(precond.InnerSolvers(P.M, P.K, tau_s, mode="pcg", fixed_counts=fixed), w)
+                z = dev(np.zeros(3 * n))
+                got = pfc.pfc_apply_pch(inst, n, tau_s, dev(w), z, fixed_counts=fixed)
+                assert list(got) == list(fixed)
+                out[(spl, tuple(fixed))] = (rel(host(z), ref), pfc.pfc_instance_launch_stats(inst)[0])
+            x = dev(np.zeros(3 * n))
+            st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
+            res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, tau, M11, host(x))) / np.linalg.norm(b)
+            assert st == pfc.PFC_OK and res <= 1e-8, (spl, st, res)
+            out[(spl, "solve")] = gi["outer_iters"]
+        for fixed in ([3, 1, 4, 5, 2], [25, 21, 17, 23, 19]):
+            (e2, l2), (e1, l1) = out[(2, tuple(fixed))], out[(1, tuple(fixed))]
+            assert e2 <= max(1e-5, 3.0 * e1), (fixed, e2, e1)
+            if sum(fixed) >= 20:
+                assert l2 < 0.8 * l1, (l2, l1)
+        assert out[(2, "solve")] == out[(1, "solve")]
     finally:
         for i in insts:
             pfc.pfc_instance_destroy(i)
