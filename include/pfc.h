@@ -139,18 +139,21 @@ typedef struct pfc_server pfc_server;
  *                 reduction of their D-weighted Gram matrix, halo rows staged
  *                 in LDS): same iterates and the same stopping decisions as the
  *                 standard iteration in exact arithmetic, and the same count
- *                 of iterations.  It applies in launches that serve the
- *                 instance alone, to single_reduction = 1 instances with
- *                 grid_columns = 1 and rows_per_thread <= 1 on 2D periodic
- *                 grid meshes of side a multiple of 64 (either precision; a
- *                 workgroup's rows are a block of 64 x 16 grid points), other
- *                 2D periodic grid meshes in float64 (a workgroup's rows are a
- *                 range of rows) and 3D periodic grid meshes of side 64 in
- *                 PFC_MIXED (a block of 4 x 4 grid lines); in PFC_MIXED the
- *                 inner iterations run in float32.  Elsewhere, and with 1, one
- *                 iteration per launch.  Results then differ from a launch
- *                 that serves the instance together with others by rounding
- *                 (1 gives the same bits alone and in a batch). */
+ *                 of iterations.  It applies to single_reduction = 1
+ *                 instances with grid_columns = 1 and rows_per_thread <= 1:
+ *                 on 2D periodic grid meshes of side a multiple of 64 in
+ *                 either precision (a workgroup's rows are a block of 64 x 16
+ *                 grid points), also in launches that serve many instances
+ *                 when every instance of the launch qualifies; in launches
+ *                 that serve the instance alone, on other 2D periodic grid
+ *                 meshes in float64 (a workgroup's rows are a range of rows)
+ *                 and on 3D periodic grid meshes of side 64 in PFC_MIXED (a
+ *                 block of 4 x 4 grid lines).  In PFC_MIXED the inner
+ *                 iterations run in float32.  Elsewhere, and with 1, one
+ *                 iteration per launch.  Results of the two forms differ by
+ *                 rounding: an instance gives the same bits alone and in a
+ *                 batch with 1, and with 2 where both launches take the block
+ *                 form. */
 typedef struct pfc_opts {
     int struct_size;
     int precision;
@@ -339,7 +342,8 @@ int pfc_instance_launch_stats(const pfc_instance* inst, long long* launches, lon
  * see pcg_steps_per_launch, else 1) and whether the solver kernel computes the
  * mesh's columns from the row (1) or reads them (0).  In a launch that serves
  * several instances (batches, the server) every instance runs one PCG
- * iteration per launch. */
+ * iteration per launch, unless every instance of the launch takes the 2D block
+ * form (see pcg_steps_per_launch). */
 int pfc_instance_config(const pfc_instance* inst, int* team_size, int* rows_per_thread, int* pcg_steps_per_launch,
                         int* grid_columns);
 
@@ -439,7 +443,7 @@ int pfc_batch_run(pfc_instance* const* insts, int count, double* const* states,
 
 /* ---- autotuning -------------------------------------------------------------
  * The launch configuration of the solver kernel (rows per thread, launches per
- * captured graph, PCG iterations per launch of a lone instance, computed or
+ * captured graph, PCG iterations per launch (one row per thread), computed or
  * read grid columns, stored or on-the-fly M + c K operators) is chosen by
  * measurement: pfc_autotune times one Rosenbrock step of `count` instances of
  * a mesh on synthetic states (psi = -0.3 + U[-0.01, 0.01] from a counter-based

@@ -462,10 +462,11 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   __shared__ double hbuf[PFC_MAXM];          // Gram-Schmidt coefficients of the current Arnoldi step
   __shared__ double gs_g[PFC_GS_NV];         // Gram sums of the step (after PH_ASPMV)
   __shared__ double gs_L[PFC_MAXM * PFC_MAXM];
-  // two PCG iterations per launch in launches that serve one instance on a
-  // periodic grid: blocks of a 2D grid (B2, either precision), else row ranges
-  // of a 2D grid in float64 and blocks of a 3D grid of side 64 in float
-  constexpr bool SB2 = B2 && SINGLE && COLS == PFC_COL_GRID;
+  // two PCG iterations per launch on periodic grids: blocks of 2D grids (B2,
+  // either precision, launches that serve one or many instances), and in
+  // launches that serve one instance row ranges of 2D grids in float64 and
+  // blocks of 3D grids of side 64 in float
+  constexpr bool SB2 = B2 && COLS == PFC_COL_GRID;
   constexpr bool SS = SINGLE && COLS == PFC_COL_GRID && std::is_same<T, double>::value && !B2;
   constexpr bool SS3 = SINGLE && COLS == PFC_COL_GRID && std::is_same<T, float>::value && !B2;
   constexpr bool SSX = SS || SS3 || SB2;
@@ -501,7 +502,7 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   static_assert(NS <= 64 && ND <= PFC_WG - 64, "state / descriptor too large for the staging threads");
   const int word = tid < 64 ? ((const int*)st_in)[min(tid, NS - 1)] : ((const int*)gI)[min(tid - 64, ND - 1)];
   double gpl[SSX ? PFC_SS_GL : 1];
-  if constexpr (SSX) ss_gram_prefetch(gram_in_arg, part_in, te.size, gpl);
+  if constexpr (SSX && SINGLE) ss_gram_prefetch(gram_in_arg, part_in, te.size, gpl);
   // columns of this workgroup's slices: positions [lo, lo + len) of the SELL
   // pattern, issued first and written to LDS once everything has arrived
   int lo = 0, len = 0;
@@ -561,11 +562,15 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     // launches after a two-iteration launch, or after the set-up that formed the first basis
     scg = S.phase == PH_SCG_ITER || (S.phase == PH_PCG_SETUP && I.sstep && scg_kind(S.kind));
     if (scg && !(S.phase == PH_SCG_ITER && S.pcur)) {
+      // the previous launch's Gram partials: loaded in the prologue where the
+      // launch serves one instance, else here from the instance's buffer
+      const double* gin = SINGLE ? gram_in_arg : I.spart + (long long)parity * te.size * 32;
+      if constexpr (!SINGLE) ss_gram_prefetch(gin, gin, te.size, gpl);
       // in flight during the reduction and the transition
       if constexpr (SB2) b2_load<T>(I, te.rank, b2p, parity);
       else if constexpr (SS) ss_load(I, S, ss_rows(I, te.rank, te.size), ssp, parity);
       else s3_load<float>(I, S, te.rank, s3p, parity);
-      ss_gram(gram_in_arg, te.size, gpl, ss_g);
+      ss_gram(gin, te.size, gpl, ss_g);
 #ifdef PFC_TICK_TIMING
       if (tid == 0) pfc_sst[4] = wall_clock64();
 #endif
@@ -1061,14 +1066,15 @@ int Group::build(hipStream_t capture, int precision, int ticks) {
 #define PFC_TICK_COLS(TT, SG)                                                  \
   switch (cols) {                                                              \
     case PFC_COL_GRID:                                                         \
-      if (b2) { PFC_TICK(TT, true, PFC_COL_GRID, true); }                      \
+      if (b2) { PFC_TICK(TT, SG, PFC_COL_GRID, true); }                        \
       else { PFC_TICK(TT, SG, PFC_COL_GRID, false); }                          \
       break;                                                                   \
     case PFC_COL_LDS: PFC_TICK(TT, SG, PFC_COL_LDS, false); break;             \
     default: PFC_TICK(TT, SG, PFC_COL_MEM, false); break;                      \
   }
     const bool sg = (count == 1);
-    const bool b2 = sg && h_descs[0].sstep == 3;  // blocks of a 2D grid (ph_scg2b)
+    bool b2 = true;  // every instance runs two PCG iterations per launch on blocks of a 2D grid (ph_scg2b)
+    for (int i = 0; i < count; ++i) b2 = b2 && h_descs[i].sstep == 3;
     if (precision == PFC_MIXED) {
       if (sg) { PFC_TICK_COLS(float, true); } else { PFC_TICK_COLS(float, false); }
     } else {

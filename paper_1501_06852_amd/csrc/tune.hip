@@ -268,7 +268,8 @@ int tune_search(pfc_mesh* const* ms, int n_meshes, int precision, int count, hip
   if (!mix) {  // a mix is tuned for the server, whose instances keep the other defaults
     if (!status && grid) axis([](Candidate& c, int v) { c.grid = v; }, {1, 0});
     if (!status && count > 1) axis([](Candidate& c, int v) { c.shared = v; }, {0, 1});
-    if (!status && count == 1) axis([](Candidate& c, int v) { c.pcg = v; }, {2, 1});
+    // the two-iteration form needs one row per thread
+    if (!status && best.rpt <= 1) axis([](Candidate& c, int v) { c.pcg = v; }, {2, 1});
     if (!status) axis([](Candidate& c, int v) { c.ticks = v; }, {32, 64, 128});
   }
   if (status) return status;

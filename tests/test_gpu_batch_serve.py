@@ -69,6 +69,60 @@ def test_batch_alone_equals_mix(pfc, prec):
             P.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_2d_blocks_alone_equals_batch(pfc, prec):
+    """Instances on 2D grids of side a multiple of 64 run two PCG iterations per launch on blocks of 64 x 16
+    rows in a batch as alone (default options): the batch gives each instance the bits it has alone and the
+    step of the one-iteration form to the accuracy of two solves at relative residual 1e-8, and float64
+    instances land on the oracle's Rosenbrock step to that accuracy."""
+    probs = [Problem(2, 64, 0.2, seed=21), Problem(2, 128, 0.0, seed=22)]
+    prm = wl.draw_params(3, 300)
+    owners = [0, 0, 1]
+    insts, states, alone = [], [], []
+    try:
+        steps = 1
+        for k, pi in enumerate(owners):
+            P = probs[pi]
+            insts.append(pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(precision=prec)))
+            assert pfc.pfc_instance_config(insts[-1])["pcg_steps_per_launch"] == 2
+            psi = wl.psi0(P.n, prm[k].psibar, 0.01, seed=prm[k].seed)
+            s0 = np.concatenate([np.zeros(P.n), psi, np.zeros(P.n)])
+            states.append(dev(s0))
+            sa = dev(s0)
+            st, _ = pfc.pfc_rosenbrock_run(insts[-1], P.n, sa, prm[k].r, prm[k].psibar, prm[k].tau, steps)
+            assert st == pfc.PFC_OK
+            alone.append(host(sa))
+        ns = [probs[pi].n for pi in owners]
+        args = ([p.r for p in prm], [p.psibar for p in prm], [p.tau for p in prm])
+        st, infos = pfc.pfc_batch_run(insts, ns, states, *args, steps)
+        assert st >= 0
+        for k in range(3):
+            assert np.array_equal(host(states[k]), alone[k]), k
+            assert all(i["true_rel_res"] <= 1e-8 for i in infos[k])
+        # the same batch with one PCG iteration per launch: the same step to the solves' accuracy
+        one = [pfc.pfc_instance_create(probs[pi].gpu_mesh(), pfc.pfc_opts_default(precision=prec, pcg_steps_per_launch=1))
+               for pi in owners]
+        insts += one
+        st1 = [dev(np.concatenate([np.zeros(probs[pi].n), wl.psi0(probs[pi].n, prm[k].psibar, 0.01, seed=prm[k].seed),
+                                   np.zeros(probs[pi].n)])) for k, pi in enumerate(owners)]
+        st, _ = pfc.pfc_batch_run(one, ns, st1, *args, steps)
+        assert st >= 0
+        for k in range(3):
+            assert rel(host(st1[k]), host(states[k])) <= 1e-6, k
+        if prec == 0:
+            for k, pi in enumerate(owners):
+                P = probs[pi]
+                psi = wl.psi0(P.n, prm[k].psibar, 0.01, seed=prm[k].seed)
+                x0 = opfc.consistent_init(P.mesh, P.M, P.K, prm[k].r, psi)
+                xr, _ = osolve.rosenbrock_run(P.mesh, P.M, P.K, x0, prm[k].r, prm[k].tau, steps, tol=1e-8)
+                assert rel(host(states[k]), xr) <= 1e-6, k
+    finally:
+        for i in insts:
+            pfc.pfc_instance_destroy(i)
+        for P in probs:
+            P.close()
+
+
 def _serve(pfc, meshes, reqs, prec, slots, budget, steps=2, rpt=0):
     import ctypes as C
     so = pfc.pfc_server_opts(C.sizeof(pfc.pfc_server_opts), prec, budget, slots, 0, rpt)
