@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # was taken on: when their digest differs, `traffic` is reported as null.
 TRAFFIC = {
     # workload: (sha256 of the kernel sources, bytes per launch, algorithmic bytes per launch of the same run)
-    "pfc2d_512_fp64": ("9d291b9d1a3157b0a8f9a8409ab70c26403d511b91a5f4edc91288af4b900148", 42997952.0, 78820966.0),
-    "pfc3d_64_mixed": ("9d291b9d1a3157b0a8f9a8409ab70c26403d511b91a5f4edc91288af4b900148", 41698443.0, 71753338.0),
+    "pfc2d_512_fp64": ("2d443438c7fdbd19e13255bee1748fe4cb36819bfca7d73e770b2d81bd91a9c7", 42890054.0, 78820966.0),
+    "pfc3d_64_mixed": ("2d443438c7fdbd19e13255bee1748fe4cb36819bfca7d73e770b2d81bd91a9c7", 41880864.0, 71753338.0),
 }
 
 

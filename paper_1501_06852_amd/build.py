@@ -17,11 +17,17 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+# the instrumented build for phase_probe.py: wall-clock stamps of each solver launch (PFC_TICK_TIMING)
+LIB_TIMING = os.path.join(HERE, "libpfc_timing.so")
+
+
+def build(verbose: bool = False, timing: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, "-I", os.path.join(HERE, "..", "include"), "-o", tmp, *srcs, "-lpthread"]
+    lib = LIB_TIMING if timing else LIB
+    tmp = lib + ".tmp"
+    extra = ["-DPFC_TICK_TIMING"] if timing else []
+    cmd = [hipcc, *FLAGS, *extra, "-I", os.path.join(HERE, "..", "include"), "-o", tmp, *srcs, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -30,10 +36,9 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed:\n" + out)
     if verbose and out.strip():
         print(out)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
-    print(LIB)
+    print(build(verbose="-v" in sys.argv, timing="--timing" in sys.argv))

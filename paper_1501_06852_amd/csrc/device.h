@@ -1405,6 +1405,18 @@ __device__ __forceinline__ void ph_scg3(const InstDev& I, const State& S, const 
     vst(o.x + og, T((double)xo + (coef[0] * p + coef[1] * tp + coef[3] * u)));
     return;
   }
+  // operator rows of the one-step frame, issued before the new p and u are
+  // formed (whose basis loads they wait for) and in flight across the barrier
+  T av[2][W15], dv[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int q1 = tid + c * PFC_WG, t1 = q1 >> 6;
+    const int g = s3_row(G, q1 & 63, t1 % 6 - 1, t1 / 6 - 1);
+    const int base = (g >> 6) * 64 * W15 + (g & 63);
+#pragma unroll
+    for (int k = 0; k < W15; ++k) av[c][k] = opval_g(o, (long long)base + k * 64);
+    dv[c] = gld(o.dinv + g);
+  }
   // new p on the two-step frame, new u on the one-step frame
 #pragma unroll
   for (int c = 0; c < PFC_SS_NA; ++c) {
@@ -1421,17 +1433,6 @@ __device__ __forceinline__ void ph_scg3(const InstDev& I, const State& S, const 
     sp[q] = pn;
     const int ly = (q >> 6) & 7, lz = q >> 9;
     if (ly >= 1 && ly < 7 && lz >= 1 && lz < 7) su[(q & 63) + 64 * ((ly - 1) + 6 * (lz - 1))] = un;
-  }
-  // operator rows of the one-step frame, in flight across the barrier
-  T av[2][W15], dv[2];
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const int q1 = tid + c * PFC_WG, t1 = q1 >> 6;
-    const int g = s3_row(G, q1 & 63, t1 % 6 - 1, t1 / 6 - 1);
-    const int base = (g >> 6) * 64 * W15 + (g & 63);
-#pragma unroll
-    for (int k = 0; k < W15; ++k) av[c][k] = opval_g(o, (long long)base + k * 64);
-    dv[c] = gld(o.dinv + g);
   }
   lds_barrier();
   // T p on the one-step frame
@@ -1654,6 +1655,19 @@ __device__ __forceinline__ void ph_scg2b(const InstDev& I, const State& S, const
     vst(o.x + og, T((double)xo + (coef[0] * p + coef[1] * tp + coef[3] * u)));
     return;
   }
+  // operator rows of the one-step frame (the second pass covers 164 rows),
+  // issued before the new p and u are formed (whose basis loads they wait for)
+  // and in flight across the barrier
+  T av[2][W7], dv[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int q1 = min(tid + c * PFC_WG, PFC_B2_N1 - 1);
+    const int g = b2_row(G, q1 % PFC_B2_W1 - 1, q1 / PFC_B2_W1 - 1);
+    const int base = (g >> 6) * 64 * W7 + (g & 63);
+#pragma unroll
+    for (int k = 0; k < W7; ++k) av[c][k] = opval_g(o, (long long)base + k * 64);
+    dv[c] = gld(o.dinv + g);
+  }
   // new p on the two-step frame, new u on the one-step frame
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
@@ -1673,19 +1687,8 @@ __device__ __forceinline__ void ph_scg2b(const InstDev& I, const State& S, const
       if (fx >= -1 && fx < 65 && fy >= -1 && fy < 17) su[(fx + 1) + PFC_B2_W1 * (fy + 1)] = un;
     }
   }
-  // operator rows of the one-step frame (the second pass covers 164 rows), in
-  // flight across the barrier
-  T av[2][W7], dv[2];
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const int q1 = min(tid + c * PFC_WG, PFC_B2_N1 - 1);
-    const int g = b2_row(G, q1 % PFC_B2_W1 - 1, q1 / PFC_B2_W1 - 1);
-    const int base = (g >> 6) * 64 * W7 + (g & 63);
-#pragma unroll
-    for (int k = 0; k < W7; ++k) av[c][k] = opval_g(o, (long long)base + k * 64);
-    dv[c] = gld(o.dinv + g);
-  }
   lds_barrier();
+  PFC_SS_STAMP(0);
   // T p on the one-step frame
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
@@ -1707,6 +1710,7 @@ __device__ __forceinline__ void ph_scg2b(const InstDev& I, const State& S, const
   for (int k = 0; k < W7; ++k) ao[k] = opval_g(o, (long long)obase + k * 64);
   const T odi = gld(o.dinv + og);
   lds_barrier();
+  PFC_SS_STAMP(1);
   // own row: T u, T^2 p, the stores and the Gram products
   const unsigned char* gd = gdir + b2_class(G, ox, oy) * PFC_GRID_W;
   const int o1 = (ox + 1) + PFC_B2_W1 * (oy + 1), o2 = (ox + 2) + PFC_B2_W2 * (oy + 2);
@@ -1766,6 +1770,7 @@ __device__ __forceinline__ void ph_scg2b(const InstDev& I, const State& S, const
     }
   }
   gp[25] = bbo;
+  PFC_SS_STAMP(2);
   // workgroup sums as ph_scg: each wave by recursive halving, then over the waves
   const int lane = tid & 63, wave = tid >> 6;
   {
@@ -1783,6 +1788,7 @@ __device__ __forceinline__ void ph_scg2b(const InstDev& I, const State& S, const
     for (int w = 0; w < PFC_WAVES; ++w) t += pfc_ssred[w * 32 + tid];
     vst(spart_out + (long long)tm.rank * 32 + tid, t);
   }
+  PFC_SS_STAMP(3);
 }
 
 // ---- orthogonalisation of an Arnoldi step (one reduction) ----------------------

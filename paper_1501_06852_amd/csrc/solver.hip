@@ -580,7 +580,7 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     if (scg) {
       if constexpr (SSX) scg_transition(S, I, writer, ss_g, ss_coef);
 #ifdef PFC_TICK_TIMING
-      if constexpr (SS) pfc_sst[5] = wall_clock64();
+      if constexpr (SSX) pfc_sst[5] = wall_clock64();
 #endif
     } else {
       Red3 red = red3(0.0, 0.0, 0.0);
@@ -677,7 +677,7 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
       r[0] = (unsigned long long)S.phase | ((unsigned long long)te.rank << 8) | ((unsigned long long)S.kind << 40) |
              ((unsigned long long)(S.it & 0xffff) << 48);
       r[1] = t_entry; r[2] = t_ld; r[3] = t_trans; r[4] = t_work; r[5] = t_exit; r[6] = blockIdx.x; r[7] = t_red;
-      for (int q = 0; q < 6; ++q) r[8 + q] = (SS && (fused || S.phase == PH_SCG_ITER)) ? pfc_sst[q] : 0;
+      for (int q = 0; q < 6; ++q) r[8 + q] = (SSX && (fused || S.phase == PH_SCG_ITER)) ? pfc_sst[q] : 0;
     }
   }
 #endif

@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpfc.so")
+# PFC_LIBRARY selects another build of the library (the instrumented one of phase_probe.py)
+LIB_PATH = os.environ.get("PFC_LIBRARY") or os.path.join(_HERE, "libpfc.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1501_06852_amd.build` (or __graft_entry__.build())")
