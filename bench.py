@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # was taken on: when their digest differs, `traffic` is reported as null.
 TRAFFIC = {
     # workload: (sha256 of the kernel sources, bytes per launch, algorithmic bytes per launch of the same run)
-    "pfc2d_512_fp64": ("2d443438c7fdbd19e13255bee1748fe4cb36819bfca7d73e770b2d81bd91a9c7", 42890054.0, 78820966.0),
-    "pfc3d_64_mixed": ("2d443438c7fdbd19e13255bee1748fe4cb36819bfca7d73e770b2d81bd91a9c7", 41880864.0, 71753338.0),
+    "pfc2d_512_fp64": ("0a53c532af651681d572c5837747515603fda5e068f8ad74fd5d5d04fa75ee06", 42716124.0, 78820966.0),
+    "pfc3d_64_mixed": ("0a53c532af651681d572c5837747515603fda5e068f8ad74fd5d5d04fa75ee06", 41894271.0, 71753338.0),
 }
 
 
