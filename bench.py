@@ -630,6 +630,7 @@ def main():
         "status": pfc.pfc_status_str(st),
         "max_true_rel_res": max(res) if res else None,
         "outer_iters_mean": float(np.mean([i["outer_iters"] for i in infos])),
+        "t_solve_mean_ms": float(np.mean([i["t_solve"] for i in infos])) * 1e3,   # device clock, per stage solve
         "inner_pcg_per_apply_mean": float(np.mean([i["inner_total"] / max(1, i["inner_applies"]) for i in infos])),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

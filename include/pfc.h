@@ -185,7 +185,10 @@ typedef struct pfc_opts {
  *   inner_total   PCG iterations summed over all applications and steps
  *   inner_max     largest PCG count seen in each of the five steps (1, 2, 3.1, 3.2, 5)
  *   est_rel_res   last Givens estimate |g_{k}| / ||b_scaled||
- *   true_rel_res  ||b - A^R x||_2 / ||b||_2 recomputed in float64 */
+ *   true_rel_res  ||b - A^R x||_2 / ||b||_2 recomputed in float64
+ *   t_solve       seconds of device time from the solve's first launch to its
+ *                 last (the device's constant 100 MHz clock; in a batch or a
+ *                 served mix the launches are shared with the other solves) */
 typedef struct pfc_solve_info {
     int status;
     int outer_iters;
@@ -196,6 +199,7 @@ typedef struct pfc_solve_info {
     int reserved;
     double est_rel_res;
     double true_rel_res;
+    double t_solve;
 } pfc_solve_info;
 
 /* Recorded iteration structure of one FGMRES solve, for replay: the length
@@ -264,6 +268,15 @@ int pfc_mesh_create_p2(int dim, int n, int n_elem, const int32_t* elem_nodes,
 int pfc_mesh_create_csr(int dim, int n, int nnz, const int32_t* row_ptr, const int32_t* col_idx,
                         const double* M_val, const double* K_val, int n_elem,
                         const int32_t* elem_nodes, const double* elem_vol, pfc_mesh** out);
+
+/* pfc_mesh_create_csr_device: the same with every array in device memory
+ * (row_ptr, col_idx, M_val, K_val, elem_nodes, elem_vol: device pointers of
+ * the sizes above).  The arrays are copied to the host for the validation of
+ * pfc_mesh_create_csr (synchronously, on the null stream); PFC_ERR_HIP if a
+ * pointer is not readable device memory. */
+int pfc_mesh_create_csr_device(int dim, int n, int nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                               const double* M_val, const double* K_val, int n_elem,
+                               const int32_t* elem_nodes, const double* elem_vol, pfc_mesh** out);
 
 /* Sizes of a mesh; any pointer may be NULL. */
 int pfc_mesh_query(const pfc_mesh* mesh, int* dim, int* n, int* nnz, int* n_elem);

@@ -869,6 +869,41 @@ int pfc_mesh_create_csr(int dim, int n, int nnz, const int32_t* row_ptr, const i
   return PFC_OK;
 }
 
+// The arrays are in device memory: copy them to the host and validate and lay
+// them out as pfc_mesh_create_csr does (mesh set-up, once per mesh).
+int pfc_mesh_create_csr_device(int dim, int n, int nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                               const double* M_val, const double* K_val, int n_elem, const int32_t* elem_nodes,
+                               const double* elem_vol, pfc_mesh** out) {
+  if (!out || !row_ptr || !col_idx || !M_val || !K_val || !elem_nodes || !elem_vol || (dim != 2 && dim != 3) ||
+      n <= 0 || nnz <= 0 || n_elem <= 0 || n_elem > (1 << 26)) {
+    set_error("pfc_mesh_create_csr_device: invalid arguments");
+    return PFC_ERR_ARG;
+  }
+  *out = nullptr;
+  const void* ptrs[6] = {row_ptr, col_idx, M_val, K_val, elem_nodes, elem_vol};
+  for (const void* p : ptrs) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess || (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)) {
+      (void)hipGetLastError();
+      set_error("pfc_mesh_create_csr_device: an array is not in device memory");
+      return PFC_ERR_ARG;
+    }
+  }
+  std::vector<int32_t> rp((size_t)n + 1), ci((size_t)nnz), en((size_t)n_elem * (dim + 1));
+  std::vector<double> mv((size_t)nnz), kv((size_t)nnz), ev((size_t)n_elem);
+  auto get = [](void* dst, const void* src, size_t bytes) {
+    return hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost) == hipSuccess;
+  };
+  if (!get(rp.data(), row_ptr, rp.size() * 4) || !get(ci.data(), col_idx, ci.size() * 4) ||
+      !get(mv.data(), M_val, mv.size() * 8) || !get(kv.data(), K_val, kv.size() * 8) ||
+      !get(en.data(), elem_nodes, en.size() * 4) || !get(ev.data(), elem_vol, ev.size() * 8)) {
+    (void)hipGetLastError();
+    set_error("pfc_mesh_create_csr_device: copy from device memory failed");
+    return PFC_ERR_HIP;
+  }
+  return pfc_mesh_create_csr(dim, n, nnz, rp.data(), ci.data(), mv.data(), kv.data(), n_elem, en.data(), ev.data(), out);
+}
+
 int pfc_mesh_query(const pfc_mesh* m, int* dim, int* n, int* nnz, int* n_elem) {
   if (!m) { set_error("pfc_mesh_query: null mesh"); return PFC_ERR_ARG; }
   if (dim) *dim = m->dim;

@@ -130,6 +130,7 @@ struct State {
   int status, cur;
   double rho, bb, alpha, beta_cg;
   double vscale, bnorm, bnorm_s, est_thresh, w0, est, rel;
+  long long t0;             // device clock at the solve's first launch
 };
 
 // Single-buffered FGMRES history of the current cycle.  Every entry is
@@ -153,6 +154,7 @@ struct InfoDev {
   int inner_max[5];
   int reserved;
   double est_rel_res, true_rel_res;
+  double t_solve;  // seconds of the device clock (100 MHz) from the solve's first launch to its last
 };
 
 struct InstDev {

@@ -164,11 +164,7 @@ int retire(pfc_server* S, Request* q) {
   PFC_HIP(hipMemcpy(&fin, I->h.st, sizeof(State), hipMemcpyDeviceToHost));
   int worst = fin.status < 0 ? fin.status : PFC_OK;
   for (size_t k = 0; k < f.size(); ++k) {
-    pfc_solve_info& d = q->infos_out[k];
-    d.status = f[k].status; d.outer_iters = f[k].outer_iters; d.cycles = f[k].cycles;
-    d.inner_applies = f[k].inner_applies; d.inner_total = f[k].inner_total;
-    for (int c = 0; c < 5; ++c) d.inner_max[c] = f[k].inner_max[c];
-    d.est_rel_res = f[k].est_rel_res; d.true_rel_res = f[k].true_rel_res;
+    fill_info(&q->infos_out[k], f[k]);
     if (f[k].status < 0) worst = f[k].status;
     else if (worst >= 0 && f[k].status > worst) worst = f[k].status;
   }

@@ -37,6 +37,8 @@ int prep_ops_public(pfc_instance* I, hipStream_t s);
 // `count` instances of a mesh; rows per thread for `count` instances of a mix
 int tuned_ticks(const pfc_mesh* m, int precision, int count);
 int tuned_mix_rows_per_thread(int precision, int count);
+// public result record of a solve from the device's record
+void fill_info(pfc_solve_info* dst, const InfoDev& s);
 
 }  // namespace pfc
 

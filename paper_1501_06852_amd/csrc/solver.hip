@@ -71,6 +71,7 @@ __device__ void finish_solve(State& S, const InstDev& I, bool wr, int status) {
       for (int k = 0; k < 5; ++k) f.inner_max[k] = I.hist->inner_max[k];
       f.est_rel_res = S.est;
       f.true_rel_res = S.rel;
+      f.t_solve = (double)((long long)wall_clock64() - S.t0) * 1e-8;
     }
   }
   if (status < 0) S.status = status;
@@ -590,6 +591,7 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
       }
       if (S.phase == PH_ASPMV) gs_coefficients(S, I, writer, gs_g, gs_L, hbuf);
       else if (!cg_iter_continues(S, I, red)) transition(S, I, writer, red, ybuf, gcol, SS && I.sstep);
+      if (S.phase == PH_SOLVE_INIT || S.phase == PH_RB_RHS) S.t0 = (long long)wall_clock64();  // a solve starts
     }
   }
   if constexpr (SSX) {
@@ -989,7 +991,7 @@ static int validate_opts(const pfc_opts* o) {
   return PFC_OK;
 }
 
-static void fill_info(pfc_solve_info* dst, const InfoDev& s) {
+void fill_info(pfc_solve_info* dst, const InfoDev& s) {
   dst->status = s.status;
   dst->outer_iters = s.outer_iters;
   dst->cycles = s.cycles;
@@ -999,6 +1001,7 @@ static void fill_info(pfc_solve_info* dst, const InfoDev& s) {
   dst->reserved = 0;
   dst->est_rel_res = s.est_rel_res;
   dst->true_rel_res = s.true_rel_res;
+  dst->t_solve = s.t_solve;
 }
 
 // The descriptors (h_descs) must be filled before build(): a one-instance

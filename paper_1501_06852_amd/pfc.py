@@ -62,12 +62,13 @@ class pfc_opts(C.Structure):
 class pfc_solve_info(C.Structure):
     _fields_ = [("status", C.c_int), ("outer_iters", C.c_int), ("cycles", C.c_int), ("inner_applies", C.c_int),
                 ("inner_total", C.c_longlong), ("inner_max", C.c_int * 5), ("reserved", C.c_int),
-                ("est_rel_res", C.c_double), ("true_rel_res", C.c_double)]
+                ("est_rel_res", C.c_double), ("true_rel_res", C.c_double), ("t_solve", C.c_double)]
 
     def as_dict(self):
         return dict(status=self.status, outer_iters=self.outer_iters, cycles=self.cycles,
                     inner_applies=self.inner_applies, inner_total=int(self.inner_total),
-                    inner_max=list(self.inner_max), est_rel_res=self.est_rel_res, true_rel_res=self.true_rel_res)
+                    inner_max=list(self.inner_max), est_rel_res=self.est_rel_res, true_rel_res=self.true_rel_res,
+                    t_solve=self.t_solve)
 
 
 class pfc_schedule(C.Structure):
@@ -121,6 +122,8 @@ _sig("pfc_tau_critical", C.c_double, [C.c_double, C.c_double])
 _sig("pfc_mesh_create_p1", C.c_int, [C.c_int, C.c_int, C.c_int, _ip, _dp, C.POINTER(_vp)])
 _sig("pfc_mesh_create_p2", C.c_int, [C.c_int, C.c_int, C.c_int, _ip, _dp, C.POINTER(_vp)])
 _sig("pfc_mesh_create_csr", C.c_int, [C.c_int, C.c_int, C.c_int, _ip, _ip, _dp, _dp, C.c_int, _ip, _dp, C.POINTER(_vp)])
+_sig("pfc_mesh_create_csr_device", C.c_int, [C.c_int, C.c_int, C.c_int, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp,
+                                              C.POINTER(_vp)])
 _sig("pfc_mesh_query", C.c_int, [_vp, _ip, _ip, _ip, _ip])
 _sig("pfc_mesh_grid_side", C.c_int, [_vp, _ip])
 _sig("pfc_mesh_export_csr", C.c_int, [_vp, _ip, _ip, _dp, _dp])
@@ -167,7 +170,7 @@ _sig("pfc_server_destroy", None, [_vp])
 # every symbol declared in include/pfc.h
 DECLARED = [
     "pfc_status_str", "pfc_last_error", "pfc_opts_default", "pfc_tau_critical", "pfc_mesh_create_p1", "pfc_mesh_create_p2",
-    "pfc_mesh_create_csr", "pfc_mesh_query", "pfc_mesh_grid_side", "pfc_mesh_export_csr", "pfc_mesh_destroy", "pfc_spmv",
+    "pfc_mesh_create_csr", "pfc_mesh_create_csr_device", "pfc_mesh_query", "pfc_mesh_grid_side", "pfc_mesh_export_csr", "pfc_mesh_destroy", "pfc_spmv",
     "pfc_assemble_N", "pfc_load_psi3", "pfc_instance_footprint", "pfc_instance_create", "pfc_instance_destroy",
     "pfc_solve", "pfc_solve_x", "pfc_last_inner_counts", "pfc_instance_launch_stats", "pfc_instance_config",
     "pfc_rosenbrock_run",
@@ -283,6 +286,26 @@ def pfc_mesh_create_csr(dim, n, row_ptr, col_idx, M_val, K_val, elem_nodes, elem
     h = _vp()
     _check(_lib.pfc_mesh_create_csr(dim, n, ci.size, prp, pci, pmv, pkv, ev.size, pen, pev, C.byref(h)),
            "pfc_mesh_create_csr")
+    return h
+
+
+def _dev_any(t, dtype, name):
+    """Device pointer of a contiguous torch tensor of `dtype` on the GPU."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor on the GPU")
+    return _vp(t.data_ptr())
+
+
+def pfc_mesh_create_csr_device(dim, n, row_ptr, col_idx, M_val, K_val, elem_nodes, elem_vol):
+    """As pfc_mesh_create_csr with every array a torch tensor on the GPU (int32 indices, float64 values)."""
+    import torch
+    args = [_dev_any(row_ptr, torch.int32, "row_ptr"), _dev_any(col_idx, torch.int32, "col_idx"),
+            _dev_any(M_val, torch.float64, "M_val"), _dev_any(K_val, torch.float64, "K_val")]
+    en, ev = _dev_any(elem_nodes, torch.int32, "elem_nodes"), _dev_any(elem_vol, torch.float64, "elem_vol")
+    h = _vp()
+    _check(_lib.pfc_mesh_create_csr_device(dim, n, col_idx.numel(), *args, elem_vol.numel(), en, ev, C.byref(h)),
+           "pfc_mesh_create_csr_device")
     return h
 
 

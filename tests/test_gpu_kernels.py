@@ -139,6 +139,28 @@ def test_mesh_from_csr_equals_p1_assembly(pfc):
         pfc.pfc_solve(i1, n, dev(P.psi), r, -0.3, tau, m11, dev(b), x1)
         pfc.pfc_solve(i2, n, dev(P.psi), r, -0.3, tau, m11, dev(b), x2)
         assert entryerr(host(x1), host(x2)) <= 1e-10
+        # the same arrays in device memory give the same mesh; host arrays are refused there
+        import torch
+        dv = torch.device("cuda:0")
+        ti = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.int32), device=dv)  # noqa: E731
+        td = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device=dv)  # noqa: E731
+        h3 = pfc.pfc_mesh_create_csr_device(2, P.n, ti(P.M.indptr), ti(P.M.indices), td(P.M.data), td(P.K.data),
+                                            ti(P.mesh.elem_nodes), td(vol))
+        try:
+            rp3, ci3, mv3, kv3 = pfc.pfc_mesh_export_csr(h3)
+            assert np.array_equal(rp3, rp) and np.array_equal(ci3, ci)
+            assert np.array_equal(mv3, mv) and np.array_equal(kv3, kv)
+        finally:
+            pfc.pfc_mesh_destroy(h3)
+        import ctypes as C
+        hp = np.ascontiguousarray(P.M.indptr, dtype=np.int32)
+        out = C.c_void_p()
+        rc = pfc._lib.pfc_mesh_create_csr_device(2, P.n, P.M.indices.size, C.c_void_p(hp.ctypes.data),
+                                                 C.c_void_p(ti(P.M.indices).data_ptr()), C.c_void_p(td(P.M.data).data_ptr()),
+                                                 C.c_void_p(td(P.K.data).data_ptr()), vol.size,
+                                                 C.c_void_p(ti(P.mesh.elem_nodes).data_ptr()),
+                                                 C.c_void_p(td(vol).data_ptr()), C.byref(out))
+        assert rc == pfc.PFC_ERR_ARG and not out.value
         # invalid CSR: a node pair of an element missing from the pattern
         rp_bad = P.M.indptr.copy()
         with pytest.raises(pfc.PFCError):

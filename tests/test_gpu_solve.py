@@ -96,11 +96,16 @@ def test_solve_tolerance_mode(pfc, dim, N, jit, tau, prec):
         _, b = _stage1(P, r, tau)
         Nm = assembly.N_matrix(P.mesh, P.psi)
         x = dev(np.zeros(3 * n))
+        import time
+        t0 = time.perf_counter()
         st, gi = pfc.pfc_solve(inst, n, dev(P.psi), r, psibar, tau, M11, dev(b), x)
+        wall = time.perf_counter() - t0
         y = host(x)
         res = np.linalg.norm(b - opfc.apply_AR(P.M, P.K, Nm, r, tau, M11, y)) / np.linalg.norm(b)
         assert st == pfc.PFC_OK and res <= 1e-8, (st, res, gi)
         assert abs(gi["true_rel_res"] - res) <= 1e-3 * res + 1e-15
+        # the solve's device time lies within the call's wall time
+        assert 0.0 < gi["t_solve"] < wall, (gi["t_solve"], wall)
         y_t, _ = osolve.solve_stage(P.M, P.K, Nm, r, tau, M11, b, tol=1e-13)
         fwd = rel(y, y_t)
         y64, i64 = osolve.solve_stage(P.M, P.K, Nm, r, tau, M11, b, tol=1e-8)
