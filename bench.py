@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # was taken on: when their digest differs, `traffic` is reported as null.
 TRAFFIC = {
     # workload: (sha256 of the kernel sources, bytes per launch, algorithmic bytes per launch of the same run)
-    "pfc2d_512_fp64": ("0a53c532af651681d572c5837747515603fda5e068f8ad74fd5d5d04fa75ee06", 42716124.0, 78820966.0),
-    "pfc3d_64_mixed": ("0a53c532af651681d572c5837747515603fda5e068f8ad74fd5d5d04fa75ee06", 41894271.0, 71753338.0),
+    "pfc2d_512_fp64": ("d999e08731c4b4ef2dbe27220ad30439bb557edb03a63365e8689a04051c62ab", 42706154.0, 78820966.0),
+    "pfc3d_64_mixed": ("d999e08731c4b4ef2dbe27220ad30439bb557edb03a63365e8689a04051c62ab", 41851928.0, 71753338.0),
 }
 
 
