@@ -144,16 +144,17 @@ typedef struct pfc_server pfc_server;
  *                 on 2D periodic grid meshes of side a multiple of 64 in
  *                 either precision (a workgroup's rows are a block of 64 x 16
  *                 grid points), also in launches that serve many instances
- *                 when every instance of the launch qualifies; in launches
- *                 that serve the instance alone, on other 2D periodic grid
+ *                 (whose other instances run one iteration per launch in
+ *                 them; the server gives its requests this form where it
+ *                 applies); in launches that serve the instance alone, on
+ *                 other 2D periodic grid
  *                 meshes in float64 (a workgroup's rows are a range of rows)
  *                 and on 3D periodic grid meshes of side 64 in PFC_MIXED (a
  *                 block of 4 x 4 grid lines).  In PFC_MIXED the inner
  *                 iterations run in float32.  Elsewhere, and with 1, one
  *                 iteration per launch.  Results of the two forms differ by
  *                 rounding: an instance gives the same bits alone and in a
- *                 batch with 1, and with 2 where both launches take the block
- *                 form. */
+ *                 batch or a served mix with 1, and with 2 in the block form. */
 typedef struct pfc_opts {
     int struct_size;
     int precision;
@@ -354,9 +355,9 @@ int pfc_instance_launch_stats(const pfc_instance* inst, long long* launches, lon
  * PCG iterations per solver launch (2 where the two-iteration form applies,
  * see pcg_steps_per_launch, else 1) and whether the solver kernel computes the
  * mesh's columns from the row (1) or reads them (0).  In a launch that serves
- * several instances (batches, the server) every instance runs one PCG
- * iteration per launch, unless every instance of the launch takes the 2D block
- * form (see pcg_steps_per_launch). */
+ * several instances (batches, the server) an instance runs two PCG iterations
+ * per launch in the 2D block form and one otherwise (see
+ * pcg_steps_per_launch). */
 int pfc_instance_config(const pfc_instance* inst, int* team_size, int* rows_per_thread, int* pcg_steps_per_launch,
                         int* grid_columns);
 

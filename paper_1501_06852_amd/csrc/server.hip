@@ -67,18 +67,20 @@ struct pfc_server {
 
 namespace {
 
-pfc_opts server_instance_opts(const pfc_server* S, int rpt) {
+pfc_opts server_instance_opts(const pfc_server* S, const pfc_mesh* m, int rpt) {
   pfc_opts o;
   pfc_opts_default(&o);
   o.precision = S->o.precision;
   o.ticks_per_graph = S->o.ticks_per_graph;
   o.rows_per_thread = rpt;
   // a request shares its launches with whichever requests are resident, and the
-  // set changes between launches while it runs: one PCG iteration per launch is
-  // valid in every launch set (the two-iteration form needs launches that serve
-  // the instance alone) and gives the same bits in any of them.  A server with a
-  // single slot runs every request alone and keeps the two-iteration form.
-  o.pcg_steps_per_launch = S->o.max_slots == 1 ? 2 : 1;
+  // set changes between launches while it runs.  The 2D block form of two PCG
+  // iterations per launch runs in any launch set (every launch that holds such
+  // an instance has it) and gives the same bits in any of them; the other
+  // two-iteration forms need launches that serve the instance alone, so those
+  // requests run one iteration per launch, which is valid in every launch set.
+  // A server with a single slot runs every request alone and keeps every form.
+  o.pcg_steps_per_launch = (S->o.max_slots == 1 || block_form_applies(m, o)) ? 2 : 1;
   return o;
 }
 
@@ -112,7 +114,7 @@ int acquire(pfc_server* S, Request* q, bool& ok) {
       ok = true;
       return PFC_OK;
     }
-  pfc_opts o = server_instance_opts(S, rpt);
+  pfc_opts o = server_instance_opts(S, q->mesh, rpt);
   const size_t need = pfc_instance_footprint(q->mesh, &o);
   while (S->used + need > S->o.hbm_budget && !S->pool.empty()) {
     pfc_instance* v = S->pool.back();
@@ -320,7 +322,7 @@ int pfc_server_submit(pfc_server* S, pfc_mesh* mesh, double r, double psibar, do
     set_error("pfc_server_submit: invalid arguments");
     return PFC_ERR_ARG;
   }
-  pfc_opts o = server_instance_opts(S, 1);  // the largest team: an upper bound of the footprint
+  pfc_opts o = server_instance_opts(S, mesh, 1);  // the largest team: an upper bound of the footprint
   if (n_steps > o.max_run_steps) { set_error("pfc_server_submit: too many steps"); return PFC_ERR_ARG; }
   if (pfc_instance_footprint(mesh, &o) > S->o.hbm_budget) {
     set_error("pfc_server_submit: request footprint exceeds the server's memory budget");

@@ -30,6 +30,9 @@ struct Group {
 
 size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int team_size);
 int team_size_for(int n_slices, int rows_per_thread);
+// whether an instance with these options on this mesh takes the 2D block form of
+// two PCG iterations per launch (with pcg_steps_per_launch = 2)
+bool block_form_applies(const pfc_mesh* m, const pfc_opts& o);
 void set_params(InstDev& h, double r, double tau, double m11);
 int set_mobility_mean(pfc_instance* I, const double* psi, hipStream_t s);
 int prep_ops_public(pfc_instance* I, hipStream_t s);

@@ -555,13 +555,16 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   // Gram partials of an orthogonalisation (the previous launch formed w = A_s z_j)
   if (S.phase == PH_ASPMV)
     gs_gather(I.gpart + (long long)parity * te.size * PFC_GS_NV, te.size, &I.hist->L[0][0], gs_g, gs_L);
-  bool scg = false;
+  bool scg = false, form = false;
   SsPre ssp;
   S3Pre<float> s3p;
   B2Pre<T> b2p;
   if constexpr (SSX) {
-    // launches after a two-iteration launch, or after the set-up that formed the first basis
-    scg = S.phase == PH_SCG_ITER || (S.phase == PH_PCG_SETUP && I.sstep && scg_kind(S.kind));
+    // launches after a two-iteration launch, or after the set-up that formed the first basis,
+    // of an instance whose two-iteration form is this launch's (a launch that serves many
+    // instances may hold instances of either form: the others run one iteration per launch)
+    form = SB2 ? I.sstep == 3 : (SS ? I.sstep == 1 : I.sstep == 2);
+    scg = form && (S.phase == PH_SCG_ITER || (S.phase == PH_PCG_SETUP && scg_kind(S.kind)));
     if (scg && !(S.phase == PH_SCG_ITER && S.pcur)) {
       // the previous launch's Gram partials: loaded in the prologue where the
       // launch serves one instance, else here from the instance's buffer
@@ -615,7 +618,7 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     // the mass solves of the consistent initial values run in float64 in every precision
     case PH_PCG_SETUP:
       if constexpr (SSX) {
-        if (I.sstep && scg_kind(S.kind)) {  // set-up and first basis of a two-iteration solve
+        if (form && scg_kind(S.kind)) {  // set-up and first basis of a two-iteration solve
           fused = true;
           double* gout = I.spart + (long long)(1 - parity) * te.size * 32;
           if constexpr (SB2) ph_scg2b<T>(I, S, tm, ss_coef, true, gout, b2p, parity);
@@ -900,6 +903,12 @@ static bool sstep_block2(const pfc_mesh* m, const pfc_opts& o, int team_size) {
          team_size == d.n_slices / PFC_WAVES;
 }
 
+bool block_form_applies(const pfc_mesh* m, const pfc_opts& o) {
+  pfc_opts o2 = o;
+  o2.pcg_steps_per_launch = 2;
+  return sstep_block2(m, o2, team_size_for(m->n_slices, o.rows_per_thread));
+}
+
 // Carve the instance arena.  With base == nullptr only the size is computed.
 size_t carve(InstDev& h, char* base, const pfc_mesh* m, const pfc_opts& o, int team_size) {
   size_t off = 0;
@@ -1076,8 +1085,10 @@ int Group::build(hipStream_t capture, int precision, int ticks) {
     default: PFC_TICK(TT, SG, PFC_COL_MEM, false); break;                      \
   }
     const bool sg = (count == 1);
-    bool b2 = true;  // every instance runs two PCG iterations per launch on blocks of a 2D grid (ph_scg2b)
-    for (int i = 0; i < count; ++i) b2 = b2 && h_descs[i].sstep == 3;
+    // the launches have the 2D block form (ph_scg2b) when some instance takes it;
+    // the other instances run one PCG iteration per launch in them
+    bool b2 = false;
+    for (int i = 0; i < count; ++i) b2 = b2 || h_descs[i].sstep == 3;
     if (precision == PFC_MIXED) {
       if (sg) { PFC_TICK_COLS(float, true); } else { PFC_TICK_COLS(float, false); }
     } else {

@@ -72,19 +72,20 @@ def test_batch_alone_equals_mix(pfc, prec):
 @pytest.mark.parametrize("prec", [0, 1])
 def test_batch_2d_blocks_alone_equals_batch(pfc, prec):
     """Instances on 2D grids of side a multiple of 64 run two PCG iterations per launch on blocks of 64 x 16
-    rows in a batch as alone (default options): the batch gives each instance the bits it has alone and the
+    rows in a batch as alone (default options), next to an instance without a two-iteration form that runs
+    one iteration per launch in the same launches: the batch gives each instance the bits it has alone and the
     step of the one-iteration form to the accuracy of two solves at relative residual 1e-8, and float64
     instances land on the oracle's Rosenbrock step to that accuracy."""
-    probs = [Problem(2, 64, 0.2, seed=21), Problem(2, 128, 0.0, seed=22)]
-    prm = wl.draw_params(3, 300)
-    owners = [0, 0, 1]
+    probs = [Problem(2, 64, 0.2, seed=21), Problem(2, 128, 0.0, seed=22), Problem(3, 4, 0.0, seed=23)]
+    prm = wl.draw_params(4, 300)
+    owners = [0, 0, 1, 2]   # the 3D instance has no two-iteration form here and runs one per launch
     insts, states, alone = [], [], []
     try:
         steps = 1
         for k, pi in enumerate(owners):
             P = probs[pi]
             insts.append(pfc.pfc_instance_create(P.gpu_mesh(), pfc.pfc_opts_default(precision=prec)))
-            assert pfc.pfc_instance_config(insts[-1])["pcg_steps_per_launch"] == 2
+            assert pfc.pfc_instance_config(insts[-1])["pcg_steps_per_launch"] == (2 if P.mesh.dim == 2 else 1)
             psi = wl.psi0(P.n, prm[k].psibar, 0.01, seed=prm[k].seed)
             s0 = np.concatenate([np.zeros(P.n), psi, np.zeros(P.n)])
             states.append(dev(s0))
@@ -96,7 +97,7 @@ def test_batch_2d_blocks_alone_equals_batch(pfc, prec):
         args = ([p.r for p in prm], [p.psibar for p in prm], [p.tau for p in prm])
         st, infos = pfc.pfc_batch_run(insts, ns, states, *args, steps)
         assert st >= 0
-        for k in range(3):
+        for k in range(len(owners)):
             assert np.array_equal(host(states[k]), alone[k]), k
             assert all(i["true_rel_res"] <= 1e-8 for i in infos[k])
         # the same batch with one PCG iteration per launch: the same step to the solves' accuracy
@@ -107,7 +108,7 @@ def test_batch_2d_blocks_alone_equals_batch(pfc, prec):
                                    np.zeros(probs[pi].n)])) for k, pi in enumerate(owners)]
         st, _ = pfc.pfc_batch_run(one, ns, st1, *args, steps)
         assert st >= 0
-        for k in range(3):
+        for k in range(len(owners)):
             assert rel(host(st1[k]), host(states[k])) <= 1e-6, k
         if prec == 0:
             for k, pi in enumerate(owners):
@@ -311,8 +312,12 @@ def test_server_large_classes_mixed(pfc):
         for k, (mi, p, psi) in enumerate(reqs):
             P = probs[mi]
             print(f"served large classes: request {k} ({P.mesh.dim}D, n = {P.n}) alone and oracle", flush=True)
+            # the server runs 2D grids of side 64k in the block form of two PCG iterations per launch,
+            # the others one iteration per launch
+            pcg = 2 if (P.mesh.dim == 2 and P.mesh.N % 64 == 0) else 1
             inst = pfc.pfc_instance_create(meshes[mi], pfc.pfc_opts_default(precision=1, rows_per_thread=1,
-                                                                            pcg_steps_per_launch=1))
+                                                                            pcg_steps_per_launch=pcg))
+            assert pfc.pfc_instance_config(inst)["pcg_steps_per_launch"] == pcg
             s = dev(np.concatenate([np.zeros(P.n), psi, np.zeros(P.n)]))
             pfc.pfc_rosenbrock_run(inst, P.n, s, p.r, p.psibar, p.tau, steps)
             alone = host(s)
