@@ -231,7 +231,7 @@ __device__ __forceinline__ bool scg_kind(int kind) { return kind >= KIND_Y0 && k
 // with the stopping test of the standard iteration after each of them.  coef
 // receives the increment of x and the new p and u as combinations of B;
 // S.pcur = 1 marks a launch that only adds the increment (the solve ends there).
-__device__ void scg_transition(State& S, const InstDev& I, bool wr, const double* g, double* coef) {
+__device__ __forceinline__ void scg_transition(State& S, const InstDev& I, bool wr, const double* g, double* coef) {
   if (S.phase == PH_SCG_ITER && S.pcur) { pcg_done(S, I, wr); return; }
   const bool first = (S.phase == PH_PCG_SETUP);  // that launch formed the solve's first basis
   S.phase = PH_SCG_ITER;
@@ -548,12 +548,12 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
 #endif
   const InstDev& I = sI;
   const bool writer = (te.rank == 0);
-  if (S.phase == PH_DONE) {
+  if (__builtin_expect(S.phase == PH_DONE, 0)) {
     if (writer && tid < NS) ((int*)st_out)[tid] = ((const int*)&S)[tid];
     return;
   }
   // Gram partials of an orthogonalisation (the previous launch formed w = A_s z_j)
-  if (S.phase == PH_ASPMV)
+  if (__builtin_expect(S.phase == PH_ASPMV, 0))
     gs_gather(I.gpart + (long long)parity * te.size * PFC_GS_NV, te.size, &I.hist->L[0][0], gs_g, gs_L);
   bool scg = false, form = false;
   SsPre ssp;
@@ -610,7 +610,17 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   const bool sd = (S.kind == KIND_SD);  // second-ring pattern, never staged
   Red3 acc = red3(0.0, 0.0, 0.0);
   bool fused = false;  // a set-up launch that formed a two-iteration solve's first basis (Gram partials only)
-  switch (S.phase) {
+  bool scg_done = false;
+  if constexpr (SSX) {
+    if (__builtin_expect(S.phase == PH_SCG_ITER, 1)) {  // the common launch, laid out first
+      double* gout = I.spart + (long long)(1 - parity) * te.size * 32;
+      if constexpr (SB2) ph_scg2b<T>(I, S, tm, ss_coef, false, gout, b2p, parity);
+      else if constexpr (SS) ph_scg<COLS>(I, S, tm, ss_coef, false, gout, ss_rows(I, te.rank, te.size), ssp, parity);
+      else ph_scg3<float>(I, S, tm, ss_coef, false, gout, s3p, parity);
+      scg_done = true;
+    }
+  }
+  if (!scg_done) switch (S.phase) {
     case PH_SOLVE_INIT:
     case PH_RB_RHS: acc = ph_solve_init<COLS>(I, S, tm); break;
     case PH_RB_BEGIN: acc = ph_rb_begin<COLS>(I, tm); break;
@@ -644,15 +654,7 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     case PH_PCH_OUT: acc = ph_pch_out<T>(I, tm); break;
     case PH_CG_INIT: acc = pcg_phase<T, COLS, PH_CG_INIT>(I, S, tm, sd); break;
     case PH_CG_ITER: acc = pcg_phase<T, COLS, PH_CG_ITER>(I, S, tm, sd); break;
-    case PH_SCG_ITER:
-      if constexpr (SSX) {
-        double* gout = I.spart + (long long)(1 - parity) * te.size * 32;
-        if constexpr (SB2) ph_scg2b<T>(I, S, tm, ss_coef, false, gout, b2p, parity);
-        else if constexpr (SS) ph_scg<COLS>(I, S, tm, ss_coef, false, gout, ss_rows(I, te.rank, te.size), ssp, parity);
-        else ph_scg3<float>(I, S, tm, ss_coef, false, gout, s3p, parity);
-      }
-      break;
-    default: break;
+    default: break;  // PH_SCG_ITER above
   }
   PFC_STAMP(t_work);
   if (phase_partials(S.phase) && !fused) {
