@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # was taken on: when their digest differs, `traffic` is reported as null.
 TRAFFIC = {
     # workload: (sha256 of the kernel sources, bytes per launch, algorithmic bytes per launch of the same run)
-    "pfc2d_512_fp64": ("d999e08731c4b4ef2dbe27220ad30439bb557edb03a63365e8689a04051c62ab", 42706154.0, 78820966.0),
-    "pfc3d_64_mixed": ("d999e08731c4b4ef2dbe27220ad30439bb557edb03a63365e8689a04051c62ab", 41851928.0, 71753338.0),
+    "pfc2d_512_fp64": ("5d6bc0093163f3443d35d0b78ade2451420cf73e36b7e59c245c743d4e41d193", 42686136.0, 78820966.0),
+    "pfc3d_64_mixed": ("5d6bc0093163f3443d35d0b78ade2451420cf73e36b7e59c245c743d4e41d193", 41853519.0, 71753338.0),
 }
 
 
