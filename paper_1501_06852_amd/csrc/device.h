@@ -96,12 +96,18 @@ __device__ __forceinline__ Red3 wg_sum3(Red3 v, Red3* lds4) {
   return r;
 }
 
-// Slices handled by this workgroup: a contiguous block, cycled over its waves.
+// Slices handled by this workgroup, cycled over its waves: a contiguous block
+// where every slice of the mesh has the same width; where widths differ (P2
+// meshes: vertex rows have 19 entries, edge rows 9, numbered in that order) the
+// team's slices are dealt round robin (slice rank + size j), so that every
+// workgroup, and every SIMD of it, gets its share of the wide slices.
 #define PFC_SLICES(I, tm)                                                          \
+  const bool _rr = (I).m.uw == 0;                                                  \
   const int _spw = ((I).m.n_slices + (tm).size - 1) / (tm).size;                   \
-  const int _sbeg = (tm).rank * _spw;                                              \
-  const int _send = min(_sbeg + _spw, (I).m.n_slices);                              \
-  for (int sl = _sbeg + (tm).wave; sl < _send; sl += PFC_WAVES)
+  const int _sbeg = _rr ? (tm).rank : (tm).rank * _spw;                            \
+  const int _send = _rr ? (I).m.n_slices : min(_sbeg + _spw, (I).m.n_slices);      \
+  const int _sstep = _rr ? (tm).size * PFC_WAVES : PFC_WAVES;                      \
+  for (int sl = _sbeg + (_rr ? (tm).size * (tm).wave : (tm).wave); sl < _send; sl += _sstep)
 
 // Row loops over the entries of a slice: the P1 meshes of this solver have 7
 // (2D) or 15 (3D) entries per row; for those widths the loop is unrolled (fully
