@@ -110,8 +110,9 @@ __device__ __forceinline__ Red3 wg_sum3(Red3 v, Red3* lds4) {
   for (int sl = _sbeg + (_rr ? (tm).size * (tm).wave : (tm).wave); sl < _send; sl += _sstep)
 
 // Row loops over the entries of a slice: the P1 meshes of this solver have 7
-// (2D) or 15 (3D) entries per row; for those widths the loop is unrolled (fully
-// for 7, in chunks of 5 for 15, to stay within the register budget) so that a
+// (2D) or 15 (3D) entries per row, 2D P2 meshes 19 (vertex rows) or 9 (edge
+// rows); for those widths the loop is unrolled (fully for 7, in chunks of 5 for
+// 15 and of 3 for the P2 widths, to stay within the register budget) so that a
 // wave issues the index, value and gather loads of many entries at once.
 template <typename F>
 __device__ __forceinline__ void for_width(int w, F f) {
@@ -121,6 +122,12 @@ __device__ __forceinline__ void for_width(int w, F f) {
   } else if (w == 15) {
 #pragma unroll 5
     for (int k = 0; k < 15; ++k) f(k);
+  } else if (w == 9) {  // P2 edge rows (2D)
+#pragma unroll 3
+    for (int k = 0; k < 9; ++k) f(k);
+  } else if (w == 19) {  // P2 vertex rows (2D)
+#pragma unroll 3
+    for (int k = 0; k < 19; ++k) f(k);
   } else {
     for (int k = 0; k < w; ++k) f(k);
   }
