@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # was taken on: when their digest differs, `traffic` is reported as null.
 TRAFFIC = {
     # workload: (sha256 of the kernel sources, bytes per launch, algorithmic bytes per launch of the same run)
-    "pfc2d_512_fp64": ("5d6bc0093163f3443d35d0b78ade2451420cf73e36b7e59c245c743d4e41d193", 42686136.0, 78820966.0),
-    "pfc3d_64_mixed": ("5d6bc0093163f3443d35d0b78ade2451420cf73e36b7e59c245c743d4e41d193", 41853519.0, 71753338.0),
+    "pfc2d_512_fp64": ("924059cb26b23abde0f2c80fcbc2d1524eef668a8853d5ca587551af96c5dc11", 43501906.0, 78820966.0),
+    "pfc3d_64_mixed": ("924059cb26b23abde0f2c80fcbc2d1524eef668a8853d5ca587551af96c5dc11", 41851172.0, 71753338.0),
 }
 
 
