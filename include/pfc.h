@@ -489,9 +489,11 @@ typedef struct pfc_tune_entry {
 int pfc_autotune(pfc_mesh* mesh, int precision, int count, int force, pfc_tune_entry* out, void* stream);
 /* The same for batches that mix several meshes (the server's case): `count`
  * instances dealt round robin over meshes[0..n_meshes-1], only rows per thread
- * searched (the other knobs keep their defaults).  The entry's key has
- * dim = n = z = 0 ("a mix"), whatever the meshes; tuning another mix replaces
- * it. */
+ * searched (the other knobs keep their defaults).  Instances that take the 2D
+ * block form at one row per thread keep one row per thread and two PCG
+ * iterations per launch, as in the server; the searched value applies to the
+ * others.  The entry's key has dim = n = z = 0 ("a mix"), whatever the meshes;
+ * tuning another mix replaces it. */
 int pfc_autotune_mix(pfc_mesh* const* meshes, int n_meshes, int precision, int count, int force, pfc_tune_entry* out,
                      void* stream);
 /* Table entry for `count` instances of a mesh with these sizes (arch: NULL
@@ -517,16 +519,21 @@ void pfc_tune_clear(void);
  *   precision   PFC_FP64 or PFC_MIXED
  *   ticks_per_graph  as in pfc_opts (0: default)
  *   rows_per_thread  rows per thread of the request instances, 1..8, or 0
- *               (the default): chosen per request at admission, one row per
+ *               (the default): chosen per request at admission.  A request
+ *               that takes the 2D block form of two PCG iterations per launch
+ *               at one row per thread (see pcg_steps_per_launch; a server with
+ *               more than one slot) gets one; any other request one row per
  *               thread while the active requests and the new one fit into one
  *               round of resident workgroups (CUs x 1024 rows), two beyond.
  *               More rows per thread give each request fewer, longer
  *               workgroups: more throughput when many requests share the GPU,
  *               longer solves when few do.
- *   tuned       1: with rows_per_thread 0, take each request's rows per thread
- *               from the autotuning table's mixed-batch entry (pfc_autotune_mix)
- *               for the number of active requests including it, and use the
- *               rule above only where the table has no such entry; 0: the rule.
+ *   tuned       1: with rows_per_thread 0, take the rows per thread of the
+ *               requests without the block form from the autotuning table's
+ *               mixed-batch entry (pfc_autotune_mix, which times its batches
+ *               with the same split) for the number of active requests
+ *               including it, and use the rule above only where the table
+ *               has no such entry; 0: the rule.
  *   n_steps ... Rosenbrock steps per request (set per request) */
 typedef struct pfc_server_opts {
     int struct_size;

@@ -93,6 +93,8 @@ pfc_opts server_instance_opts(const pfc_server* S, const pfc_mesh* m, int rpt) {
 // workgroups: more throughput when the GPU is full).
 int choose_rpt(const pfc_server* S, const Request* q) {
   if (S->o.rows_per_thread > 0) return S->o.rows_per_thread;
+  // requests that take the 2D block form at one row per thread keep it
+  if (S->o.max_slots > 1 && block_form_applies(q->mesh, server_instance_opts(S, q->mesh, 1))) return 1;
   if (S->o.tuned) {
     const int t = tuned_mix_rows_per_thread(S->o.precision, (int)S->active.size() + 1);
     if (t > 0) return t;

@@ -184,11 +184,22 @@ double time_candidate(pfc_mesh* const* ms, int n_meshes, int precision, int coun
   o.grid_columns = c.grid;
   o.shared_ops = c.shared;
   o.max_run_steps = 4;
+  // a mix is timed as the server runs it: instances that take the 2D block form
+  // at one row per thread keep it, one iteration per launch for the others
+  std::vector<pfc_opts> om(n_meshes, o);
+  if (n_meshes > 1)
+    for (int k = 0; k < n_meshes; ++k) {
+      pfc_opts b = o;
+      b.rows_per_thread = 1;
+      b.pcg_steps_per_launch = 2;
+      if (block_form_applies(ms[k], b)) om[k] = b;
+      else om[k].pcg_steps_per_launch = 1;
+    }
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) { *status = PFC_ERR_HIP; return -1; }
   double need = 0.0;
   for (int k = 0; k < count; ++k) {
-    const size_t fp = pfc_instance_footprint(ms[k % n_meshes], &o);
+    const size_t fp = pfc_instance_footprint(ms[k % n_meshes], &om[k % n_meshes]);
     if (fp == 0) { *status = PFC_ERR_ARG; return -1; }
     need += (double)fp;
   }
@@ -202,7 +213,7 @@ double time_candidate(pfc_mesh* const* ms, int n_meshes, int precision, int coun
   for (int k = 0; k < count && !rc; ++k) {
     pfc_mesh* m = ms[k % n_meshes];
     const int n = m->n;
-    rc = pfc_instance_create(m, &o, &insts[k]);
+    rc = pfc_instance_create(m, &om[k % n_meshes], &insts[k]);
     if (rc) break;
     if (hipMalloc((void**)&states[k], sizeof(double) * 3 * (size_t)n) != hipSuccess) { rc = PFC_ERR_OOM; break; }
     h.assign((size_t)3 * n, 0.0);
