@@ -209,14 +209,6 @@ template <> struct TV<float> {
 // with S_k = sum over the vertices of psi^k and c_m = m!/(m+4)!.
 __device__ __forceinline__ double cm_of(int dim) { return dim == 2 ? (1.0 / 360.0) : (1.0 / 840.0); }
 
-// psi values of the vertices of element el; psi(node) supplied by a functor
-template <typename PsiF>
-__device__ __forceinline__ void elem_psi(const MeshDev& m, int el, PsiF psi, double* p) {
-  const int k = m.dim + 1;
-  const int* en = m.elem_nodes + (long long)el * k;
-  for (int a = 0; a < k; ++a) p[a] = psi(en[a]);
-}
-
 // P2 (Section 3, p = 2; integrands of degree 8, exact through the reference
 // table C4[a][b][c][d] = int phi_a phi_b phi_c phi_d / |T|):
 //   Mpsi2^T_ab             = |T| sum_{c,d} psi_c psi_d C4[a][b][c][d]
@@ -274,22 +266,52 @@ __device__ __forceinline__ double node_psi3_p2(const MeshDev& m, int i, PsiF psi
   return acc;
 }
 
+// The P1 element sums below visit an element list in groups of PFC_EV: the
+// loads of a group (list entries, then the elements' nodes, then psi there)
+// are issued together instead of one dependent chain per visit, and the
+// visits' terms are then added in list order as one visit at a time would.
+#define PFC_EV 4  // entry sums
+#define PFC_EVN 3  // node sums: psi there is a stage combination (up to three loads)
+// psi at the vertices of element el, psi(node) supplied by a functor (p[3] = 0
+// on triangles)
+template <typename PsiF>
+__device__ __forceinline__ void elem_psi4(const MeshDev& m, int el, PsiF psi, double* p) {
+  const int k = m.dim + 1;
+  const int* en = m.elem_nodes + (long long)el * k;
+  const int n0 = en[0], n1 = en[1], n2 = en[2];
+  const int n3 = k == 4 ? en[3] : n2;
+  p[0] = psi(n0);
+  p[1] = psi(n1);
+  p[2] = psi(n2);
+  p[3] = k == 4 ? psi(n3) : 0.0;
+}
+
 template <typename PsiF>
 __device__ __forceinline__ double entry_Mpsi2(const MeshDev& m, long long e, PsiF psi) {
   if (m.degree == 2) return m.dim == 2 ? entry_Mpsi2_p2<6>(m, e, psi) : entry_Mpsi2_p2<10>(m, e, psi);
   double acc = 0.0;
   const double cm = cm_of(m.dim);
   const int t0 = m.sl_el_ptr[e], t1 = m.sl_el_ptr[e + 1];
-  for (int t = t0; t < t1; ++t) {
-    const int pk = m.sl_el[t];
-    const int el = pk >> 4, a = (pk >> 2) & 3, b = pk & 3;
-    double p[4];
-    elem_psi(m, el, psi, p);
-    double S1 = 0.0, S2 = 0.0;
-    for (int v = 0; v <= m.dim; ++v) { S1 += p[v]; S2 += p[v] * p[v]; }
-    const double pa = p[a], pb = p[b];
-    const double s = S1 * S1 + S2 + 2.0 * S1 * (pa + pb) + 2.0 * (pa * pa + pb * pb + pa * pb);
-    acc += m.elem_vol[el] * cm * (a == b ? 2.0 : 1.0) * s;
+  for (int t = t0; t < t1; t += PFC_EV) {
+    int pk[PFC_EV];
+#pragma unroll
+    for (int u = 0; u < PFC_EV; ++u) pk[u] = m.sl_el[min(t + u, t1 - 1)];
+    double p[PFC_EV][4], vol[PFC_EV];
+#pragma unroll
+    for (int u = 0; u < PFC_EV; ++u) {
+      elem_psi4(m, pk[u] >> 4, psi, p[u]);
+      vol[u] = m.elem_vol[pk[u] >> 4];
+    }
+#pragma unroll
+    for (int u = 0; u < PFC_EV; ++u) {
+      if (t + u >= t1) break;
+      const int a = (pk[u] >> 2) & 3, b = pk[u] & 3;
+      double S1 = 0.0, S2 = 0.0;
+      for (int v = 0; v <= m.dim; ++v) { S1 += p[u][v]; S2 += p[u][v] * p[u][v]; }
+      const double pa = p[u][a], pb = p[u][b];
+      const double s = S1 * S1 + S2 + 2.0 * S1 * (pa + pb) + 2.0 * (pa * pa + pb * pb + pa * pb);
+      acc += vol[u] * cm * (a == b ? 2.0 : 1.0) * s;
+    }
   }
   return acc;
 }
@@ -300,16 +322,26 @@ __device__ __forceinline__ double node_psi3(const MeshDev& m, int i, PsiF psi) {
   double acc = 0.0;
   const double cm = cm_of(m.dim);
   const int t0 = m.nd_el_ptr[i], t1 = m.nd_el_ptr[i + 1];
-  for (int t = t0; t < t1; ++t) {
-    const int pk = m.nd_el[t];
-    const int el = pk >> 2, a = pk & 3;
-    double p[4];
-    elem_psi(m, el, psi, p);
-    double S1 = 0.0, S2 = 0.0, S3 = 0.0;
-    for (int v = 0; v <= m.dim; ++v) { S1 += p[v]; S2 += p[v] * p[v]; S3 += p[v] * p[v] * p[v]; }
-    const double pa = p[a];
-    const double s = S1 * S1 * S1 + 3.0 * S1 * S2 + 2.0 * S3 + 3.0 * pa * (S1 * S1 + S2) + 6.0 * pa * pa * S1 + 6.0 * pa * pa * pa;
-    acc += m.elem_vol[el] * cm * s;
+  for (int t = t0; t < t1; t += PFC_EVN) {
+    int pk[PFC_EVN];
+#pragma unroll
+    for (int u = 0; u < PFC_EVN; ++u) pk[u] = m.nd_el[min(t + u, t1 - 1)];
+    double p[PFC_EVN][4], vol[PFC_EVN];
+#pragma unroll
+    for (int u = 0; u < PFC_EVN; ++u) {
+      elem_psi4(m, pk[u] >> 2, psi, p[u]);
+      vol[u] = m.elem_vol[pk[u] >> 2];
+    }
+#pragma unroll
+    for (int u = 0; u < PFC_EVN; ++u) {
+      if (t + u >= t1) break;
+      const int a = pk[u] & 3;
+      double S1 = 0.0, S2 = 0.0, S3 = 0.0;
+      for (int v = 0; v <= m.dim; ++v) { S1 += p[u][v]; S2 += p[u][v] * p[u][v]; S3 += p[u][v] * p[u][v] * p[u][v]; }
+      const double pa = p[u][a];
+      const double s = S1 * S1 * S1 + 3.0 * S1 * S2 + 2.0 * S3 + 3.0 * pa * (S1 * S1 + S2) + 6.0 * pa * pa * S1 + 6.0 * pa * pa * pa;
+      acc += vol[u] * cm * s;
+    }
   }
   return acc;
 }
