@@ -1949,11 +1949,19 @@ __device__ __forceinline__ void ph_aspmv(const InstDev& I, const State& S, const
 // basis' stored Gram rows L (the Hist record) come to Ls[32 * 32] in the same
 // round trip.  Every thread of the workgroup calls this.
 static_assert(PFC_WG == PFC_MAXM * PFC_MAXM, "gs_gather loads the stored Gram rows one entry per thread");
+#define PFC_GS_U 8  // partials per thread whose loads are issued together
 __device__ __forceinline__ void gs_gather(const double* part, int size, const double* Lg, double* g, double* Ls) {
   const int tid = threadIdx.x, v = tid & 63, grp = tid >> 6;
   const double lv = Lg[tid];  // PFC_WG = PFC_MAXM * PFC_MAXM entries, one per thread
   double s = 0.0;
-  for (int k = grp; k < size; k += PFC_WAVES) s += part[(long long)k * PFC_GS_NV + v];
+  for (int k0 = grp; k0 < size; k0 += PFC_GS_U * PFC_WAVES) {
+    double t[PFC_GS_U];
+#pragma unroll
+    for (int u = 0; u < PFC_GS_U; ++u) t[u] = part[(long long)min(k0 + u * PFC_WAVES, size - 1) * PFC_GS_NV + v];
+#pragma unroll
+    for (int u = 0; u < PFC_GS_U; ++u)
+      if (k0 + u * PFC_WAVES < size) s += t[u];
+  }
   pfc_gsred[grp * PFC_GS_NV + v] = s;
   Ls[tid] = lv;
   __syncthreads();

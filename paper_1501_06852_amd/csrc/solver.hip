@@ -502,6 +502,10 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   constexpr int NS = (int)(sizeof(State) / 4), ND = (int)(sizeof(InstDev) / 4);
   static_assert(NS <= 64 && ND <= PFC_WG - 64, "state / descriptor too large for the staging threads");
   const int word = tid < 64 ? ((const int*)st_in)[min(tid, NS - 1)] : ((const int*)gI)[min(tid - 64, ND - 1)];
+  // the fields that choose a workgroup's path before the transition, read from
+  // the state record itself: thread 0 rewrites the LDS copy in the transition
+  // while the other waves may still be reading them
+  const int ph_in = st_in->phase, kind_in = st_in->kind, pcur_in = st_in->pcur;
   double gpl[SSX ? PFC_SS_GL : 1];
   if constexpr (SSX && SINGLE) ss_gram_prefetch(gram_in_arg, part_in, te.size, gpl);
   // columns of this workgroup's slices: positions [lo, lo + len) of the SELL
@@ -548,12 +552,12 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
 #endif
   const InstDev& I = sI;
   const bool writer = (te.rank == 0);
-  if (__builtin_expect(S.phase == PH_DONE, 0)) {
+  if (__builtin_expect(ph_in == PH_DONE, 0)) {
     if (writer && tid < NS) ((int*)st_out)[tid] = ((const int*)&S)[tid];
     return;
   }
   // Gram partials of an orthogonalisation (the previous launch formed w = A_s z_j)
-  if (__builtin_expect(S.phase == PH_ASPMV, 0))
+  if (__builtin_expect(ph_in == PH_ASPMV, 0))
     gs_gather(I.gpart + (long long)parity * te.size * PFC_GS_NV, te.size, &I.hist->L[0][0], gs_g, gs_L);
   bool scg = false, form = false;
   SsPre ssp;
@@ -564,8 +568,8 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     // of an instance whose two-iteration form is this launch's (a launch that serves many
     // instances may hold instances of either form: the others run one iteration per launch)
     form = SB2 ? I.sstep == 3 : (SS ? I.sstep == 1 : I.sstep == 2);
-    scg = form && (S.phase == PH_SCG_ITER || (S.phase == PH_PCG_SETUP && scg_kind(S.kind)));
-    if (scg && !(S.phase == PH_SCG_ITER && S.pcur)) {
+    scg = form && (ph_in == PH_SCG_ITER || (ph_in == PH_PCG_SETUP && scg_kind(kind_in)));
+    if (scg && !(ph_in == PH_SCG_ITER && pcur_in)) {
       // the previous launch's Gram partials: loaded in the prologue where the
       // launch serves one instance, else here from the instance's buffer
       const double* gin = SINGLE ? gram_in_arg : I.spart + (long long)parity * te.size * 32;
