@@ -456,6 +456,7 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
                                                  double* part_out_arg, int parity, const int* __restrict__ col_arg,
                                                  int uw_arg, int nsl_arg, const double* gram_in_arg) {
   __shared__ State S;
+  __shared__ State S0;  // entry state of launches that serve many instances (path choice)
   __shared__ InstDev sI;
   __shared__ Red3 lds4[PFC_WAVES];
   __shared__ double ybuf[PFC_MAXM];
@@ -502,10 +503,16 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   constexpr int NS = (int)(sizeof(State) / 4), ND = (int)(sizeof(InstDev) / 4);
   static_assert(NS <= 64 && ND <= PFC_WG - 64, "state / descriptor too large for the staging threads");
   const int word = tid < 64 ? ((const int*)st_in)[min(tid, NS - 1)] : ((const int*)gI)[min(tid - 64, ND - 1)];
-  // the fields that choose a workgroup's path before the transition, read from
-  // the state record itself: thread 0 rewrites the LDS copy in the transition
-  // while the other waves may still be reading them
-  const int ph_in = st_in->phase, kind_in = st_in->kind, pcur_in = st_in->pcur;
+  // the fields that choose a workgroup's path before the transition: thread 0
+  // rewrites S in the transition while the other waves may still be reading
+  // them, so they come from the state record itself (one instance per launch),
+  // or from S0, an LDS copy of the entry state that nothing rewrites
+  int ph_in = 0, kind_in = 0, pcur_in = 0;
+  if constexpr (SINGLE) {
+    ph_in = st_in->phase;
+    kind_in = st_in->kind;
+    pcur_in = st_in->pcur;
+  }
   double gpl[SSX ? PFC_SS_GL : 1];
   if constexpr (SSX && SINGLE) ss_gram_prefetch(gram_in_arg, part_in, te.size, gpl);
   // columns of this workgroup's slices: positions [lo, lo + len) of the SELL
@@ -529,8 +536,12 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   for (int k = tid + PFC_WG; k < te.size; k += PFC_WG) {  // teams of more than PFC_WG workgroups
     pre2.a += part_in[4 * k]; pre2.b += part_in[4 * k + 1]; pre2.c += part_in[4 * k + 2];
   }
-  if (tid < NS) ((int*)&S)[tid] = word;
-  else if (tid >= 64 && tid < 64 + ND) ((int*)&sI)[tid - 64] = word;
+  if (tid < NS) {
+    ((int*)&S)[tid] = word;
+    if constexpr (!SINGLE) ((int*)&S0)[tid] = word;
+  } else if (tid >= 64 && tid < 64 + ND) {
+    ((int*)&sI)[tid - 64] = word;
+  }
   if (COLS == PFC_COL_LDS) {
 #pragma unroll
     for (int q = 0; q < PFC_LCOL_W; ++q) {
@@ -550,6 +561,11 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   const unsigned long long t_ld = wall_clock64();
   unsigned long long t_red = 0;
 #endif
+  if constexpr (!SINGLE) {
+    ph_in = S0.phase;
+    kind_in = S0.kind;
+    pcur_in = S0.pcur;
+  }
   const InstDev& I = sI;
   const bool writer = (te.rank == 0);
   if (__builtin_expect(ph_in == PH_DONE, 0)) {
