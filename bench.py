@@ -361,13 +361,23 @@ def bench_served(args, torch, wl, pfc):
     for k, (_, c, _) in enumerate(stream(0.0)):
         if c not in sample and meshes[c][0].n <= 32768:
             sample[c] = k
+    def leg(name, res):
+        print(f"served: {name} done, {res['solves_per_s']:.1f} stage solves/s over {res['wall_s']:.1f} s",
+              file=sys.stderr, flush=True)
+        return res
+
     base_bl, _ = serve(0, 1, 0.0, 0)   # a single slot: every request alone (tuned table entries apply from 8)
+    leg("float64 FIFO, backlogged", base_bl)
     rate = 0.8 * nreq / base_bl["wall_s"]
     ours_bl, kept = serve(1, args.slots, 0.0, rpt, keep=set(sample.values()))
+    leg("mixed continuous, backlogged", ours_bl)
     base, _ = serve(0, 1, rate, 0)
+    leg("float64 FIFO, Poisson arrivals", base)
     ours, _ = serve(1, args.slots, rate, rpt)
+    leg("mixed continuous, Poisson arrivals", ours)
     # the same backlogged stream with the load rule instead of the table (for comparison)
     ours_rule, _ = serve(1, args.slots, 0.0, rpt, use_tuned=0)
+    leg("mixed continuous with the load rule, backlogged", ours_rule)
     if not args.no_precision_check:
         reqs0 = stream(0.0)
         errs = {}
@@ -517,7 +527,7 @@ def main():
     ap.add_argument("--no-handpicked", action="store_true", help="batched: skip the hand-picked comparison run")
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--plain-sample", type=int, default=16)
-    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--req-steps", type=int, default=5)
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--rows-per-thread", type=int, default=None,
