@@ -1605,6 +1605,8 @@ __device__ __forceinline__ void ph_scg3(const InstDev& I, const State& S, const 
 #define PFC_B2_N2 (PFC_B2_W2 * 20)  // two-step frame
 #define PFC_B2_W1 66
 #define PFC_B2_N1 (PFC_B2_W1 * 18)  // one-step frame
+#define PFC_B2_W3 70
+#define PFC_B2_N3 (PFC_B2_W3 * 22)  // three-step frame (a set-up that also ends the previous solve)
 struct B2Geo {
   int x0, y0, N;
 };
@@ -1644,6 +1646,25 @@ __device__ __forceinline__ void b2_load(const InstDev& I, int rank, B2Pre<T>& P,
   }
 }
 
+// The launch after one that ended a solve in its set-up (State::fuse) stores
+// that solve's final x on the own rows: x plus the last increment over the
+// basis, which is still the other parity's (this launch writes its own rows'
+// basis there only afterwards), as the launch that only adds the increment
+// would.
+template <typename T>
+__device__ __forceinline__ void b2_end_store(const InstDev& I, int rank, int kind, double c0, double c1, double c3,
+                                             int par) {
+  const long long nn = I.n;
+  const int tid = threadIdx.x;
+  const B2Geo G = b2_geo(rank, I.m.gN);
+  const int og = b2_row(G, tid & 63, tid >> 6);
+  T* x = pcg_ops<T>(I, kind).x;
+  const T* bas = (const T*)I.sbas + (long long)(1 - par) * 5 * nn;
+  const T xo = gld(x + og);
+  const double p = gld(bas + og), tp = gld(bas + nn + og), u = gld(bas + 3 * nn + og);
+  vst(x + og, T((double)xo + (c0 * p + c1 * tp + c3 * u)));
+}
+
 template <typename T>
 __device__ __forceinline__ void ph_scg2b(const InstDev& I, const State& S, const Team& tm, const double* coef, bool init,
                                          double* spart_out, B2Pre<T>& P, int par) {
@@ -1660,7 +1681,8 @@ __device__ __forceinline__ void ph_scg2b(const InstDev& I, const State& S, const
   T* su = sp + PFC_B2_N2;      // new u on the one-step frame
   T* stp = su + PFC_B2_N1;     // T p on the one-step frame
   T* sb = stp + PFC_B2_N1;     // right-hand side on the two-step frame (first launch of a solve)
-  static_assert((2 * PFC_B2_N2 + 2 * PFC_B2_N1) * sizeof(double) <= sizeof(pfc_ss),
+  T* sv = sb + PFC_B2_N2;      // v on the three-step frame (a set-up that also ends the previous solve)
+  static_assert((2 * PFC_B2_N2 + 2 * PFC_B2_N1 + PFC_B2_N3) * sizeof(double) <= sizeof(pfc_ss),
                 "the frames of ph_scg2b exceed the s-step LDS");
   const int ox = tid & 63, oy = tid >> 6;
   const int og = b2_row(G, ox, oy);
@@ -1675,13 +1697,38 @@ __device__ __forceinline__ void ph_scg2b(const InstDev& I, const State& S, const
                                                                                                       : (const T*)I.x1;
     const double* t = kind == KIND_Y0 ? I.W : (kind == KIND_Y1 ? Vj + nn : (kind == KIND_X2 ? Vj + 2 * nn : nullptr));
     const double ts = kind == KIND_Y0 ? S.vscale : 1.0, sa = kind == KIND_Y1 ? I.tau_p : 1.0;
+    const bool fz = S.fuse != 0;
+    if (fz) {
+      // the previous solve (the P_CH step before, whose x is this solve's v) ends
+      // in this launch: its x plus the last increment, formed on the three-step
+      // frame; x itself stays unchanged here (other workgroups read it on their
+      // halos) and is stored by the next launch (b2_end_store)
+      const T* xp = pcg_ops<T>(I, S.fkind).x;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int q3 = tid + c * PFC_WG;
+        if (q3 < PFC_B2_N3) {
+          const int g = b2_row(G, q3 % PFC_B2_W3 - 3, q3 / PFC_B2_W3 - 3);
+          const T xo = gld(xp + g);
+          const double p = gld(bold + g), tp = gld(bold + nn + g), u = gld(bold + 3 * nn + g);
+          sv[q3] = T((double)xo + (coef[0] * p + coef[1] * tp + coef[3] * u));
+        }
+      }
+      lds_barrier();
+    }
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const int q = tid + c * PFC_WG, qc = min(q, PFC_B2_N2 - 1);
-      const int g = b2_row(G, qc % PFC_B2_W2 - 2, qc / PFC_B2_W2 - 2);
+      const int fx = qc % PFC_B2_W2 - 2, fy = qc / PFC_B2_W2 - 2;
+      const int g = b2_row(G, fx, fy);
       const int base = (g >> 6) * 64 * W7 + (g & 63);
       T d = T(0);
-      if (A) {
+      if (A && fz) {
+        const unsigned char* gd = gdir + b2_class(G, fx, fy) * PFC_GRID_W;
+        const int q3 = (fx + 3) + PFC_B2_W3 * (fy + 3);
+#pragma unroll
+        for (int k = 0; k < W7; ++k) d += gld(A + (long long)base + k * 64) * sv[q3 + b2_doff(gd[k], PFC_B2_W3)];
+      } else if (A) {
 #pragma unroll
         for (int k = 0; k < W7; ++k) {
           const long long e = (long long)base + k * 64;
@@ -1783,7 +1830,8 @@ __device__ __forceinline__ void ph_scg2b(const InstDev& I, const State& S, const
     } else if (S.kind == KIND_X2) {  // (4): z_j = (y0 + (y1 - x1) / delta, x1, x2)
       double* Zj = I.Z + (long long)S.j * n3;
       const double y0i = (double)gld((const T*)I.y0 + og), y1i = (double)gld((const T*)I.y1 + og);
-      const double x1i = (double)gld((const T*)I.x1 + og);
+      // x1 (the solve that ends in this launch when it fuses) from the frame
+      const double x1i = S.fuse ? (double)sv[(ox + 3) + PFC_B2_W3 * (oy + 3)] : (double)gld((const T*)I.x1 + og);
       vst(Zj + og, y0i + (y1i - x1i) / I.delta);
       vst(Zj + nn + og, x1i);
     }

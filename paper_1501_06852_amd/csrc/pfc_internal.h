@@ -125,10 +125,11 @@ struct State {
   int phase;
   int job;
   int step, stage;          // Rosenbrock position
-  int kind, it, pcur, pad0; // inner PCG
+  int kind, it, pcur, fuse;  // inner PCG; fuse: this launch also ended the solve of kind fkind
   int j, cycle, total, apply, kcols;
-  int status, cur;
+  int status, cur, fkind;
   double rho, bb, alpha, beta_cg;
+  double xc0, xc1, xc3;      // its last increment of x over the basis [p, Tp, ., u] (stored the launch after)
   double vscale, bnorm, bnorm_s, est_thresh, w0, est, rel;
   long long t0;             // device clock at the solve's first launch
 };

@@ -281,6 +281,24 @@ __device__ __forceinline__ void scg_transition(State& S, const InstDev& I, bool 
   S.pcur = 0;
 }
 
+// 2D block form: a solve whose last increment this launch adds (S.pcur) ends
+// here if the next P_CH step's set-up reads its x as v (steps (1)-(4) to the
+// next one, not into S_D): this launch then also forms that set-up from x plus
+// the increment on a three-step frame (S.fuse, the kind ending S.fkind), and
+// the next launch stores that x (the increment's coefficients kept in S.xc*).
+__device__ __forceinline__ void b2_fuse_end(State& S, const InstDev& I, bool wr, const double* coef) {
+  S.fuse = 0;
+  if (S.phase != PH_SCG_ITER || !S.pcur) return;
+  const int k = S.kind;
+  if (!(k == KIND_Y0 || k == KIND_Z || k == KIND_X1 || (k == KIND_Y1 && !I.schur_d))) return;
+  pcg_done(S, I, wr);
+  S.fuse = 1;
+  S.fkind = k;
+  S.xc0 = coef[0];
+  S.xc1 = coef[1];
+  S.xc3 = coef[3];
+}
+
 // After w = A_s z_j and its Gram sums g (slots as in ph_aspmv; Ls: the rows of
 // L stored by earlier steps of the cycle): h solves (I + L) h = c by forward
 // substitution, which is modified Gram-Schmidt's sequence of coefficients.
@@ -507,11 +525,12 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   // rewrites S in the transition while the other waves may still be reading
   // them, so they come from the state record itself (one instance per launch),
   // or from S0, an LDS copy of the entry state that nothing rewrites
-  int ph_in = 0, kind_in = 0, pcur_in = 0;
+  int ph_in = 0, kind_in = 0, pcur_in = 0, fuse_in = 0;
   if constexpr (SINGLE) {
     ph_in = st_in->phase;
     kind_in = st_in->kind;
     pcur_in = st_in->pcur;
+    if constexpr (SB2) fuse_in = st_in->fuse;
   }
   double gpl[SSX ? PFC_SS_GL : 1];
   if constexpr (SSX && SINGLE) ss_gram_prefetch(gram_in_arg, part_in, te.size, gpl);
@@ -565,6 +584,7 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
     ph_in = S0.phase;
     kind_in = S0.kind;
     pcur_in = S0.pcur;
+    if constexpr (SB2) fuse_in = S0.fuse;
   }
   const InstDev& I = sI;
   const bool writer = (te.rank == 0);
@@ -603,10 +623,12 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   if (tid == 0) {
     if (scg) {
       if constexpr (SSX) scg_transition(S, I, writer, ss_g, ss_coef);
+      if constexpr (SB2) b2_fuse_end(S, I, writer, ss_coef);
 #ifdef PFC_TICK_TIMING
       if constexpr (SSX) pfc_sst[5] = wall_clock64();
 #endif
     } else {
+      S.fuse = 0;
       Red3 red = red3(0.0, 0.0, 0.0);
       if (phase_partials(S.phase)) {
 #pragma unroll
@@ -627,6 +649,13 @@ __global__ __launch_bounds__(PFC_WG) void k_tick(const TeamEntry* __restrict__ t
   // the new state is final: workgroup 0 stores it while the phase runs
   if (writer && tid < NS) ((int*)st_out)[tid] = ((const int*)&S)[tid];
   Team tm{te.rank, te.size, tid >> 6, tid & 63, lo};
+  if constexpr (SB2) {
+    // the previous launch ended a solve in its set-up: that solve's x on the own rows
+    if (__builtin_expect(fuse_in != 0, 0)) {
+      const State& Se = SINGLE ? *st_in : S0;
+      b2_end_store<T>(I, te.rank, Se.fkind, Se.xc0, Se.xc1, Se.xc3, parity);
+    }
+  }
   const bool sd = (S.kind == KIND_SD);  // second-ring pattern, never staged
   Red3 acc = red3(0.0, 0.0, 0.0);
   bool fused = false;  // a set-up launch that formed a two-iteration solve's first basis (Gram partials only)
