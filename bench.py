@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # was taken on: when their digest differs, `traffic` is reported as null.
 TRAFFIC = {
     # workload: (sha256 of the kernel sources, bytes per launch, algorithmic bytes per launch of the same run)
-    "pfc2d_512_fp64": ("e663e26416e2e0f959f18ffa656068b33b4cc42aef3ea9c1c82aa4978ea63a23", 42713160.0, 78820966.0),
-    "pfc3d_64_mixed": ("e663e26416e2e0f959f18ffa656068b33b4cc42aef3ea9c1c82aa4978ea63a23", 38860354.0, 71753338.0),
+    "pfc2d_512_fp64": ("9ff8f5f98174d6032f9200ac3dd8c209432041b5c5084cdcb35e2ea7fc0d6bd8", 46748597.0, 85211856.0),
+    "pfc3d_64_mixed": ("9ff8f5f98174d6032f9200ac3dd8c209432041b5c5084cdcb35e2ea7fc0d6bd8", 38870673.0, 71753338.0),
 }
 
 
